@@ -1,0 +1,47 @@
+"""Flux-limited diffusion: limiter (Sec. 2.2, Eq. 12) and D_E (Eq. 25).
+
+Face discretization (a reading: the paper does not print one).  For the face
+between cell P and Q = P + e_d (periodic):
+  E_f     = (E_P + E_Q) / 2
+  kappa_f = max((kappa_P + kappa_Q) / 2, 1e-6 / (a dx))      (proper 1/cm)
+  R_f     = |E_Q - E_P| / (a dx * max(E_f, tiny))            (Eq. 12's R_i)
+  D_f     = c (2 kappa_f + R_f) / (6 kappa_f^2 + 3 kappa_f R_f + R_f^2)
+and, in comoving form, (D_E)_P = -(1/(a^2 dx^2)) sum_d [D_{P+}(E_{P+d} - E_P)
+- D_{P-}(E_P - E_{P-d})].  kappa_T = kappa (no scattering, Sec. 2.2).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .model import C_LIGHT, E_FLOOR, KAPPA_FLOOR_CELLS
+
+
+def limiter(kappa, R):
+    """Diffusion coefficient D(kappa_T, R) of Eq. 12."""
+    return C_LIGHT * (2.0 * kappa + R) / (6.0 * kappa * kappa + 3.0 * kappa * R + R * R)
+
+
+def face_coefficients(E, kappa, a, model):
+    """D on the +x, +y, +z faces of every cell (list of 3 arrays)."""
+    out = []
+    for d in range(3):
+        if model.limiter_mode == 1:
+            out.append(np.full(E.shape, model.D0))
+            continue
+        Eq = np.roll(E, -1, axis=d)
+        kq = np.roll(kappa, -1, axis=d)
+        Ef = 0.5 * (E + Eq)
+        kf = np.maximum(0.5 * (kappa + kq), KAPPA_FLOOR_CELLS / (a * model.dx))
+        R = np.abs(Eq - E) / (a * model.dx * np.maximum(Ef, E_FLOOR))
+        out.append(limiter(kf, R))
+    return out
+
+
+def diffusion_operator(E, Dfaces, a, dx):
+    """D_E = -div(D grad E) in comoving form with the face coefficients Dfaces."""
+    acc = np.zeros_like(E)
+    for d in range(3):
+        flux_plus = Dfaces[d] * (np.roll(E, -1, axis=d) - E)   # on the + face
+        flux_minus = np.roll(flux_plus, 1, axis=d)             # the - face
+        acc += flux_plus - flux_minus
+    return -acc / (a * a * dx * dx)

@@ -1,0 +1,171 @@
+"""Geometric multigrid V-cycle and preconditioned CG for the Schur system.
+
+The paper solves the scalar Schur system with a multigrid-preconditioned
+conjugate gradient method (Sec. 3.2.1) but gives the multigrid only by
+reference to a library, so its definition here is a stated reading:
+
+Hierarchy (periodic, n_{l+1} = n_l / 2), built once per Schur matrix:
+  local_l   = diag_l - sum over the 6 faces of c_l
+  local_l+1 = mean of local_l over the 8 children
+  c^d_l+1   = (1/4) * mean of the 4 fine c^d on the coarse face (I, I + e_d)
+  diag_l+1  = local_l+1 + sum over the 6 faces of c_l+1
+Smoother: red-black Gauss-Seidel, colour (i + j + k) mod 2 (red = 0),
+  x_P <- (b_P + sum_faces c_f x_nbr) / diag_P.
+Transfers: cell-centred trilinear prolongation P (weights 3/4, 1/4 per axis)
+  and restriction R = P^T / 8.
+V(l): x = 0; nu1 x (red, black); r = b - A x; V(l+1) on R r; x += P e;
+  nu2 x (black, red).  Coarsest: k x (red, black) then k x (black, red).
+PCG: flexible (Polak-Ribiere) beta, x0 = 0, stop when ||r||_2 <= rtol ||b||_2.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .jacobian import apply_schur
+
+
+def colour_mask(shape, colour):
+    i, j, k = np.indices(shape)
+    return ((i + j + k) % 2) == colour
+
+
+def _pair_mean(a, axis):
+    """Mean of consecutive pairs (2I, 2I+1) along `axis`."""
+    ev = np.take(a, np.arange(0, a.shape[axis], 2), axis=axis)
+    od = np.take(a, np.arange(1, a.shape[axis], 2), axis=axis)
+    return 0.5 * (ev + od)
+
+
+def coarsen(op):
+    """Coarse operator (diag, cx, cy, cz) from a fine one (periodic)."""
+    diag, cs = op[0], op[1:]
+    csum = sum(c + np.roll(c, 1, axis=d) for d, c in enumerate(cs))
+    local_c = diag - csum
+    for ax in range(3):
+        local_c = _pair_mean(local_c, ax)            # mean over the 8 children
+    cc = []
+    for d, c in enumerate(cs):
+        # fine + faces lying on the coarse + face have fine index 2I+1 along d
+        on_face = np.take(c, np.arange(1, c.shape[d], 2), axis=d)
+        for ax in range(3):
+            if ax != d:
+                on_face = _pair_mean(on_face, ax)    # mean of the 4 fine faces
+        cc.append(0.25 * on_face)
+    csum_c = sum(c + np.roll(c, 1, axis=d) for d, c in enumerate(cc))
+    return (local_c + csum_c, cc[0], cc[1], cc[2])
+
+
+def hierarchy(op, levels):
+    ops = [tuple(op)]
+    for _ in range(levels - 1):
+        ops.append(coarsen(ops[-1]))
+    return ops
+
+
+def rbgs_colour(x, b, op, colour):
+    """One red-black Gauss-Seidel half sweep on cells of `colour` (in place)."""
+    diag, cx, cy, cz = op
+    s = b.copy()
+    for d, c in enumerate((cx, cy, cz)):
+        s = s + c * np.roll(x, -1, axis=d) + np.roll(c * x, 1, axis=d)
+    m = colour_mask(x.shape, colour)
+    x[m] = s[m] / diag[m]
+
+
+def _prolong_axis(c, axis):
+    n = c.shape[axis]
+    f = np.repeat(c, 2, axis=axis) * 0.75
+    left = np.repeat(np.roll(c, 1, axis=axis), 2, axis=axis)    # I-1 for even children
+    right = np.repeat(np.roll(c, -1, axis=axis), 2, axis=axis)  # I+1 for odd children
+    idx = np.arange(2 * n)
+    shape = [1, 1, 1]
+    shape[axis] = 2 * n
+    even = (idx % 2 == 0).reshape(shape)
+    return f + 0.25 * np.where(even, left, right)
+
+
+def prolong(xc):
+    """Cell-centred trilinear interpolation to the fine grid."""
+    f = xc
+    for ax in range(3):
+        f = _prolong_axis(f, ax)
+    return f
+
+
+def _restrict_axis(f, axis):
+    a0 = np.take(f, np.arange(0, f.shape[axis], 2), axis=axis)     # 2I
+    a1 = np.take(f, np.arange(1, f.shape[axis], 2), axis=axis)     # 2I+1
+    am = np.roll(a1, 1, axis=axis)                                  # 2I-1
+    ap = np.roll(a0, -1, axis=axis)                                 # 2I+2
+    return 0.375 * (a0 + a1) + 0.125 * (am + ap)
+
+
+def restrict(r):
+    """R = P^T / 8."""
+    c = r
+    for ax in range(3):
+        c = _restrict_axis(c, ax)
+    return c
+
+
+def vcycle(b, ops, model, level=0, dtype=np.float64):
+    """Apply the V-cycle preconditioner on level `level` to right side b."""
+    op = tuple(o.astype(dtype) for o in ops[level])
+    b = b.astype(dtype)
+    x = np.zeros_like(b)
+    if level == len(ops) - 1:
+        for _ in range(model.mg_coarse_sweeps):
+            rbgs_colour(x, b, op, 0)
+            rbgs_colour(x, b, op, 1)
+        for _ in range(model.mg_coarse_sweeps):
+            rbgs_colour(x, b, op, 1)
+            rbgs_colour(x, b, op, 0)
+        return x
+    for _ in range(model.mg_pre):
+        rbgs_colour(x, b, op, 0)
+        rbgs_colour(x, b, op, 1)
+    r = b - apply_schur(x, *op)
+    e = vcycle(restrict(r), ops, model, level + 1, dtype)
+    x = x + prolong(e)
+    for _ in range(model.mg_post):
+        rbgs_colour(x, b, op, 1)
+        rbgs_colour(x, b, op, 0)
+    return x
+
+
+def pcg(op, b, model, rtol=None, maxit=None, precond=True):
+    """Flexible PCG on S s = b; returns (s, iterations, ||r||/||b||)."""
+    rtol = model.pcg_rtol if rtol is None else rtol
+    maxit = model.pcg_maxit if maxit is None else maxit
+    ops = hierarchy(op, model.mg_levels) if precond else None
+    dt = np.float32 if model.mg_fp32 else np.float64
+
+    def V(r):
+        if not precond:
+            return r.copy()
+        return vcycle(r, ops, model, 0, dt).astype(np.float64)
+
+    x = np.zeros_like(b)
+    bn = np.sqrt(np.sum(b * b))
+    if bn == 0.0:
+        return x, 0, 0.0
+    r = b.copy()
+    z = V(r)
+    p = z.copy()
+    rho = np.sum(r * z)
+    rn = bn
+    for k in range(1, maxit + 1):
+        q = apply_schur(p, *op)
+        alpha = rho / np.sum(p * q)
+        x = x + alpha * p
+        r_old = r
+        r = r - alpha * q
+        rn = np.sqrt(np.sum(r * r))
+        if rn <= rtol * bn:
+            return x, k, rn / bn
+        z = V(r)
+        rho_new = np.sum(z * r)
+        beta = (rho_new - np.sum(z * r_old)) / rho
+        rho = rho_new
+        p = z + beta * p
+    return x, maxit, rn / bn

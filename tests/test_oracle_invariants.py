@@ -1,0 +1,174 @@
+"""Invariants and special cases that pin the oracle independently of itself.
+
+- photon number: with monochromatic hydrogen in a periodic static box, the
+  discrete theta-scheme conserves photons + ions exactly up to the emitted
+  and recombined photons, to within the final Newton residual (the analogue
+  of the paper's total-energy conservation check, Sec. 4.2, Table 1);
+- cube symmetry of a centred source in a uniform medium;
+- flux-limiter limits (Sec. 2.2): D -> c/(3 kappa) for R -> 0, the flux
+  R D -> c for kappa -> 0, and D decreasing in R;
+- zero-iteration exit when the initial guess already converges (Sec. 3.2.4);
+- the V-cycle is a symmetric operator and contracts;
+- restriction is P^T / 8 and both transfers preserve constants;
+- the temperature reading of Eq. 8 returns 1e4 K for the 1e4 K energy.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+import oracle
+from oracle import fld, mg, newton, residual
+from oracle.model import ALPHA_B_1E4, C_LIGHT, HNU_HI
+from oracle.physics import recombination_coefficients, temperature
+from tests.oracle_cases import hii_workload
+
+
+@pytest.mark.parametrize("theta,dt", [(1.0, 3e11), (0.51, 1e10)])
+def test_photon_number_conservation(theta, dt):
+    # theta = 0.51 rings (E changes sign) once dt c kappa >> 1, hence a short step
+    w = hii_workload(16, theta=theta, dt=dt, newton_tol=1e-9, pcg_rtol=1e-12)
+    m = oracle.model_from_workload(w)
+    s = synth.initial_state(w)
+    nH, eh = s["nH"], s["eh"]
+    h3 = w.dx ** 3
+    Un = s["U"]
+    # take a first step so that the second one starts from a non-uniform state
+    Un, st = newton.newton_step(Un, Un, nH, eh, s["src_cells"], s["src_Q"], w.dt,
+                                (1, 0, 1, 0), m)
+    assert st["status"] == 0
+    eh = eh + Un[0]
+    Un[0] = 0.0
+    U, st = newton.newton_step(Un, Un, nH, eh, s["src_cells"], s["src_Q"], w.dt,
+                               (1, 0, 1, 0), m)
+    assert st["status"] == 0
+
+    def recomb(V):
+        x = V[1]
+        T = temperature(eh + V[0], x, 0.0, 0.0, m)
+        aH = recombination_coefficients(T)[0]
+        return np.sum(aH * (nH * (1 - x)) ** 2) * h3
+
+    def count(V):
+        return (np.sum(V[2]) / HNU_HI + np.sum(nH * (1 - V[1]))) * h3
+
+    Q = float(np.sum(s["src_Q"]))
+    lhs = count(U) - count(Un)
+    rhs = w.dt * (Q - theta * recomb(U) - (1 - theta) * recomb(Un))
+    tl = residual.time_level(Un, nH, eh, s["src_cells"], s["src_Q"], w.dt, (1, 0, 1, 0), m)
+    f = residual.residual(U, tl, nH, eh, w.dt, 1.0, 0.0, m)
+    bound = np.sum(m.u_E * np.abs(f[2]) / HNU_HI + nH * np.abs(f[1])) * h3
+    # rounding of the fractions near 1 costs ~eps * n_H dx^3 atoms per cell
+    slack = 1e-15 * np.sum(nH) * h3 + 1e-13 * w.dt * Q
+    assert abs(lhs - rhs) <= bound + slack, (lhs, rhs, bound, slack)
+    assert slack <= 1e-8 * w.dt * Q
+    assert bound <= 1e-6 * w.dt * Q
+
+
+def test_cube_symmetry():
+    n = 16
+    w = hii_workload(n, newton_tol=1e-12, pcg_rtol=1e-14)
+    m = oracle.model_from_workload(w)
+    s = synth.initial_state(w)
+    U, st = newton.newton_step(s["U"], s["U"], s["nH"], s["eh"], s["src_cells"],
+                               s["src_Q"], w.dt, (1, 0, 1, 0), m, linear="direct")
+    assert st["status"] == 0
+    idx = (n - np.arange(n)) % n          # mirror about the source cell n/2
+    scale = np.max(np.abs(U), axis=(1, 2, 3))[:, None, None, None]
+    for perm in itertools.permutations(range(3)):
+        V = np.transpose(U, (0,) + tuple(p + 1 for p in perm))
+        assert np.max(np.abs(V - U) / scale) <= 1e-12
+    for ax in range(3):
+        V = np.take(U, idx, axis=ax + 1)
+        assert np.max(np.abs(V - U) / scale) <= 1e-12
+
+
+def test_limiter_limits():
+    k = np.array([1e-24, 1e-21, 1e-18])
+    assert np.allclose(fld.limiter(k, 0.0 * k), C_LIGHT / (3 * k), rtol=1e-15, atol=0)
+    R = np.array([1e-22, 1e-20, 1e-18])
+    assert np.allclose(R * fld.limiter(1e-40 * R, R), C_LIGHT, rtol=1e-12, atol=0)
+    Rs = np.logspace(-26, -16, 200)
+    D = fld.limiter(1e-21, Rs)
+    assert np.all(np.diff(D) < 0)
+
+
+def test_zero_iteration_exit():
+    w = hii_workload(16)
+    m = oracle.model_from_workload(w)
+    s = synth.initial_state(w)
+    U, st = newton.newton_step(s["U"], s["U"], s["nH"], s["eh"], s["src_cells"], s["src_Q"],
+                               w.dt, (1, 0, 1, 0), m)
+    assert st["status"] == 0 and st["newton_its"] > 0
+    U2, st2 = newton.newton_step(s["U"], U, s["nH"], s["eh"], s["src_cells"], s["src_Q"],
+                                 w.dt, (1, 0, 1, 0), m)
+    assert st2["newton_its"] == 0 and st2["status"] == 0
+    assert np.array_equal(U2, U)
+
+
+def const_op(n, c=2.0):
+    ones = np.ones((n, n, n))
+    return (ones * (1 + 6 * c), ones * c, ones * c, ones * c)
+
+
+def test_vcycle_symmetric_and_contracting():
+    n = 32
+    m = oracle.model_from_workload(synth.CFG_SMALL)
+    rng = np.random.default_rng(7)
+    # variable coefficients: symmetry must not rely on constant coefficients
+    op = const_op(n)
+    op = (op[0] + rng.uniform(0, 1, op[0].shape),) + tuple(c * rng.uniform(0.5, 1.5, c.shape)
+                                                            for c in op[1:])
+    csum = sum(c + np.roll(c, 1, axis=d) for d, c in enumerate(op[1:]))
+    op = (op[0] + csum - 6 * 2.0,) + op[1:]
+    ops = mg.hierarchy(op, 3)
+    r1, r2 = rng.standard_normal((2, n, n, n))
+    a = np.sum(mg.vcycle(r1, ops, m) * r2)
+    b = np.sum(r1 * mg.vcycle(r2, ops, m))
+    assert abs(a - b) <= 1e-13 * abs(a)
+    # contraction of the error-propagation operator I - V A on the model problem
+    cop = const_op(n)
+    cops = mg.hierarchy(cop, 3)
+    e = rng.standard_normal((n, n, n))
+    for _ in range(3):
+        e_new = e - mg.vcycle(mg.apply_schur(e, *cop), cops, m)
+        rho = np.linalg.norm(e_new) / np.linalg.norm(e)
+        e = e_new
+    assert rho <= 0.2
+
+
+def test_transfers():
+    n = 8
+    N, Nc = n ** 3, (n // 2) ** 3
+    P = np.zeros((N, Nc))
+    for j in range(Nc):
+        ec = np.zeros(Nc)
+        ec[j] = 1.0
+        P[:, j] = mg.prolong(ec.reshape((n // 2,) * 3)).ravel()
+    R = np.zeros((Nc, N))
+    for i in range(N):
+        ef = np.zeros(N)
+        ef[i] = 1.0
+        R[:, i] = mg.restrict(ef.reshape((n,) * 3)).ravel()
+    assert np.allclose(R, P.T / 8, rtol=0, atol=1e-15)
+    assert np.allclose(P @ np.ones(Nc), 1.0)
+    assert np.allclose(R @ np.ones(N), 1.0)
+    # trilinear weights: a fine cell receives 27/64 from its parent
+    assert np.isclose(P.max(), 27 / 64)
+
+
+def test_coarsening_of_constant_operator():
+    """Rediscretization at 2h: c -> c/4, local reaction part preserved."""
+    op = const_op(8, c=2.0)
+    op = (op[0] + 0.5,) + op[1:]
+    d, cx, cy, cz = mg.coarsen(op)
+    assert np.allclose(cx, 0.5) and np.allclose(cy, 0.5) and np.allclose(cz, 0.5)
+    assert np.allclose(d, 1.5 + 6 * 0.5)
+
+
+def test_temperature_reading():
+    m = oracle.model_from_workload(synth.CFG_SMALL)
+    T = temperature(synth.E_GAS_1E4K_X09999, 0.9999, 0.0, 0.0, m)
+    assert abs(T / 1e4 - 1) < 1e-12
+    assert recombination_coefficients(1e4)[0] == ALPHA_B_1E4
