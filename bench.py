@@ -1,0 +1,185 @@
+#!/usr/bin/env python
+"""Benchmark: implicit Newton-step cell-updates/s at 256^3 on one MI355X.
+
+A step is one full implicit time step of the 256^3 periodic hydrogen problem
+(centred 5e48 photons/s source in a 13.2 kpc box, dt = 1e11 s, theta = 1):
+time-level set-up, Newton iterations with Schur elimination, MG-PCG and line
+search until the RMS residual is below 1e-6, then the energy fold.  Inputs
+stay resident in HBM; W warm-up steps run first, then K steps are timed, each
+from the state the previous one produced.
+
+Modes: plain (FP64 V-cycle) and mixed (FP32 V-cycle inside FP64 Newton/CG).
+The JSON line reports the headline mode in `value` and every mode in
+`modes`; `roofline` covers the kernel class with the largest share of the
+timed region, timed with HIP events on the library's stream; `cpu_baseline`
+times the CPU FP64 oracle on a bounded sample of the same problem.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Newton-step cell-updates/s at 256^3, mixed+learned vs plain FP64, Newton tol 1e-6"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per cell and launch of each kernel class (H-only, FP64
+# fields = 8 B; FP32 V-cycle fields = 4 B).  Neighbour values read through the
+# cache are not counted: a stencil needs each field once.
+#   residual : read U(3) g(3) n_H e_h D(3), write f(3)                  = 14 x 8
+#   schur    : read U(3) f(3) n_H e_h D(3), write f~_M(2) W(2) S(4) b   = 20 x 8
+#   trial    : read U(3) f~_M(2) W(2) s_E, write U_t(3)                 = 11 x 8
+#   spmv     : read diag cx cy cz p, write q                            = 6 x 8
+#   rbgs     : one colour: all 3 couplings, diag and b of the colour,
+#              the other colour's x, write the colour's x              = (3 + 1) w + 1 w = 5 w
+#              first half-sweep from x = 0: diag, b of the colour, write x = 1.5 w
+BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0}
+
+
+def rbgs_bytes(counts_per_vcycle, w):
+    first, regular = counts_per_vcycle
+    return first * 1.5 * w + regular * 5.0 * w
+
+
+def run_mode(mode, steps, warmup, n=256):
+    import torch
+    import synth
+    from paper_0901_1110_amd.driver import Simulation
+
+    w = synth.CFG_256.replace(n=n, mg_fp32=1 if mode == "mixed" else 0)
+    sim = Simulation(w)
+    for _ in range(warmup):
+        st = sim.step()
+        if st["status"] != 0:
+            raise RuntimeError("warm-up step failed: %s" % st)
+        sim.advance()
+    stats = []
+    torch.cuda.synchronize()
+    sim.grid.rt_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(sim.grid.stream)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = sim.step()
+        if st["status"] != 0:
+            raise RuntimeError("timed step failed: %s" % st)
+        stats.append(st)
+        sim.advance()
+    ev1.record(sim.grid.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = sim.grid.rt_timing(False)
+    gpu_ms = ev0.elapsed_time(ev1)
+    N = n ** 3
+    newton = sum(s["newton_its"] for s in stats)
+    cg = sum(s["cg_its_total"] for s in stats)
+    vc = sum(s["vcycles"] for s in stats)
+    res = dict(mode=mode, cells=N, steps=steps, wall_s=wall, event_ms=gpu_ms,
+               value=N * steps / wall, ms_per_step=1e3 * wall / steps,
+               newton_its=newton, cg_its=cg, vcycles=vc,
+               cell_newton_its_per_s=N * newton / wall, kernels=kt)
+    # roofline of the dominant kernel class
+    wbytes = 4.0 if mode == "mixed" else 8.0
+    p = sim.grid.params
+    per_vc = (1, 2 * p.mg_pre - 1 + 2 * p.mg_post) if p.mg_pre > 0 else (0, 2 * p.mg_post)
+    dom = max(kt, key=lambda k: kt[k][1])
+    cnt, ms = kt[dom]
+    if dom == "rbgs_fine":
+        nvc = cnt / float(sum(per_vc))
+        total_bytes = nvc * rbgs_bytes(per_vc, wbytes) * N
+    elif dom in BYTES_PER_CELL:
+        total_bytes = cnt * BYTES_PER_CELL[dom] * N
+    else:
+        total_bytes = None
+    if total_bytes is not None and ms > 0:
+        achieved = total_bytes / (ms * 1e-3) / 1e9
+        res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                           "launches": cnt, "avg_launch_us": round(1e3 * ms / cnt, 2),
+                           "share_of_timed": round(ms / gpu_ms, 3)}
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(n=64, budget_s=30.0):
+    """The oracle on a bounded sample: the first implicit step of the same
+    256^3-spacing problem on an n^3 periodic box around the source."""
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    import oracle
+    from oracle import newton
+
+    w = synth.CFG_256.replace(n=n, mg_levels=4)
+    m = oracle.model_from_workload(w)
+    s = synth.initial_state(w)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        U, st = newton.newton_step(s["U"], s["U"], s["nH"], s["eh"], s["src_cells"], s["src_Q"],
+                                   w.dt, w.cosmology(0), m)
+        dt = time.perf_counter() - t0
+    return {"value": n ** 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "first implicit step (status %d, %d Newton its) of the 256^3-spacing "
+                      "centred-source problem on a %d^3 periodic box, NumPy FP64, 1 thread, "
+                      "%.1f s" % (st["status"], st["newton_its"], n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--modes", default="plain,mixed")
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    modes = [m for m in args.modes.split(",") if m]
+    results = {}
+    for mode in modes:
+        print("# mode %s: %d warm-up + %d timed steps at %d^3" % (mode, args.warmup, args.steps, args.n),
+              file=sys.stderr, flush=True)
+        results[mode] = run_mode(mode, args.steps, args.warmup, args.n)
+        print("# %s: %.3e cell-updates/s, %.1f ms/step" % (mode, results[mode]["value"],
+                                                          results[mode]["ms_per_step"]),
+              file=sys.stderr, flush=True)
+    head = "mixed" if "mixed" in results else modes[0]
+    H = results[head]
+    line = {
+        "metric": METRIC, "value": H["value"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": H["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32" if head == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "hii_256: %d^3 periodic hydrogen, centred 5e48 photons/s source, "
+                               "13.2 kpc box, dt=1e11 s, theta=1, Newton tol 1e-6, PCG rtol 1e-8, "
+                               "5-level V-cycle RB-GS 2+2" % args.n,
+                   "mode": head, "grid": args.n, "parallelism": "single GPU"},
+        "roofline": H.get("roofline"),
+        "modes": {k: {kk: v[kk] for kk in ("value", "ms_per_step", "newton_its", "cg_its",
+                                           "vcycles", "cell_newton_its_per_s")}
+                  for k, v in results.items()},
+    }
+    if "plain" in results and head != "plain":
+        line["speedup_vs_plain"] = H["value"] / results["plain"]["value"]
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+    with open(os.path.join(ROOT, "gpurun_out", "bench_kernels.json") if os.path.isdir(
+            os.path.join(ROOT, "gpurun_out")) else os.devnull, "w") as fh:
+        json.dump({k: v["kernels"] for k, v in results.items()}, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

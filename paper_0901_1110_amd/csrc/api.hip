@@ -1,0 +1,755 @@
+// Host solver control and C ABI of the implicit Newton step (see rt.h).
+//
+// Only control scalars cross the host/device boundary: the residual norm and
+// bound-violation count of each line-search trial and ||r||^2 of each CG
+// iteration (8-16 byte copies).  CG's alpha and beta stay on the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/rt.h"
+#include "internal.hpp"
+
+using namespace rtk;
+
+namespace {
+
+constexpr double LAMBDA_MIN = 1.0 / 1024.0;   // line-search floor 2^-10
+constexpr double ARMIJO = 1.0e-4;
+constexpr size_t ALIGN = 256;
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  bool dry;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + ALIGN - 1) / ALIGN * ALIGN;
+    T* p = dry ? nullptr : reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Workspace {
+  double *D, *g, *f, *ft, *Ut;
+  double *ftM, *W;
+  double *diag, *cx, *cy, *cz, *b;
+  double *x, *r, *z, *p, *q;
+  double *parts, *sc;
+  long long* src_cells;
+  double* src_Q;
+  std::vector<Level<double>> L64;
+  std::vector<Level<float>> L32;
+  float* r32;   // FP32 copy of the CG residual fed to the V-cycle
+};
+
+}  // namespace
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;           // events, reused across collections
+  std::vector<int> cls;                   // class of each recorded launch
+  size_t used = 0;
+};
+
+struct rt_grid {
+  Timer tm;
+  rt_params prm;
+  DevParams P;
+  hipStream_t st;
+  Workspace w;
+  const double* nH = nullptr;
+  const double* eh = nullptr;
+  int nsrc = 0;
+  bool have_tl = false;     // time-level face coefficients present
+  bool mg_stale = true;     // coarse operators need rebuilding
+  bool have_op = false;     // a Schur matrix is present
+  std::string err;
+};
+
+namespace {
+
+int fail(rt_grid* g, int code, const char* fmt, ...) {
+  if (g) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g->err = buf;
+  }
+  return code;
+}
+
+// record a start event (returns the slot) / stop event around a launch
+inline long tstart(rt_grid* g, int cls) {
+  Timer& t = g->tm;
+  if (!t.on) return -1;
+  if (t.used + 2 > t.pool.size()) {
+    const size_t grow = t.pool.size() < 1024 ? 1024 : t.pool.size();
+    for (size_t i = 0; i < grow; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { t.on = false; return -1; }
+      t.pool.push_back(e);
+    }
+  }
+  const long slot = (long)t.used;
+  hipEventRecord(t.pool[t.used], g->st);
+  t.used += 2;
+  t.cls.push_back(cls);
+  return slot;
+}
+inline void tstop(rt_grid* g, long slot) {
+  if (slot >= 0) hipEventRecord(g->tm.pool[slot + 1], g->st);
+}
+#define TK(g, cls, expr)               \
+  do {                                 \
+    const long slot_ = tstart(g, cls); \
+    expr;                              \
+    tstop(g, slot_);                   \
+  } while (0)
+
+#define HIPCHK(g, call)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail((g), RT_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));              \
+  } while (0)
+
+#define RTCHK(call)              \
+  do {                           \
+    int s_ = (call);             \
+    if (s_ != RT_OK) return s_;  \
+  } while (0)
+
+bool is_pow2_div(int n, int levels) {
+  const int f = 1 << (levels - 1);
+  return n % f == 0 && (n / f) >= 4 && ((n / f) % 2 == 0);
+}
+
+int validate(const rt_params* p, std::string* why) {
+  auto bad = [&](const char* m) { *why = m; return RT_EINVAL; };
+  if (!p) return bad("null params");
+  if (p->nspecies != 1 && p->nspecies != 3) return bad("nspecies must be 1 or 3");
+  if (p->mg_levels < 1 || p->mg_levels > 12) return bad("mg_levels out of range");
+  if (!is_pow2_div(p->nx, p->mg_levels) || !is_pow2_div(p->ny, p->mg_levels) ||
+      !is_pow2_div(p->nz, p->mg_levels))
+    return bad("grid sizes must be divisible by 2^(mg_levels-1) with an even coarsest size >= 4");
+  const double N = (double)p->nx * p->ny * p->nz;
+  if (N * (p->nspecies + 2) >= 2147483647.0) return bad("grid too large for 32-bit indexing");
+  if (!(p->dx > 0) || !(p->theta > 0 && p->theta <= 1)) return bad("dx or theta invalid");
+  if (!(p->u_e > 0) || !(p->u_E > 0)) return bad("unit scales must be positive");
+  if (p->newton_maxit < 0 || p->newton_maxit > RT_MAX_NEWTON) return bad("newton_maxit out of range");
+  if (p->pcg_maxit < 0 || p->mg_pre < 0 || p->mg_post < 0 || p->mg_coarse_sweeps < 1)
+    return bad("negative solver counts");
+  if (p->max_sources < 0) return bad("max_sources < 0");
+  if (p->limiter_mode != 0 && p->limiter_mode != 1) return bad("limiter_mode must be 0 or 1");
+  return RT_OK;
+}
+
+size_t carve(const rt_params* p, char* base, Workspace* w) {
+  Carver c{base, 0, base == nullptr};
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  const int nv = p->nspecies + 2, nb = p->nspecies + 1;
+  w->D = c.take<double>(3 * N);
+  w->g = c.take<double>(nv * N);
+  w->f = c.take<double>(nv * N);
+  w->ft = c.take<double>(nv * N);
+  w->Ut = c.take<double>(nv * N);
+  w->ftM = c.take<double>(nb * N);
+  w->W = c.take<double>(nb * N);
+  w->diag = c.take<double>(N);
+  w->cx = c.take<double>(N);
+  w->cy = c.take<double>(N);
+  w->cz = c.take<double>(N);
+  w->b = c.take<double>(N);
+  w->x = c.take<double>(N);
+  w->r = c.take<double>(N);
+  w->z = c.take<double>(N);
+  w->p = c.take<double>(N);
+  w->q = c.take<double>(N);
+  w->parts = c.take<double>((size_t)MAX_PARTS * NCOMP_MAX);
+  w->sc = c.take<double>(32);
+  w->src_cells = c.take<long long>(p->max_sources > 0 ? p->max_sources : 1);
+  w->src_Q = c.take<double>(p->max_sources > 0 ? p->max_sources : 1);
+  w->L64.clear();
+  w->L32.clear();
+  w->r32 = nullptr;
+  int nx = p->nx, ny = p->ny, nz = p->nz;
+  for (int l = 0; l < p->mg_levels; ++l) {
+    const size_t n = (size_t)nx * ny * nz;
+    if (!p->mg_fp32) {
+      Level<double> L{nx, ny, nz};
+      if (l == 0) {
+        L.diag = w->diag; L.cx = w->cx; L.cy = w->cy; L.cz = w->cz;
+        L.x = nullptr; L.b = nullptr;          // bound per application
+        L.r = c.take<double>(n);
+      } else {
+        L.diag = c.take<double>(n); L.cx = c.take<double>(n); L.cy = c.take<double>(n);
+        L.cz = c.take<double>(n); L.x = c.take<double>(n); L.b = c.take<double>(n);
+        L.r = c.take<double>(n);
+      }
+      w->L64.push_back(L);
+    } else {
+      Level<float> L{nx, ny, nz};
+      L.diag = c.take<float>(n); L.cx = c.take<float>(n); L.cy = c.take<float>(n);
+      L.cz = c.take<float>(n); L.x = c.take<float>(n); L.b = c.take<float>(n);
+      L.r = c.take<float>(n);
+      w->L32.push_back(L);
+    }
+    nx /= 2; ny /= 2; nz /= 2;
+  }
+  return c.off + ALIGN;
+}
+
+Step step_new(double dt, const rt_cosmo* c) { return Step{dt, c->a_new, c->H_new}; }
+
+// ---------------------------------------------------------------------------
+// multigrid
+template <class T>
+void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l) {
+  const rt_params& p = g->prm;
+  hipStream_t st = g->st;
+  Level<T>& L = Ls[l];
+  const bool coarsest = (l + 1 == (int)Ls.size());
+  const int kc = l == 0 ? RT_K_RBGS_FINE : RT_K_RBGS_COARSE;
+  const int pre = coarsest ? p.mg_coarse_sweeps : p.mg_pre;
+  if (pre > 0) {
+    TK(g, kc, launch_rbgs_first<T>(L, st));     // red from x = 0
+    TK(g, kc, launch_rbgs<T>(L, 1, st));        // black
+    for (int s = 1; s < pre; ++s) {
+      TK(g, kc, launch_rbgs<T>(L, 0, st));
+      TK(g, kc, launch_rbgs<T>(L, 1, st));
+    }
+  } else {
+    TK(g, RT_K_OTHER, launch_fill<T>((long)L.nx * L.ny * L.nz, L.x, T(0), st));
+  }
+  if (!coarsest) {
+    TK(g, RT_K_MG_TRANSFER, launch_mg_residual<T>(L, st));
+    TK(g, RT_K_MG_TRANSFER, launch_restrict<T>(L, Ls[l + 1], st));
+    vcycle<T>(g, Ls, l + 1);
+    TK(g, RT_K_MG_TRANSFER, launch_prolong_add<T>(Ls[l + 1], L, st));
+  }
+  const int post = coarsest ? p.mg_coarse_sweeps : p.mg_post;
+  for (int s = 0; s < post; ++s) {
+    TK(g, kc, launch_rbgs<T>(L, 1, st));
+    TK(g, kc, launch_rbgs<T>(L, 0, st));
+  }
+}
+
+int build_hierarchy(rt_grid* g) {
+  if (!g->mg_stale) return RT_OK;
+  Workspace& w = g->w;
+  const long N = g->P.N;
+  if (!g->prm.mg_fp32) {
+    for (size_t l = 1; l < w.L64.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<double>(w.L64[l - 1], w.L64[l], g->st));
+  } else {
+    Level<float>& L0 = w.L32[0];
+    TK(g, RT_K_MG_SETUP, launch_cvt_d2f(N, w.diag, L0.diag, g->st));
+    TK(g, RT_K_MG_SETUP, launch_cvt_d2f(N, w.cx, L0.cx, g->st));
+    TK(g, RT_K_MG_SETUP, launch_cvt_d2f(N, w.cy, L0.cy, g->st));
+    TK(g, RT_K_MG_SETUP, launch_cvt_d2f(N, w.cz, L0.cz, g->st));
+    for (size_t l = 1; l < w.L32.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<float>(w.L32[l - 1], w.L32[l], g->st));
+  }
+  g->mg_stale = false;
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+// z = V r on the current hierarchy
+void apply_vcycle(rt_grid* g, const double* r, double* z) {
+  Workspace& w = g->w;
+  const long N = g->P.N;
+  if (!g->prm.mg_fp32) {
+    w.L64[0].b = const_cast<double*>(r);
+    w.L64[0].x = z;
+    vcycle<double>(g, w.L64, 0);
+  } else {
+    Level<float>& L0 = w.L32[0];
+    TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
+    vcycle<float>(g, w.L32, 0);
+    TK(g, RT_K_MG_TRANSFER, launch_cvt_f2d(N, L0.x, z, g->st));
+  }
+}
+
+int read_scalars(rt_grid* g, const double* d, double* h, int n) {
+  HIPCHK(g, hipMemcpyAsync(h, d, n * sizeof(double), hipMemcpyDeviceToHost, g->st));
+  HIPCHK(g, hipStreamSynchronize(g->st));
+  return RT_OK;
+}
+
+// reduce `ncomp` partials of the last reduction kernel into sc[slot...]
+void finish_reduce(rt_grid* g, int n_items_blocks, int ncomp, int slot) {
+  TK(g, RT_K_REDUCE, launch_final_reduce(g->w.parts, n_items_blocks, ncomp, g->w.sc + slot, g->st));
+}
+
+// PCG on the workspace Schur matrix: solve S x = b (x in w.x)
+int pcg(rt_grid* g, const double* b, double* x, double rtol, int maxit, int* iters,
+        double* relres, int* vcycles) {
+  Workspace& w = g->w;
+  const long N = g->P.N;
+  const int nparts = reduce_blocks(N);
+  RTCHK(build_hierarchy(g));
+  double h[2];
+  TK(g, RT_K_CG_VECTOR, launch_dot1(N, b, b, w.parts, g->st));
+  finish_reduce(g, nparts, 1, S_BB);
+  RTCHK(read_scalars(g, w.sc + S_BB, h, 1));
+  const double bn = std::sqrt(h[0]);
+  TK(g, RT_K_CG_VECTOR, launch_fill<double>(N, x, 0.0, g->st));
+  *iters = 0;
+  *relres = 0.0;
+  if (!(bn > 0.0)) {
+    if (!std::isfinite(bn)) return fail(g, RT_ENONFINITE, "non-finite Schur right side");
+    HIPCHK(g, hipGetLastError());
+    return RT_OK;
+  }
+  HIPCHK(g, hipMemcpyAsync(w.r, b, N * sizeof(double), hipMemcpyDeviceToDevice, g->st));
+  apply_vcycle(g, w.r, w.z);
+  ++*vcycles;
+  TK(g, RT_K_CG_VECTOR, launch_dot1(N, w.r, w.z, w.parts, g->st));
+  finish_reduce(g, nparts, 1, S_RHO);
+  HIPCHK(g, hipMemcpyAsync(w.p, w.z, N * sizeof(double), hipMemcpyDeviceToDevice, g->st));
+  double rn = bn;
+  int k = 0;
+  for (k = 1; k <= maxit; ++k) {
+    TK(g, RT_K_SPMV, launch_spmv_dot(g->P.nx, g->P.ny, g->P.nz, w.diag, w.cx, w.cy, w.cz, w.p, w.q, w.parts, g->st));
+    finish_reduce(g, nparts, 1, S_PQ);
+    TK(g, RT_K_REDUCE, launch_cg_alpha(w.sc, g->st));
+    TK(g, RT_K_CG_VECTOR, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st));
+    finish_reduce(g, nparts, 1, S_RR);
+    RTCHK(read_scalars(g, w.sc + S_RR, h, 1));
+    rn = std::sqrt(h[0]);
+    if (!std::isfinite(rn)) return fail(g, RT_ENONFINITE, "non-finite CG residual");
+    if (rn <= rtol * bn) break;
+    if (k == maxit) break;
+    apply_vcycle(g, w.r, w.z);
+    ++*vcycles;
+    TK(g, RT_K_CG_VECTOR, launch_dot2(N, w.z, w.r, w.q, w.parts, g->st));
+    finish_reduce(g, nparts, 2, S_ZR);
+    TK(g, RT_K_REDUCE, launch_cg_beta(w.sc, g->st));
+    TK(g, RT_K_CG_VECTOR, launch_update_p(N, w.p, w.z, w.sc, g->st));
+  }
+  *iters = k > maxit ? maxit : k;
+  *relres = rn / bn;
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+int time_level(rt_grid* g, const double* Un, double dt, const rt_cosmo* c, double* gn) {
+  const DevParams& P = g->P;
+  TK(g, RT_K_TIMELEVEL, launch_faces(P, Un, g->nH, c->a_old, g->w.D, g->st));
+  if (P.theta != 1.0) {
+    TK(g, RT_K_TIMELEVEL, launch_explicit(P, Un, g->nH, g->eh, g->w.D, Step{dt, c->a_old, c->H_old}, gn, g->st));
+  } else {
+    HIPCHK(g, hipMemcpyAsync(gn, Un, (size_t)P.nv * P.N * sizeof(double),
+                             hipMemcpyDeviceToDevice, g->st));
+  }
+  const double scale = dt * P.hnu / (P.dx * P.dx * P.dx);
+  TK(g, RT_K_TIMELEVEL, launch_sources(g->w.src_cells, g->w.src_Q, g->nsrc, scale, gn + (size_t)(P.nv - 1) * P.N, g->st));
+  g->have_tl = true;
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+// residual + norm; returns rms in *fn and violation count in *viol (sync)
+int residual_norm(rt_grid* g, const double* U, const double* gn, Step s, double* f, double* fn,
+                  double* viol) {
+  const DevParams& P = g->P;
+  TK(g, RT_K_RESIDUAL, launch_residual(P, U, gn, g->nH, g->eh, g->w.D, s, f, g->w.parts, g->st));
+  finish_reduce(g, reduce_blocks(P.N), 2, S_FN);
+  double h[2];
+  RTCHK(read_scalars(g, g->w.sc + S_FN, h, 2));
+  *fn = std::sqrt(h[0] / ((double)P.N * P.nv));
+  *viol = h[1];
+  return RT_OK;
+}
+
+int check_ready(rt_grid* g, bool need_tl) {
+  if (!g) return RT_EINVAL;
+  if (!g->nH || !g->eh) return fail(g, RT_EINVAL, "rt_set_medium has not been called");
+  if (need_tl && !g->have_tl) return fail(g, RT_EINVAL, "rt_time_level has not been called");
+  return RT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int rt_workspace_bytes(const rt_params* p, uint64_t* bytes) {
+  std::string why;
+  if (!bytes || validate(p, &why) != RT_OK) return RT_EINVAL;
+  Workspace w;
+  *bytes = carve(p, nullptr, &w);
+  return RT_OK;
+}
+
+int rt_create_grid(const rt_params* p, void* d_ws, uint64_t ws_bytes, void* hip_stream,
+                   rt_grid** out) {
+  if (!out) return RT_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (validate(p, &why) != RT_OK) return RT_EINVAL;
+  Workspace tmp;
+  const size_t need = carve(p, nullptr, &tmp);
+  if (!d_ws || ws_bytes < need) return RT_EINVAL;
+  char* base = reinterpret_cast<char*>(d_ws);
+  base += (ALIGN - reinterpret_cast<uintptr_t>(base) % ALIGN) % ALIGN;
+  rt_grid* g = new rt_grid();
+  g->prm = *p;
+  g->st = reinterpret_cast<hipStream_t>(hip_stream);
+  carve(p, base, &g->w);
+  DevParams& P = g->P;
+  P.nx = p->nx; P.ny = p->ny; P.nz = p->nz;
+  P.ns = p->nspecies; P.nv = p->nspecies + 2; P.nb = p->nspecies + 1;
+  P.N = p->nx * p->ny * p->nz;
+  P.iso = p->isothermal; P.lim_mode = p->limiter_mode;
+  P.dx = p->dx; P.theta = p->theta; P.u_e = p->u_e; P.u_E = p->u_E;
+  P.m = p->grey ? 1.0 : 0.0; P.y = p->y_he; P.T_iso = p->T_iso; P.D0 = p->D0;
+  for (int s = 0; s < 3; ++s) {
+    P.Kg[s] = p->K_gamma[s]; P.Kk[s] = p->K_kappa[s]; P.Kh[s] = p->K_heat[s];
+  }
+  if (p->nspecies == 1) {
+    for (int s = 1; s < 3; ++s) P.Kg[s] = P.Kk[s] = P.Kh[s] = 0.0;
+  }
+  P.hnu = p->hnu_mean;
+  P.alpha0[0] = 2.59e-13;                            // case-B HII at 1e4 K
+  P.alpha0[1] = 2.72e-13;                            // HeII (placeholder datum)
+  P.alpha0[2] = 2.0 * 2.59e-13 * std::pow(4.0, 0.7); // HeIII, hydrogenic Z = 2
+  *out = g;
+  return RT_OK;
+}
+
+int rt_destroy_grid(rt_grid* g) {
+  if (g) {
+    for (hipEvent_t e : g->tm.pool) hipEventDestroy(e);
+  }
+  delete g;
+  return RT_OK;
+}
+
+const char* rt_last_error(const rt_grid* g) { return g ? g->err.c_str() : "null grid"; }
+
+int rt_set_medium(rt_grid* g, const double* d_nH, const double* d_eh) {
+  if (!g) return RT_EINVAL;
+  if (!d_nH || !d_eh) return fail(g, RT_EINVAL, "null medium pointer");
+  g->nH = d_nH;
+  g->eh = d_eh;
+  g->have_tl = false;
+  return RT_OK;
+}
+
+int rt_set_sources(rt_grid* g, int32_t n, const int64_t* h_cells, const double* h_Q) {
+  if (!g) return RT_EINVAL;
+  if (n < 0 || n > g->prm.max_sources) return fail(g, RT_EINVAL, "source count %d out of range", n);
+  if (n > 0 && (!h_cells || !h_Q)) return fail(g, RT_EINVAL, "null source arrays");
+  for (int i = 0; i < n; ++i) {
+    if (h_cells[i] < 0 || h_cells[i] >= g->P.N)
+      return fail(g, RT_EINVAL, "source cell %lld out of range", (long long)h_cells[i]);
+    if (!std::isfinite(h_Q[i]) || h_Q[i] < 0) return fail(g, RT_EINVAL, "invalid source rate");
+  }
+  if (n > 0) {
+    HIPCHK(g, hipMemcpyAsync(g->w.src_cells, h_cells, n * sizeof(long long),
+                             hipMemcpyHostToDevice, g->st));
+    HIPCHK(g, hipMemcpyAsync(g->w.src_Q, h_Q, n * sizeof(double), hipMemcpyHostToDevice, g->st));
+    HIPCHK(g, hipStreamSynchronize(g->st));
+  }
+  g->nsrc = n;
+  g->have_tl = false;
+  return RT_OK;
+}
+
+int rt_time_level(rt_grid* g, const double* d_Un, double dt, const rt_cosmo* c, double* d_gn) {
+  RTCHK(check_ready(g, false));
+  if (!d_Un || !d_gn || !c) return fail(g, RT_EINVAL, "null argument");
+  return time_level(g, d_Un, dt, c, d_gn);
+}
+
+int rt_eval_residual(rt_grid* g, const double* d_U, const double* d_gn, double dt,
+                     const rt_cosmo* c, double* d_f, double* h_rms) {
+  RTCHK(check_ready(g, true));
+  if (!d_U || !d_gn || !d_f || !c) return fail(g, RT_EINVAL, "null argument");
+  if (h_rms) {
+    double viol;
+    RTCHK(residual_norm(g, d_U, d_gn, step_new(dt, c), d_f, h_rms, &viol));
+  } else {
+    launch_residual(g->P, d_U, d_gn, g->nH, g->eh, g->w.D, step_new(dt, c), d_f, g->w.parts, g->st);
+  }
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+int rt_local_jacobian(rt_grid* g, const double* d_U, double dt, const rt_cosmo* c, double* d_M,
+                      double* d_Ucol, double* d_Lrow, double* d_dloc) {
+  RTCHK(check_ready(g, false));
+  if (!d_U || !d_M || !d_Ucol || !d_Lrow || !d_dloc || !c)
+    return fail(g, RT_EINVAL, "null argument");
+  launch_local_jac(g->P, d_U, g->nH, g->eh, step_new(dt, c), d_M, d_Ucol, d_Lrow, d_dloc, g->st);
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+int rt_schur_form(rt_grid* g, const double* d_U, const double* d_f, double dt, const rt_cosmo* c,
+                  double* d_b) {
+  RTCHK(check_ready(g, true));
+  if (!d_U || !d_f || !d_b || !c) return fail(g, RT_EINVAL, "null argument");
+  Workspace& w = g->w;
+  launch_schur(g->P, d_U, d_f, g->nH, g->eh, w.D, step_new(dt, c), w.ftM, w.W, w.diag, w.cx, w.cy,
+               w.cz, d_b, g->st);
+  g->mg_stale = true;
+  g->have_op = true;
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+int rt_schur_get(rt_grid* g, double* d_ftM, double* d_W, double* d_diag, double* d_cx,
+                 double* d_cy, double* d_cz) {
+  if (!g) return RT_EINVAL;
+  if (!g->have_op) return fail(g, RT_EINVAL, "no Schur matrix yet");
+  const size_t N = g->P.N, nb = g->P.nb;
+  Workspace& w = g->w;
+  auto cp = [&](double* dst, const double* src, size_t n) -> int {
+    if (dst) HIPCHK(g, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, g->st));
+    return RT_OK;
+  };
+  RTCHK(cp(d_ftM, w.ftM, nb * N));
+  RTCHK(cp(d_W, w.W, nb * N));
+  RTCHK(cp(d_diag, w.diag, N));
+  RTCHK(cp(d_cx, w.cx, N));
+  RTCHK(cp(d_cy, w.cy, N));
+  RTCHK(cp(d_cz, w.cz, N));
+  return RT_OK;
+}
+
+int rt_set_operator(rt_grid* g, const double* d_diag, const double* d_cx, const double* d_cy,
+                    const double* d_cz) {
+  if (!g) return RT_EINVAL;
+  if (!d_diag || !d_cx || !d_cy || !d_cz) return fail(g, RT_EINVAL, "null operator array");
+  const size_t N = g->P.N;
+  Workspace& w = g->w;
+  HIPCHK(g, hipMemcpyAsync(w.diag, d_diag, N * 8, hipMemcpyDeviceToDevice, g->st));
+  HIPCHK(g, hipMemcpyAsync(w.cx, d_cx, N * 8, hipMemcpyDeviceToDevice, g->st));
+  HIPCHK(g, hipMemcpyAsync(w.cy, d_cy, N * 8, hipMemcpyDeviceToDevice, g->st));
+  HIPCHK(g, hipMemcpyAsync(w.cz, d_cz, N * 8, hipMemcpyDeviceToDevice, g->st));
+  g->mg_stale = true;
+  g->have_op = true;
+  return RT_OK;
+}
+
+int rt_mg_vcycle(rt_grid* g, const double* d_r, double* d_z) {
+  if (!g) return RT_EINVAL;
+  if (!g->have_op) return fail(g, RT_EINVAL, "no Schur matrix yet");
+  if (!d_r || !d_z) return fail(g, RT_EINVAL, "null argument");
+  RTCHK(build_hierarchy(g));
+  apply_vcycle(g, d_r, d_z);
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+int rt_mg_pcg_solve(rt_grid* g, const double* d_b, double* d_sE, double rtol, int32_t maxit,
+                    int32_t* h_iters, double* h_relres) {
+  if (!g) return RT_EINVAL;
+  if (!g->have_op) return fail(g, RT_EINVAL, "no Schur matrix yet");
+  if (!d_b || !d_sE || maxit < 0 || !(rtol >= 0)) return fail(g, RT_EINVAL, "bad argument");
+  int its = 0, vc = 0;
+  double rr = 0;
+  RTCHK(pcg(g, d_b, d_sE, rtol, maxit, &its, &rr, &vc));
+  if (h_iters) *h_iters = its;
+  if (h_relres) *h_relres = rr;
+  return RT_OK;
+}
+
+int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_Ualt, double dt,
+                   const rt_cosmo* c, rt_newton_stats* h_stats) {
+  RTCHK(check_ready(g, false));
+  if (!d_Un || !d_U || !c || !(dt > 0)) return fail(g, RT_EINVAL, "bad argument");
+  rt_newton_stats st;
+  std::memset(&st, 0, sizeof st);
+  st.fnorm_alt = -1.0;
+  Workspace& w = g->w;
+  const DevParams& P = g->P;
+  const size_t bytesU = (size_t)P.nv * P.N * sizeof(double);
+  const Step s = step_new(dt, c);
+  auto finish = [&](int status) {
+    st.status = status;
+    if (h_stats) *h_stats = st;
+    return status;
+  };
+  RTCHK(time_level(g, d_Un, dt, c, w.g));
+  double fn, viol;
+  RTCHK(residual_norm(g, d_U, w.g, s, w.f, &fn, &viol));
+  st.fnorm_guess = fn;
+  if (d_Ualt) {
+    double fa, va;
+    RTCHK(residual_norm(g, d_Ualt, w.g, s, w.ft, &fa, &va));
+    st.fnorm_alt = fa;
+    if (std::isfinite(fa) && va == 0.0 && fa < fn) {
+      HIPCHK(g, hipMemcpyAsync(d_U, d_Ualt, bytesU, hipMemcpyDeviceToDevice, g->st));
+      std::swap(w.f, w.ft);
+      fn = fa;
+      st.used_alt_guess = 1;
+    }
+  }
+  st.fnorm[0] = fn;
+  if (!std::isfinite(fn)) return finish(fail(g, RT_ENONFINITE, "non-finite initial residual"));
+  double* cur = d_U;       // current iterate: the caller's buffer or w.Ut
+  double* spare = w.Ut;
+  int k = 0;
+  int status = RT_OK;
+  while (fn >= g->prm.newton_tol && k < g->prm.newton_maxit) {
+    TK(g, RT_K_SCHUR, launch_schur(P, cur, w.f, g->nH, g->eh, w.D, s, w.ftM, w.W, w.diag, w.cx,
+                                   w.cy, w.cz, w.b, g->st));
+    g->mg_stale = true;
+    g->have_op = true;
+    int its = 0, vc = 0;
+    double rr = 0;
+    status = pcg(g, w.b, w.x, g->prm.pcg_rtol, g->prm.pcg_maxit, &its, &rr, &vc);
+    if (status != RT_OK) break;
+    st.cg_its[k] = its;
+    st.cg_its_total += its;
+    st.vcycles += vc;
+    double lam = 1.0, ftn = 0.0;
+    bool ok = false;
+    while (status == RT_OK) {
+      TK(g, RT_K_TRIAL, launch_trial(P, cur, w.ftM, w.W, w.x, lam, spare, g->st));
+      status = residual_norm(g, spare, w.g, s, w.ft, &ftn, &viol);
+      if (status != RT_OK) break;
+      ++st.ls_trials;
+      if (viol == 0.0 && ftn <= (1.0 - ARMIJO * lam) * fn) {
+        ok = true;
+        break;
+      }
+      lam *= 0.5;
+      if (lam < LAMBDA_MIN) break;
+    }
+    if (status != RT_OK) break;
+    if (!ok) {
+      status = fail(g, RT_ELINESEARCH, "line search failed at Newton iteration %d", k);
+      break;
+    }
+    std::swap(cur, spare);
+    std::swap(w.f, w.ft);
+    fn = ftn;
+    st.lambda[k] = lam;
+    st.fnorm[k + 1] = fn;
+    ++k;
+  }
+  st.newton_its = k;
+  st.fnorm_final = fn;
+  // the last accepted iterate ends in the caller's buffer
+  if (cur != d_U) HIPCHK(g, hipMemcpyAsync(d_U, cur, bytesU, hipMemcpyDeviceToDevice, g->st));
+  HIPCHK(g, hipStreamSynchronize(g->st));
+  if (status == RT_OK) {
+    if (!std::isfinite(fn)) status = fail(g, RT_ENONFINITE, "non-finite residual");
+    else if (fn >= g->prm.newton_tol) status = fail(g, RT_ENOCONV, "no convergence in %d its", k);
+  }
+  return finish(status);
+}
+
+int rt_timing(rt_grid* g, int32_t enable, rt_kernel_timing* out) {
+  if (!g) return RT_EINVAL;
+  Timer& t = g->tm;
+  if (enable) {
+    t.on = true;
+    t.used = 0;
+    t.cls.clear();
+    return RT_OK;
+  }
+  t.on = false;
+  HIPCHK(g, hipStreamSynchronize(g->st));
+  if (out) {
+    std::memset(out, 0, sizeof *out);
+    for (size_t i = 0; i < t.cls.size(); ++i) {
+      float ms = 0.f;
+      HIPCHK(g, hipEventElapsedTime(&ms, t.pool[2 * i], t.pool[2 * i + 1]));
+      out->count[t.cls[i]] += 1;
+      out->total_ms[t.cls[i]] += ms;
+    }
+  }
+  t.used = 0;
+  t.cls.clear();
+  return RT_OK;
+}
+
+int rt_fold_energy(rt_grid* g, double* d_U, double* d_eh) {
+  if (!g) return RT_EINVAL;
+  if (!d_U || !d_eh) return fail(g, RT_EINVAL, "null argument");
+  launch_fold_energy(g->P.N, d_U, d_eh, g->st);
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// spectrum constants by composite Gauss-Legendre quadrature on log(nu)
+int rt_spectrum_constants(int32_t grey, double T_B, double* Kg, double* Kk, double* Kh,
+                          double* hnu) {
+  if (!Kg || !Kk || !Kh || !hnu) return RT_EINVAL;
+  const double h = 6.62607015e-27, kB = 1.380649e-16, eV = 1.602176634e-12;
+  const double thr[3] = {13.6 * eV, 24.6 * eV, 54.4 * eV};
+  const double sig0[3] = {6.30e-18, 7.42e-18, 1.575e-18};
+  if (!grey) {
+    Kg[0] = sig0[0] / thr[0]; Kk[0] = sig0[0]; Kh[0] = 0.0;
+    for (int s = 1; s < 3; ++s) Kg[s] = Kk[s] = Kh[s] = 0.0;
+    *hnu = thr[0];
+    return RT_OK;
+  }
+  if (!(T_B > 0)) return RT_EINVAL;
+  // 20-point Gauss-Legendre nodes/weights on [-1, 1]
+  static const double xg[10] = {0.0765265211334973, 0.2277858511416451, 0.3737060887154195,
+                                0.5108670019508271, 0.6360536807265150, 0.7463319064601508,
+                                0.8391169718222188, 0.9122344282513259, 0.9639719272779138,
+                                0.9931285991850949};
+  static const double wg[10] = {0.1527533871307258, 0.1491729864726037, 0.1420961093183820,
+                                0.1316886384491766, 0.1181945319615184, 0.1019301198172404,
+                                0.0832767415767048, 0.0626720483341091, 0.0406014298003869,
+                                0.0176140071391521};
+  const double kT = kB * T_B;
+  auto chi = [&](double e) { return e * e * e / std::expm1(e / kT); };   // e = h nu
+  auto sigma = [&](int s, double e) { return e < thr[s] ? 0.0 : sig0[s] * std::pow(e / thr[s], -3.0); };
+  // integrate f(e) de over [lo, hi] on a log grid, panels split at thresholds
+  auto integ = [&](auto f, double lo, double hi) {
+    double edges[8];
+    int ne = 0;
+    edges[ne++] = lo;
+    for (int s = 1; s < 3; ++s)
+      if (thr[s] > lo && thr[s] < hi) edges[ne++] = thr[s];
+    edges[ne++] = hi;
+    double total = 0.0;
+    for (int e = 0; e + 1 < ne; ++e) {
+      const double a = std::log(edges[e]), b = std::log(edges[e + 1]);
+      const int panels = 400;
+      const double hpan = (b - a) / panels;
+      for (int pnl = 0; pnl < panels; ++pnl) {
+        const double mid = a + (pnl + 0.5) * hpan, half = 0.5 * hpan;
+        for (int q = 0; q < 10; ++q) {
+          for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const double t = mid + sgn * half * xg[q];
+            const double en = std::exp(t);
+            total += wg[q] * half * f(en) * en;   // de = e dt
+          }
+        }
+      }
+    }
+    return total;
+  };
+  const double hi = 80.0 * kT + 100.0 * thr[0];
+  const double norm = integ([&](double e) { return chi(e); }, thr[0], hi);
+  for (int s = 0; s < 3; ++s) {
+    Kg[s] = integ([&](double e) { return sigma(s, e) * chi(e) / e; }, thr[s], hi) / norm;
+    Kk[s] = integ([&](double e) { return sigma(s, e) * chi(e); }, thr[s], hi) / norm;
+    Kh[s] = integ([&](double e) { return sigma(s, e) * (1.0 - thr[s] / e) * chi(e); }, thr[s], hi) / norm;
+  }
+  const double photons = integ([&](double e) { return chi(e) / e; }, thr[0], hi);
+  *hnu = norm / photons;
+  (void)h;
+  return RT_OK;
+}
+
+}  // extern "C"

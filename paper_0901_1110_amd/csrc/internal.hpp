@@ -1,0 +1,83 @@
+// Launchers of the gfx950 kernels (defined in kernels.hip) used by the host
+// solver control (api.hip).  All launches are asynchronous on `st`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "physics.hpp"
+
+namespace rtk {
+
+constexpr int BLOCK = 256;          // threads per block (4 wave64)
+constexpr int MAX_PARTS = 2048;     // partial sums per reduction
+constexpr int NCOMP_MAX = 4;        // components per reduction
+
+// Number of blocks a reduction kernel over n items uses (fixed per n, so the
+// summation tree, and therefore the result, is deterministic).
+inline int reduce_blocks(long n) {
+  long b = (n + BLOCK - 1) / BLOCK;
+  return (int)(b < MAX_PARTS ? (b < 1 ? 1 : b) : MAX_PARTS);
+}
+
+// Indices of the device scalar slots used by CG.
+enum Scalar { S_RHO = 0, S_PQ, S_ALPHA, S_RR, S_ZR, S_ZQ, S_BETA, S_BB, S_FN, S_VIOL, S_COUNT };
+
+struct Step {     // per-call time-step data
+  double dt, a, H;
+};
+
+// ---- residual / time level ----
+void launch_faces(const DevParams& P, const double* Un, const double* nH, double a,
+                  double* D, hipStream_t st);
+void launch_explicit(const DevParams& P, const double* Un, const double* nH, const double* eh,
+                     const double* D, Step s, double* g, hipStream_t st);
+void launch_sources(const long long* cells, const double* Q, int n, double scale, double* gE,
+                    hipStream_t st);
+void launch_residual(const DevParams& P, const double* U, const double* g, const double* nH,
+                     const double* eh, const double* D, Step s, double* f, double* parts,
+                     hipStream_t st);
+void launch_trial(const DevParams& P, const double* U, const double* ftM, const double* W,
+                  const double* sE, double lambda, double* Ut, hipStream_t st);
+void launch_local_jac(const DevParams& P, const double* U, const double* nH, const double* eh,
+                      Step s, double* M, double* Ucol, double* Lrow, double* dloc,
+                      hipStream_t st);
+void launch_schur(const DevParams& P, const double* U, const double* f, const double* nH,
+                  const double* eh, const double* D, Step s, double* ftM, double* W,
+                  double* diag, double* cx, double* cy, double* cz, double* b, hipStream_t st);
+
+// ---- reductions / scalars ----
+void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out,
+                         hipStream_t st);
+void launch_cg_alpha(double* sc, hipStream_t st);
+void launch_cg_beta(double* sc, hipStream_t st);
+
+// ---- CG vector kernels (FP64) ----
+void launch_spmv_dot(int nx, int ny, int nz, const double* diag, const double* cx,
+                     const double* cy, const double* cz, const double* p, double* q,
+                     double* parts, hipStream_t st);
+void launch_update_xr(long n, double* x, double* r, const double* p, const double* q,
+                      const double* sc, double* parts, hipStream_t st);
+void launch_dot2(long n, const double* z, const double* r, const double* q, double* parts,
+                 hipStream_t st);
+void launch_dot1(long n, const double* a, const double* b, double* parts, hipStream_t st);
+void launch_update_p(long n, double* p, const double* z, const double* sc, hipStream_t st);
+
+// ---- multigrid (T = double or float) ----
+template <class T>
+struct Level {
+  int nx, ny, nz;
+  T *diag, *cx, *cy, *cz;   // operator
+  T *x, *b, *r;             // solution, right side, residual scratch
+};
+template <class T> void launch_fill(long n, T* x, T v, hipStream_t st);
+template <class T> void launch_rbgs(const Level<T>& L, int colour, hipStream_t st);
+template <class T> void launch_rbgs_first(const Level<T>& L, hipStream_t st);
+template <class T> void launch_mg_residual(const Level<T>& L, hipStream_t st);
+template <class T> void launch_restrict(const Level<T>& F, const Level<T>& C, hipStream_t st);
+template <class T> void launch_prolong_add(const Level<T>& C, const Level<T>& F, hipStream_t st);
+template <class T> void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st);
+void launch_fold_energy(int N, double* U, double* eh, hipStream_t st);
+void launch_cvt_d2f(long n, const double* a, float* b, hipStream_t st);
+void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st);
+
+}  // namespace rtk

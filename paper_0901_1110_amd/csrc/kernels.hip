@@ -1,0 +1,790 @@
+// gfx950 kernels of the implicit radiation / ionization / energy Newton step.
+//
+// Layout: every field is structure-of-arrays FP64 (FP32 for the mixed-
+// precision V-cycle), cell (i,j,k) at (i*ny + j)*nz + k, periodic.  One
+// thread owns one cell; consecutive lanes of a 64-wide wavefront own
+// consecutive z cells, so every field access of a wavefront is a coalesced
+// 512-byte (FP64) line run and the +-z, +-y neighbours of a block are served
+// from the L2 lines the block itself brings in.  All kernels are HBM-bound
+// (a few hundred flops per cell against 50-150 bytes); reductions are
+// deterministic: fixed grid, wave64 butterfly, fixed-order block and final
+// combine.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace rtk {
+
+// ---------------------------------------------------------------------------
+// indexing helpers
+struct Nb {
+  int xm, xp, ym, yp, zm, zp;
+};
+
+__device__ inline Nb neighbours(int idx, int nx, int ny, int nz) {
+  const int k = idx % nz;
+  const int t = idx / nz;
+  const int j = t % ny;
+  const int i = t / ny;
+  const int sx = ny * nz;
+  Nb n;
+  n.xp = idx + (i + 1 < nx ? sx : -(nx - 1) * sx);
+  n.xm = idx + (i > 0 ? -sx : (nx - 1) * sx);
+  n.yp = idx + (j + 1 < ny ? nz : -(ny - 1) * nz);
+  n.ym = idx + (j > 0 ? -nz : (ny - 1) * nz);
+  n.zp = idx + (k + 1 < nz ? 1 : -(nz - 1));
+  n.zm = idx + (k > 0 ? -1 : (nz - 1));
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic block reduction of NC values (result valid in thread 0)
+template <int NC>
+__device__ inline void block_reduce(double (&v)[NC], double* out) {
+  __shared__ double sh[BLOCK / 64][NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[c] = x;
+  }
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sh[w][c] = v[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < BLOCK / 64; ++i) s += sh[i][c];
+      out[blockIdx.x * NCOMP_MAX + c] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// time level: face coefficients at U^n (lagged flux limiter)
+template <int NS>
+__global__ __launch_bounds__(BLOCK) void k_faces(DevParams P, const double* __restrict__ Un,
+                                                  const double* __restrict__ nH, double a,
+                                                  double* __restrict__ D) {
+  const int N = P.N;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= N) return;
+  const Nb nb = neighbours(idx, P.nx, P.ny, P.nz);
+  const double* E = Un + (NS + 1) * N;
+  double x[NS];
+  const int nbr[3] = {nb.xp, nb.yp, nb.zp};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) x[s] = Un[(1 + s) * N + idx];
+  const double kP = opacity<NS>(x, nH[idx], a, P);
+  const double EP = E[idx];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int q = nbr[d];
+    double xq[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xq[s] = Un[(1 + s) * N + q];
+    const double kQ = opacity<NS>(xq, nH[q], a, P);
+    D[d * N + idx] = face_D(EP, E[q], kP, kQ, a, P);
+  }
+}
+
+// sum over the faces of D_f (E_nbr - E_P) with the +/- ordering of the text
+__device__ inline double diffusion_sum(const double* __restrict__ E, const double* __restrict__ D,
+                                       int N, int idx, const Nb& nb, double EP) {
+  double acc = 0.0;
+  acc += D[idx] * (E[nb.xp] - EP) - D[nb.xm] * (EP - E[nb.xm]);
+  acc += D[N + idx] * (E[nb.yp] - EP) - D[N + nb.ym] * (EP - E[nb.ym]);
+  acc += D[2 * N + idx] * (E[nb.zp] - EP) - D[2 * N + nb.zm] * (EP - E[nb.zm]);
+  return acc;
+}
+
+// g = U^n + dt (theta - 1) [L; D_E + L_E](U^n)   (theta != 1)
+template <int NS>
+__global__ __launch_bounds__(BLOCK) void k_explicit(DevParams P, const double* __restrict__ Un,
+                                                     const double* __restrict__ nH,
+                                                     const double* __restrict__ eh,
+                                                     const double* __restrict__ D, Step s,
+                                                     double* __restrict__ g) {
+  constexpr int NV = NS + 2;
+  const int N = P.N;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= N) return;
+  double u[NV], L[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Un[v * N + idx];
+  local_ops<NS, double>(u, nH[idx], eh[idx], s.a, s.H, P, L);
+  const Nb nb = neighbours(idx, P.nx, P.ny, P.nz);
+  const double dif = diffusion_sum(Un + (NS + 1) * N, D, N, idx, nb, u[NS + 1]);
+  L[NS + 1] += -dif / (s.a * s.a * P.dx * P.dx);
+  const double w = s.dt * (P.theta - 1.0);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) g[v * N + idx] = u[v] + w * L[v];
+}
+
+__global__ void k_sources(const long long* __restrict__ cells, const double* __restrict__ Q, int n,
+                          double scale, double* __restrict__ gE) {
+  // one thread, fixed order: several sources may share a cell
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int i = 0; i < n; ++i) gE[cells[i]] += scale * Q[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// residual f~ = (U + dt theta [L; D_E + L_E](U) - g) / u  and sum f~^2,
+// count of cells with e_h + e_c <= 0
+template <int NS>
+__global__ __launch_bounds__(BLOCK) void k_residual(DevParams P, const double* __restrict__ U,
+                                                     const double* __restrict__ g,
+                                                     const double* __restrict__ nH,
+                                                     const double* __restrict__ eh,
+                                                     const double* __restrict__ D, Step s,
+                                                     double* __restrict__ f,
+                                                     double* __restrict__ parts) {
+  constexpr int NV = NS + 2;
+  const int N = P.N;
+  const double dtt = s.dt * P.theta;
+  const double inv_a2dx2 = 1.0 / (s.a * s.a * P.dx * P.dx);
+  double acc[2] = {0.0, 0.0};
+  for (int idx = blockIdx.x * BLOCK + threadIdx.x; idx < N; idx += gridDim.x * BLOCK) {
+    double u[NV], L[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[v * N + idx];
+    const double ehv = eh[idx];
+    local_ops<NS, double>(u, nH[idx], ehv, s.a, s.H, P, L);
+    const Nb nb = neighbours(idx, P.nx, P.ny, P.nz);
+    const double dif = diffusion_sum(U + (NS + 1) * N, D, N, idx, nb, u[NS + 1]);
+    L[NS + 1] += -dif * inv_a2dx2;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double sc = v == 0 ? P.u_e : (v == NS + 1 ? P.u_E : 1.0);
+      const double fv = (u[v] + dtt * L[v] - g[v * N + idx]) / sc;
+      f[v * N + idx] = fv;
+      acc[0] += fv * fv;
+    }
+    if (!(ehv + u[0] > 0.0)) acc[1] += 1.0;
+  }
+  block_reduce<2>(acc, parts);
+}
+
+// trial point U_t = project(U + lambda u * [s_M; s_E]), s_M = -f~_M - W s_E
+template <int NS>
+__global__ __launch_bounds__(BLOCK) void k_trial(DevParams P, const double* __restrict__ U,
+                                                  const double* __restrict__ ftM,
+                                                  const double* __restrict__ W,
+                                                  const double* __restrict__ sE, double lam,
+                                                  double* __restrict__ Ut) {
+  constexpr int NB = NS + 1;
+  const int N = P.N;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= N) return;
+  const double se = sE[idx];
+  double v[NS + 2];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    const double sc = r == 0 ? P.u_e : 1.0;
+    const double step = (-ftM[r * N + idx] - W[r * N + idx] * se) * sc;
+    v[r] = U[r * N + idx] + lam * step;
+  }
+  v[NB] = U[NB * N + idx] + lam * (se * P.u_E);
+  // projection onto the physical bounds
+#pragma unroll
+  for (int r = 1; r <= NS; ++r) v[r] = fmin(fmax(v[r], 0.0), 1.0);
+  if constexpr (NS == 3) {
+    const double tot = v[2] + v[3];
+    if (tot > 1.0) {
+      v[2] = v[2] / tot;
+      v[3] = v[3] / tot;
+    }
+  }
+  v[NB] = fmax(v[NB], 0.0);
+#pragma unroll
+  for (int r = 0; r < NS + 2; ++r) Ut[r * N + idx] = v[r];
+}
+
+// ---------------------------------------------------------------------------
+// local Jacobian blocks by forward-mode differentiation of local_ops
+template <int NS>
+__device__ inline void local_blocks(const DevParams& P, const double* u, double nHv, double ehv,
+                                    Step s, double (&M)[NS + 1][NS + 1], double (&Uc)[NS + 1],
+                                    double (&Lr)[NS + 1], double& dloc) {
+  constexpr int NV = NS + 2;
+  constexpr int NB = NS + 1;
+  double us[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) us[v] = v == 0 ? P.u_e : (v == NV - 1 ? P.u_E : 1.0);
+  Dual<NV> ud[NV], Ld[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    ud[v] = Dual<NV>(u[v]);
+    ud[v].d[v] = us[v];          // derivative with respect to the scaled unknown
+  }
+  local_ops<NS, Dual<NV>>(ud, nHv, ehv, s.a, s.H, P, Ld);
+  const double dtt = s.dt * P.theta;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) M[i][j] = (i == j ? 1.0 : 0.0) + dtt * Ld[i].d[j] / us[i];
+    Uc[i] = dtt * Ld[i].d[NB] / us[i];
+    Lr[i] = dtt * Ld[NB].d[i] / us[NB];
+  }
+  dloc = 1.0 + dtt * Ld[NB].d[NB] / us[NB];
+}
+
+template <int NS>
+__global__ __launch_bounds__(BLOCK) void k_local_jac(DevParams P, const double* __restrict__ U,
+                                                      const double* __restrict__ nH,
+                                                      const double* __restrict__ eh, Step s,
+                                                      double* __restrict__ Mo,
+                                                      double* __restrict__ Uo,
+                                                      double* __restrict__ Lo,
+                                                      double* __restrict__ Do) {
+  constexpr int NB = NS + 1;
+  const int N = P.N;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= N) return;
+  double u[NS + 2];
+#pragma unroll
+  for (int v = 0; v < NS + 2; ++v) u[v] = U[v * N + idx];
+  double M[NB][NB], Uc[NB], Lr[NB], dloc;
+  local_blocks<NS>(P, u, nH[idx], eh[idx], s, M, Uc, Lr, dloc);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) Mo[(i * NB + j) * N + idx] = M[i][j];
+    Uo[i * N + idx] = Uc[i];
+    Lo[i * N + idx] = Lr[i];
+  }
+  Do[idx] = dloc;
+}
+
+// Gaussian elimination with partial pivoting on one small dense system with
+// two right-hand sides, fully in registers.  Pivot: largest |a_ik|, first on
+// ties (a row is moved up only if strictly larger).
+template <int NB>
+__device__ inline void gepp2(double (&A)[NB][NB], double (&B)[NB][2]) {
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+#pragma unroll
+    for (int i = k + 1; i < NB; ++i) {
+      if (fabs(A[i][k]) > fabs(A[k][k])) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const double t = A[k][j]; A[k][j] = A[i][j]; A[i][j] = t;
+        }
+        const double t0 = B[k][0]; B[k][0] = B[i][0]; B[i][0] = t0;
+        const double t1 = B[k][1]; B[k][1] = B[i][1]; B[i][1] = t1;
+      }
+    }
+    const double inv = 1.0 / A[k][k];
+#pragma unroll
+    for (int i = k + 1; i < NB; ++i) {
+      const double l = A[i][k] * inv;
+#pragma unroll
+      for (int j = k + 1; j < NB; ++j) A[i][j] -= l * A[k][j];
+      B[i][0] -= l * B[k][0];
+      B[i][1] -= l * B[k][1];
+    }
+  }
+#pragma unroll
+  for (int i = NB - 1; i >= 0; --i) {
+    double s0 = B[i][0], s1 = B[i][1];
+#pragma unroll
+    for (int j = i + 1; j < NB; ++j) {
+      s0 -= A[i][j] * B[j][0];
+      s1 -= A[i][j] * B[j][1];
+    }
+    B[i][0] = s0 / A[i][i];
+    B[i][1] = s1 / A[i][i];
+  }
+}
+
+// Schur steps (i)-(ii): f~_M, W = M^-1 [f_M, U]; S = D - L W; b = L f~_M - f_E
+template <int NS>
+__global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __restrict__ U,
+                                                  const double* __restrict__ f,
+                                                  const double* __restrict__ nH,
+                                                  const double* __restrict__ eh,
+                                                  const double* __restrict__ D, Step s,
+                                                  double* __restrict__ ftM,
+                                                  double* __restrict__ Wo,
+                                                  double* __restrict__ diag,
+                                                  double* __restrict__ cx,
+                                                  double* __restrict__ cy,
+                                                  double* __restrict__ cz,
+                                                  double* __restrict__ b) {
+  constexpr int NB = NS + 1;
+  const int N = P.N;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= N) return;
+  double u[NS + 2];
+#pragma unroll
+  for (int v = 0; v < NS + 2; ++v) u[v] = U[v * N + idx];
+  double M[NB][NB], Uc[NB], Lr[NB], dloc;
+  local_blocks<NS>(P, u, nH[idx], eh[idx], s, M, Uc, Lr, dloc);
+  double B[NB][2];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    B[i][0] = f[i * N + idx];
+    B[i][1] = Uc[i];
+  }
+  gepp2<NB>(M, B);
+  const Nb nb = neighbours(idx, P.nx, P.ny, P.nz);
+  const double cf = s.dt * P.theta / (s.a * s.a * P.dx * P.dx);
+  const double cxp = cf * D[idx], cxm = cf * D[nb.xm];
+  const double cyp = cf * D[N + idx], cym = cf * D[N + nb.ym];
+  const double czp = cf * D[2 * N + idx], czm = cf * D[2 * N + nb.zm];
+  const double csum = ((cxp + cxm) + (cyp + cym)) + (czp + czm);
+  double lw = 0.0, lf = 0.0;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    lw += Lr[i] * B[i][1];
+    lf += Lr[i] * B[i][0];
+    ftM[i * N + idx] = B[i][0];
+    Wo[i * N + idx] = B[i][1];
+  }
+  diag[idx] = (dloc + csum) - lw;
+  cx[idx] = cxp;
+  cy[idx] = cyp;
+  cz[idx] = czp;
+  b[idx] = lf - f[NB * N + idx];
+}
+
+// ---------------------------------------------------------------------------
+// reductions and CG scalars
+__global__ __launch_bounds__(1024) void k_final_reduce(const double* __restrict__ parts,
+                                                       int nparts, int ncomp,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[1024 / 64][NCOMP_MAX];
+  for (int c = 0; c < ncomp; ++c) {
+    double x = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 1024) x += parts[i * NCOMP_MAX + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][c] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < ncomp) {
+    double s = 0.0;
+    for (int w = 0; w < 1024 / 64; ++w) s += sh[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+__global__ void k_cg_alpha(double* sc) {
+  if (threadIdx.x == 0) sc[S_ALPHA] = sc[S_RHO] / sc[S_PQ];
+}
+
+// flexible (Polak-Ribiere) beta = (z.r - z.r_old) / rho with r - r_old = -alpha q
+__global__ void k_cg_beta(double* sc) {
+  if (threadIdx.x == 0) {
+    sc[S_BETA] = (-sc[S_ALPHA] * sc[S_ZQ]) / sc[S_RHO];
+    sc[S_RHO] = sc[S_ZR];
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_spmv_dot(int nx, int ny, int nz,
+                                                     const double* __restrict__ diag,
+                                                     const double* __restrict__ cx,
+                                                     const double* __restrict__ cy,
+                                                     const double* __restrict__ cz,
+                                                     const double* __restrict__ p,
+                                                     double* __restrict__ q,
+                                                     double* __restrict__ parts) {
+  const int N = nx * ny * nz;
+  double acc[1] = {0.0};
+  for (int idx = blockIdx.x * BLOCK + threadIdx.x; idx < N; idx += gridDim.x * BLOCK) {
+    const Nb nb = neighbours(idx, nx, ny, nz);
+    const double pv = p[idx];
+    double y = diag[idx] * pv;
+    y = y - cx[idx] * p[nb.xp] - cx[nb.xm] * p[nb.xm];
+    y = y - cy[idx] * p[nb.yp] - cy[nb.ym] * p[nb.ym];
+    y = y - cz[idx] * p[nb.zp] - cz[nb.zm] * p[nb.zm];
+    q[idx] = y;
+    acc[0] += pv * y;
+  }
+  block_reduce<1>(acc, parts);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_update_xr(long n, double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ q,
+                                                      const double* __restrict__ sc,
+                                                      double* __restrict__ parts) {
+  const double alpha = sc[S_ALPHA];
+  double acc[1] = {0.0};
+  for (long i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK) {
+    x[i] = x[i] + alpha * p[i];
+    const double rv = r[i] - alpha * q[i];
+    r[i] = rv;
+    acc[0] += rv * rv;
+  }
+  block_reduce<1>(acc, parts);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_dot2(long n, const double* __restrict__ z,
+                                                 const double* __restrict__ r,
+                                                 const double* __restrict__ q,
+                                                 double* __restrict__ parts) {
+  double acc[2] = {0.0, 0.0};
+  for (long i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK) {
+    const double zv = z[i];
+    acc[0] += zv * r[i];
+    acc[1] += zv * q[i];
+  }
+  block_reduce<2>(acc, parts);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_dot1(long n, const double* __restrict__ a,
+                                                 const double* __restrict__ b,
+                                                 double* __restrict__ parts) {
+  double acc[1] = {0.0};
+  for (long i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK)
+    acc[0] += a[i] * b[i];
+  block_reduce<1>(acc, parts);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_update_p(long n, double* __restrict__ p,
+                                                     const double* __restrict__ z,
+                                                     const double* __restrict__ sc) {
+  const double beta = sc[S_BETA];
+  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+// ---------------------------------------------------------------------------
+// multigrid
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_fill(long n, T* __restrict__ x, T v) {
+  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// one colour of a red-black Gauss-Seidel sweep; thread t owns the t-th cell of
+// that colour in z-fastest order (nz even)
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_rbgs(Level<T> L, int colour) {
+  const int half = L.nz >> 1;
+  const int n2 = L.nx * L.ny * half;
+  const int t = blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= n2) return;
+  const int row = t / half;
+  const int j = row % L.ny;
+  const int i = row / L.ny;
+  const int k = 2 * (t - row * half) + ((i + j + colour) & 1);
+  const int idx = row * L.nz + k;
+  const Nb nb = neighbours(idx, L.nx, L.ny, L.nz);
+  const T* x = L.x;
+  T s = L.b[idx];
+  s = s + L.cx[idx] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
+  s = s + L.cy[idx] * x[nb.yp] + L.cy[nb.ym] * x[nb.ym];
+  s = s + L.cz[idx] * x[nb.zp] + L.cz[nb.zm] * x[nb.zm];
+  L.x[idx] = s / L.diag[idx];
+}
+
+// first red half-sweep from x = 0: red cells b/diag, black cells 0
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_rbgs_first(Level<T> L) {
+  const int N = L.nx * L.ny * L.nz;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= N) return;
+  const int k = idx % L.nz;
+  const int t = idx / L.nz;
+  const int j = t % L.ny;
+  const int i = t / L.ny;
+  L.x[idx] = ((i + j + k) & 1) == 0 ? L.b[idx] / L.diag[idx] : T(0);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L) {
+  const int N = L.nx * L.ny * L.nz;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= N) return;
+  const Nb nb = neighbours(idx, L.nx, L.ny, L.nz);
+  const T* x = L.x;
+  T y = L.diag[idx] * x[idx];
+  y = y - L.cx[idx] * x[nb.xp] - L.cx[nb.xm] * x[nb.xm];
+  y = y - L.cy[idx] * x[nb.yp] - L.cy[nb.ym] * x[nb.ym];
+  y = y - L.cz[idx] * x[nb.zp] - L.cz[nb.zm] * x[nb.zm];
+  L.r[idx] = L.b[idx] - y;
+}
+
+__device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// b_coarse = R r_fine with R = P^T / 8: weights (1,3,3,1)/8 per axis over
+// fine cells 2I-1 .. 2I+2
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C) {
+  const int Nc = C.nx * C.ny * C.nz;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= Nc) return;
+  const int K = idx % C.nz;
+  const int t = idx / C.nz;
+  const int J = t % C.ny;
+  const int I = t / C.ny;
+  const T w[4] = {T(0.125), T(0.375), T(0.375), T(0.125)};
+  T acc = T(0);
+  for (int a = 0; a < 4; ++a) {
+    const int i = wrap(2 * I - 1 + a, F.nx);
+    T acc_j = T(0);
+    for (int b = 0; b < 4; ++b) {
+      const int j = wrap(2 * J - 1 + b, F.ny);
+      const T* rr = F.r + (i * F.ny + j) * F.nz;
+      T acc_k = T(0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc_k += w[c] * rr[wrap(2 * K - 1 + c, F.nz)];
+      acc_j += w[b] * acc_k;
+    }
+    acc += w[a] * acc_j;
+  }
+  C.b[idx] = acc;
+}
+
+// x_fine += P x_coarse: cell-centred trilinear, weights 3/4 (parent) and 1/4
+// (the parent's neighbour on the child's side) per axis
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_prolong_add(Level<T> C, Level<T> F) {
+  const int Nf = F.nx * F.ny * F.nz;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= Nf) return;
+  const int k = idx % F.nz;
+  const int t = idx / F.nz;
+  const int j = t % F.ny;
+  const int i = t / F.ny;
+  const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+  const int I1 = wrap(I0 + ((i & 1) ? 1 : -1), C.nx);
+  const int J1 = wrap(J0 + ((j & 1) ? 1 : -1), C.ny);
+  const int K1 = wrap(K0 + ((k & 1) ? 1 : -1), C.nz);
+  const T* x = C.x;
+  auto at = [&](int a, int b, int c) { return x[(a * C.ny + b) * C.nz + c]; };
+  const T w0 = T(0.75), w1 = T(0.25);
+  const T zI0 = w0 * (w0 * at(I0, J0, K0) + w1 * at(I0, J0, K1)) +
+                w1 * (w0 * at(I0, J1, K0) + w1 * at(I0, J1, K1));
+  const T zI1 = w0 * (w0 * at(I1, J0, K0) + w1 * at(I1, J0, K1)) +
+                w1 * (w0 * at(I1, J1, K0) + w1 * at(I1, J1, K1));
+  F.x[idx] = F.x[idx] + (w0 * zI0 + w1 * zI1);
+}
+
+// coarse operator: mean local part over the 8 children; face couplings
+// (1/4) * mean of the 4 fine couplings on the coarse face; diag = local + sum
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_coarsen(Level<T> F, Level<T> C) {
+  const int Nc = C.nx * C.ny * C.nz;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= Nc) return;
+  const int K = idx % C.nz;
+  const int t = idx / C.nz;
+  const int J = t % C.ny;
+  const int I = t / C.ny;
+  auto fi = [&](int i, int j, int k) {
+    return (wrap(i, F.nx) * F.ny + wrap(j, F.ny)) * F.nz + wrap(k, F.nz);
+  };
+  T local = T(0);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int c = 0; c < 2; ++c) {
+        const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+        const int p = fi(i, j, k);
+        const T cs = ((F.cx[p] + F.cx[fi(i - 1, j, k)]) + (F.cy[p] + F.cy[fi(i, j - 1, k)])) +
+                     (F.cz[p] + F.cz[fi(i, j, k - 1)]);
+        local += F.diag[p] - cs;
+      }
+  local *= T(0.125);
+  // couplings on the + faces of coarse cells (I,J,K) and of its - neighbours
+  auto face = [&](const T* c, int d, int i0, int j0, int k0) {
+    // fine + faces with index 2*I0+1 along d, 2x2 in the other directions
+    T s = T(0);
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) {
+        int i = 2 * i0, j = 2 * j0, k = 2 * k0;
+        if (d == 0) { i += 1; j += u; k += v; }
+        if (d == 1) { j += 1; i += u; k += v; }
+        if (d == 2) { k += 1; i += u; j += v; }
+        s += c[fi(i, j, k)];
+      }
+    return T(0.0625) * s;
+  };
+  const T cxp = face(F.cx, 0, I, J, K), cxm = face(F.cx, 0, I - 1, J, K);
+  const T cyp = face(F.cy, 1, I, J, K), cym = face(F.cy, 1, I, J - 1, K);
+  const T czp = face(F.cz, 2, I, J, K), czm = face(F.cz, 2, I, J, K - 1);
+  C.cx[idx] = cxp;
+  C.cy[idx] = cyp;
+  C.cz[idx] = czp;
+  C.diag[idx] = local + (((cxp + cxm) + (cyp + cym)) + (czp + czm));
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cvt_d2f(long n, const double* __restrict__ a,
+                                                    float* __restrict__ b) {
+  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+__global__ __launch_bounds__(BLOCK) void k_cvt_f2d(long n, const float* __restrict__ a,
+                                                    double* __restrict__ b) {
+  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fold_energy(int N, double* __restrict__ U,
+                                                        double* __restrict__ eh) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i < N) {
+    eh[i] = eh[i] + U[i];
+    U[i] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+static inline dim3 grid_for(long n) { return dim3((unsigned)((n + BLOCK - 1) / BLOCK)); }
+
+void launch_faces(const DevParams& P, const double* Un, const double* nH, double a, double* D,
+                  hipStream_t st) {
+  if (P.ns == 1) hipLaunchKernelGGL(k_faces<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, nH, a, D);
+  else hipLaunchKernelGGL(k_faces<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, nH, a, D);
+}
+
+void launch_explicit(const DevParams& P, const double* Un, const double* nH, const double* eh,
+                     const double* D, Step s, double* g, hipStream_t st) {
+  if (P.ns == 1)
+    hipLaunchKernelGGL(k_explicit<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, nH, eh, D, s, g);
+  else
+    hipLaunchKernelGGL(k_explicit<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, nH, eh, D, s, g);
+}
+
+void launch_sources(const long long* cells, const double* Q, int n, double scale, double* gE,
+                    hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_sources, dim3(1), dim3(64), 0, st, cells, Q, n, scale, gE);
+}
+
+void launch_residual(const DevParams& P, const double* U, const double* g, const double* nH,
+                     const double* eh, const double* D, Step s, double* f, double* parts,
+                     hipStream_t st) {
+  const int nb = reduce_blocks(P.N);
+  if (P.ns == 1)
+    hipLaunchKernelGGL(k_residual<1>, dim3(nb), dim3(BLOCK), 0, st, P, U, g, nH, eh, D, s, f, parts);
+  else
+    hipLaunchKernelGGL(k_residual<3>, dim3(nb), dim3(BLOCK), 0, st, P, U, g, nH, eh, D, s, f, parts);
+}
+
+void launch_trial(const DevParams& P, const double* U, const double* ftM, const double* W,
+                  const double* sE, double lambda, double* Ut, hipStream_t st) {
+  if (P.ns == 1)
+    hipLaunchKernelGGL(k_trial<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, ftM, W, sE, lambda, Ut);
+  else
+    hipLaunchKernelGGL(k_trial<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, ftM, W, sE, lambda, Ut);
+}
+
+void launch_local_jac(const DevParams& P, const double* U, const double* nH, const double* eh,
+                      Step s, double* M, double* Ucol, double* Lrow, double* dloc,
+                      hipStream_t st) {
+  if (P.ns == 1)
+    hipLaunchKernelGGL(k_local_jac<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, nH, eh, s, M, Ucol,
+                       Lrow, dloc);
+  else
+    hipLaunchKernelGGL(k_local_jac<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, nH, eh, s, M, Ucol,
+                       Lrow, dloc);
+}
+
+void launch_schur(const DevParams& P, const double* U, const double* f, const double* nH,
+                  const double* eh, const double* D, Step s, double* ftM, double* W, double* diag,
+                  double* cx, double* cy, double* cz, double* b, hipStream_t st) {
+  if (P.ns == 1)
+    hipLaunchKernelGGL(k_schur<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, f, nH, eh, D, s, ftM, W,
+                       diag, cx, cy, cz, b);
+  else
+    hipLaunchKernelGGL(k_schur<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, f, nH, eh, D, s, ftM, W,
+                       diag, cx, cy, cz, b);
+}
+
+void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(1024), 0, st, parts, nparts, ncomp, out);
+}
+void launch_cg_alpha(double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, st, sc);
+}
+void launch_cg_beta(double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, st, sc);
+}
+
+void launch_spmv_dot(int nx, int ny, int nz, const double* diag, const double* cx,
+                     const double* cy, const double* cz, const double* p, double* q,
+                     double* parts, hipStream_t st) {
+  const long N = (long)nx * ny * nz;
+  hipLaunchKernelGGL(k_spmv_dot, dim3(reduce_blocks(N)), dim3(BLOCK), 0, st, nx, ny, nz, diag, cx,
+                     cy, cz, p, q, parts);
+}
+void launch_update_xr(long n, double* x, double* r, const double* p, const double* q,
+                      const double* sc, double* parts, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_xr, dim3(reduce_blocks(n)), dim3(BLOCK), 0, st, n, x, r, p, q, sc,
+                     parts);
+}
+void launch_dot2(long n, const double* z, const double* r, const double* q, double* parts,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_dot2, dim3(reduce_blocks(n)), dim3(BLOCK), 0, st, n, z, r, q, parts);
+}
+void launch_dot1(long n, const double* a, const double* b, double* parts, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot1, dim3(reduce_blocks(n)), dim3(BLOCK), 0, st, n, a, b, parts);
+}
+void launch_update_p(long n, double* p, const double* z, const double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_p, grid_for(n), dim3(BLOCK), 0, st, n, p, z, sc);
+}
+
+template <class T>
+void launch_fill(long n, T* x, T v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill<T>, grid_for(n), dim3(BLOCK), 0, st, n, x, v);
+}
+template <class T>
+void launch_rbgs(const Level<T>& L, int colour, hipStream_t st) {
+  const long n2 = (long)L.nx * L.ny * (L.nz / 2);
+  hipLaunchKernelGGL(k_rbgs<T>, grid_for(n2), dim3(BLOCK), 0, st, L, colour);
+}
+template <class T>
+void launch_rbgs_first(const Level<T>& L, hipStream_t st) {
+  hipLaunchKernelGGL(k_rbgs_first<T>, grid_for((long)L.nx * L.ny * L.nz), dim3(BLOCK), 0, st, L);
+}
+template <class T>
+void launch_mg_residual(const Level<T>& L, hipStream_t st) {
+  hipLaunchKernelGGL(k_mg_residual<T>, grid_for((long)L.nx * L.ny * L.nz), dim3(BLOCK), 0, st, L);
+}
+template <class T>
+void launch_restrict(const Level<T>& F, const Level<T>& C, hipStream_t st) {
+  hipLaunchKernelGGL(k_restrict<T>, grid_for((long)C.nx * C.ny * C.nz), dim3(BLOCK), 0, st, F, C);
+}
+template <class T>
+void launch_prolong_add(const Level<T>& C, const Level<T>& F, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong_add<T>, grid_for((long)F.nx * F.ny * F.nz), dim3(BLOCK), 0, st, C, F);
+}
+template <class T>
+void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarsen<T>, grid_for((long)C.nx * C.ny * C.nz), dim3(BLOCK), 0, st, F, C);
+}
+void launch_fold_energy(int N, double* U, double* eh, hipStream_t st) {
+  hipLaunchKernelGGL(k_fold_energy, grid_for(N), dim3(BLOCK), 0, st, N, U, eh);
+}
+void launch_cvt_d2f(long n, const double* a, float* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_cvt_d2f, grid_for(n), dim3(BLOCK), 0, st, n, a, b);
+}
+void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_cvt_f2d, grid_for(n), dim3(BLOCK), 0, st, n, a, b);
+}
+
+#define RT_INST(T)                                                                   \
+  template void launch_fill<T>(long, T*, T, hipStream_t);                            \
+  template void launch_rbgs<T>(const Level<T>&, int, hipStream_t);                   \
+  template void launch_rbgs_first<T>(const Level<T>&, hipStream_t);                  \
+  template void launch_mg_residual<T>(const Level<T>&, hipStream_t);                 \
+  template void launch_restrict<T>(const Level<T>&, const Level<T>&, hipStream_t);   \
+  template void launch_prolong_add<T>(const Level<T>&, const Level<T>&, hipStream_t); \
+  template void launch_coarsen<T>(const Level<T>&, const Level<T>&, hipStream_t);
+RT_INST(double)
+RT_INST(float)
+#undef RT_INST
+
+}  // namespace rtk

@@ -1,0 +1,196 @@
+"""GPU <-> oracle parity, entry point by entry point, through the C ABI.
+
+Every case feeds identical seeded inputs to the CPU FP64 oracle and to the
+HIP library.  Tolerances (FP64 on both sides; differences come only from
+summation order and from the flexible-CG beta formula, which is algebraically
+identical):
+  time level, residual, local blocks, Schur set-up, one V-cycle   1e-12
+  CG with a fixed iteration count                                  1e-11
+  a full Newton step                                               1e-10
+Sizes span several 256-thread blocks and a ragged last block (n^3 = 4096,
+32768), and the 256^3 workload of the benchmark is checked at full size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+import oracle
+from oracle import jacobian as ojac
+from oracle import mg as omg
+from oracle import newton as onewt
+from oracle import residual as ores
+from tests.gpu_cases import dev, host, pair, random_case, rel
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (nspecies, n, theta, a, seed)
+    (1, 8, 1.0, 1.0, 11),
+    (1, 16, 0.51, 1.0, 12),
+    (1, 16, 1.0, 0.1, 13),
+    (3, 8, 1.0, 1.0, 14),
+    (3, 16, 0.51, 0.1, 15),
+]
+
+
+def scale_of(*arrs):
+    return max(float(np.max(np.abs(a))) for a in arrs)
+
+
+@pytest.mark.parametrize("ns,n,theta,a,seed", CASES)
+def test_time_level_and_residual(ns, n, theta, a, seed):
+    w, c = random_case(ns, n, theta, a, seed)
+    m, g = pair(w, c)
+    tl = ores.time_level(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], c["dt"], c["cosmo"], m)
+    f_o = ores.residual(c["U"], tl, c["nH"], c["eh"], c["dt"], c["cosmo"][2], c["cosmo"][3], m)
+    gn = g.rt_time_level(dev(c["Un"]), c["dt"], c["cosmo"])
+    f, rms = g.rt_eval_residual(dev(c["U"]), gn, c["dt"], c["cosmo"])
+    gn, f = host(gn), host(f)
+    u = m.scales
+    for v in range(m.nv):
+        assert rel(gn[v], tl["g"][v], scale_of(tl["g"][v], c["Un"][v])) <= 1e-13, v
+        s = scale_of(f_o[v], c["U"][v] / u[v], tl["g"][v] / u[v])
+        assert rel(f[v], f_o[v], s) <= 1e-12, v
+    assert abs(rms / ores.rms(f_o) - 1) <= 1e-12
+
+
+@pytest.mark.parametrize("ns,n,theta,a,seed", CASES)
+def test_local_jacobian(ns, n, theta, a, seed):
+    w, c = random_case(ns, n, theta, a, seed)
+    m, g = pair(w, c)
+    cos = c["cosmo"]
+    M, Uc, Lr, dl = ojac.local_blocks(c["U"], c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    gM, gU, gL, gd = [host(t) for t in g.rt_local_jacobian(dev(c["U"]), c["dt"], cos)]
+    assert rel(gM, M, max(1.0, scale_of(M))) <= 1e-12
+    assert rel(gU, Uc) <= 1e-12
+    assert rel(gL, Lr) <= 1e-12
+    assert rel(gd, dl) <= 1e-12
+
+
+@pytest.mark.parametrize("ns,n,theta,a,seed", CASES)
+def test_schur_form(ns, n, theta, a, seed):
+    w, c = random_case(ns, n, theta, a, seed)
+    m, g = pair(w, c)
+    cos = c["cosmo"]
+    tl = ores.time_level(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], c["dt"], cos, m)
+    f_o = ores.residual(c["U"], tl, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    sch = ojac.schur_form(c["U"], f_o, tl["D"], c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    gn = g.rt_time_level(dev(c["Un"]), c["dt"], cos)
+    fd = dev(f_o)                                  # same residual input on both sides
+    b = host(g.rt_schur_form(dev(c["U"]), fd, c["dt"], cos))
+    got = {k: host(v) for k, v in g.rt_schur_get().items()}
+    del gn
+    for k in ("ftM", "W"):
+        for r in range(m.nb):
+            assert rel(got[k][r], sch[k][r]) <= 1e-12, (k, r)
+    for k in ("diag", "cx", "cy", "cz"):
+        assert rel(got[k], sch[k]) <= 1e-12, k
+    assert rel(b, sch["b"]) <= 1e-12
+
+
+@pytest.mark.parametrize("n,levels", [(16, 3), (32, 3), (32, 4)])
+def test_vcycle(n, levels):
+    w, c = random_case(1, n, 1.0, 1.0, 21, levels=levels)
+    m, g = pair(w, c)
+    rng = np.random.default_rng(5)
+    # variable-coefficient SPD operator of Schur form
+    d0 = 1.0 + rng.uniform(0, 20, (n,) * 3)
+    cs = [rng.uniform(0.1, 10, (n,) * 3) for _ in range(3)]
+    csum = sum(cc + np.roll(cc, 1, axis=dd) for dd, cc in enumerate(cs))
+    op = (d0 + csum, cs[0], cs[1], cs[2])
+    g.rt_set_operator(*[dev(o) for o in op])
+    r = rng.standard_normal((n,) * 3)
+    z = host(g.rt_mg_vcycle(dev(r)))
+    z_o = omg.vcycle(r, omg.hierarchy(op, levels), m)
+    assert rel(z, z_o) <= 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_pcg_fixed_iterations(k):
+    n, levels = 32, 3
+    w, c = random_case(1, n, 1.0, 1.0, 31, levels=levels)
+    m, g = pair(w, c)
+    cos = c["cosmo"]
+    tl = ores.time_level(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], c["dt"], cos, m)
+    f_o = ores.residual(c["U"], tl, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    sch = ojac.schur_form(c["U"], f_o, tl["D"], c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    op = (sch["diag"], sch["cx"], sch["cy"], sch["cz"])
+    g.rt_set_operator(*[dev(o) for o in op])
+    s, its, rr = g.rt_mg_pcg_solve(dev(sch["b"]), 0.0, k)
+    s_o, its_o, rr_o = omg.pcg(op, sch["b"], m, rtol=0.0, maxit=k)
+    assert its == its_o == k
+    assert rel(host(s), s_o) <= 1e-11
+    assert abs(rr - rr_o) <= 1e-9 * max(rr_o, 1e-30) + 1e-14
+
+
+def test_pcg_converges_to_direct_solution():
+    n, levels = 16, 3
+    w, c = random_case(1, n, 1.0, 1.0, 41, levels=levels)
+    m, g = pair(w, c)
+    cos = c["cosmo"]
+    tl = ores.time_level(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], c["dt"], cos, m)
+    f_o = ores.residual(c["U"], tl, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    sch = ojac.schur_form(c["U"], f_o, tl["D"], c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    op = (sch["diag"], sch["cx"], sch["cy"], sch["cz"])
+    g.rt_set_operator(*[dev(o) for o in op])
+    s, its, rr = g.rt_mg_pcg_solve(dev(sch["b"]), 1e-13, 200)
+    assert rr <= 1e-13
+    s_direct = onewt.direct_solve(op, sch["b"])
+    assert rel(host(s), s_direct) <= 1e-11
+
+
+def newton_parity(w, state, steps=1, tol_fields=1e-10, mg_fp32=0):
+    """Run `steps` steps on both sides from the same state; compare each step."""
+    m = oracle.model_from_workload(w)
+    from paper_0901_1110_amd.driver import Simulation
+    sim = Simulation(w, state={k: v.copy() if hasattr(v, "copy") else v
+                               for k, v in state.items()})
+    Un, eh = state["U"].copy(), state["eh"].copy()
+    out = []
+    for n in range(steps):
+        cos = w.cosmology(n)
+        U_o, st_o = onewt.newton_step(Un, Un, state["nH"], eh, state["src_cells"],
+                                      state["src_Q"], w.dt, cos, m)
+        st = sim.step()
+        assert st["status"] == 0 and st_o["status"] == 0, (st, st_o)
+        assert st["newton_its"] == st_o["newton_its"], (st, st_o)
+        assert st["cg_its"] == st_o["cg_its"], (st, st_o)
+        assert st["lambdas"] == st_o["lambdas"]
+        U = host(sim.U)
+        for v in range(m.nv):
+            assert rel(U[v], U_o[v]) <= tol_fields, (n, v, rel(U[v], U_o[v]))
+        out.append((st, st_o))
+        sim.advance()
+        eh = eh + U_o[0]
+        U_o[0] = 0.0
+        Un = U_o
+    return out
+
+
+def test_newton_step_small_config():
+    """The 32^3 single-source hydrogen step, end to end."""
+    w = synth.CFG_SMALL
+    newton_parity(w, synth.initial_state(w))
+
+
+def test_newton_steps_256_spacing():
+    """Three steps at the 256^3 cell size (64^3 box): fronts, line search."""
+    w = synth.CFG_256.replace(n=64, mg_levels=4)
+    newton_parity(w, synth.initial_state(w), steps=3)
+
+
+def test_newton_steps_expanding_lognormal():
+    """Expanding lognormal medium with 16 sources (32^3 cut of the 128^3 workload)."""
+    w = synth.CFG_COSMO.replace(n=32, mg_levels=3, dx=synth.CFG_COSMO.dx)
+    newton_parity(w, synth.initial_state(w), steps=2)
+
+
+def test_newton_step_hydrogen_helium():
+    w = synth.CFG_HHE.replace(n=16, mg_levels=2)
+    newton_parity(w, synth.initial_state(w), steps=1)
+
+
+def test_newton_step_theta_051():
+    w = synth.CFG_SMALL.replace(theta=0.51, dt=1e10)
+    newton_parity(w, synth.initial_state(w), steps=2)
