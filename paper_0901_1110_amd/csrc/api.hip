@@ -48,6 +48,7 @@ struct Workspace {
   std::vector<Level<double>> L64;
   std::vector<Level<float>> L32;
   float* r32;   // FP32 copy of the CG residual fed to the V-cycle
+  size_t nparts_cap;
 };
 
 }  // namespace
@@ -175,7 +176,11 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
   w->z = c.take<double>(N);
   w->p = c.take<double>(N);
   w->q = c.take<double>(N);
-  w->parts = c.take<double>((size_t)MAX_PARTS * NCOMP_MAX);
+  {
+    const size_t sb = (size_t)stencil_blocks(p->nx, p->ny, p->nz);
+    w->nparts_cap = sb > (size_t)MAX_PARTS ? sb : (size_t)MAX_PARTS;
+    w->parts = c.take<double>(w->nparts_cap * NCOMP_MAX);
+  }
   w->sc = c.take<double>(32);
   w->src_cells = c.take<long long>(p->max_sources > 0 ? p->max_sources : 1);
   w->src_Q = c.take<double>(p->max_sources > 0 ? p->max_sources : 1);
@@ -220,16 +225,20 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l) {
   Level<T>& L = Ls[l];
   const bool coarsest = (l + 1 == (int)Ls.size());
   const int kc = l == 0 ? RT_K_RBGS_FINE : RT_K_RBGS_COARSE;
+  const long n = (long)L.nx * L.ny * L.nz;
+  if (coarsest && n <= COARSE_SOLVE_MAX) {
+    TK(g, kc, launch_coarse_solve<T>(L, p.mg_coarse_sweeps, st));
+    return;
+  }
   const int pre = coarsest ? p.mg_coarse_sweeps : p.mg_pre;
   if (pre > 0) {
-    TK(g, kc, launch_rbgs_first<T>(L, st));     // red from x = 0
-    TK(g, kc, launch_rbgs<T>(L, 1, st));        // black
+    TK(g, kc, launch_rbgs_first_pair<T>(L, st));   // (red, black) from x = 0
     for (int s = 1; s < pre; ++s) {
       TK(g, kc, launch_rbgs<T>(L, 0, st));
       TK(g, kc, launch_rbgs<T>(L, 1, st));
     }
   } else {
-    TK(g, RT_K_OTHER, launch_fill<T>((long)L.nx * L.ny * L.nz, L.x, T(0), st));
+    TK(g, RT_K_OTHER, launch_fill<T>(n, L.x, T(0), st));
   }
   if (!coarsest) {
     TK(g, RT_K_MG_TRANSFER, launch_mg_residual<T>(L, st));
@@ -320,7 +329,7 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, int maxit, int* ite
   int k = 0;
   for (k = 1; k <= maxit; ++k) {
     TK(g, RT_K_SPMV, launch_spmv_dot(g->P.nx, g->P.ny, g->P.nz, w.diag, w.cx, w.cy, w.cz, w.p, w.q, w.parts, g->st));
-    finish_reduce(g, nparts, 1, S_PQ);
+    finish_reduce(g, stencil_blocks(g->P.nx, g->P.ny, g->P.nz), 1, S_PQ);
     TK(g, RT_K_REDUCE, launch_cg_alpha(w.sc, g->st));
     TK(g, RT_K_CG_VECTOR, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st));
     finish_reduce(g, nparts, 1, S_RR);
@@ -363,7 +372,7 @@ int residual_norm(rt_grid* g, const double* U, const double* gn, Step s, double*
                   double* viol) {
   const DevParams& P = g->P;
   TK(g, RT_K_RESIDUAL, launch_residual(P, U, gn, g->nH, g->eh, g->w.D, s, f, g->w.parts, g->st));
-  finish_reduce(g, reduce_blocks(P.N), 2, S_FN);
+  finish_reduce(g, stencil_blocks(P.nx, P.ny, P.nz), 2, S_FN);
   double h[2];
   RTCHK(read_scalars(g, g->w.sc + S_FN, h, 2));
   *fn = std::sqrt(h[0] / ((double)P.N * P.nv));

@@ -71,7 +71,10 @@ struct Level {
 };
 template <class T> void launch_fill(long n, T* x, T v, hipStream_t st);
 template <class T> void launch_rbgs(const Level<T>& L, int colour, hipStream_t st);
-template <class T> void launch_rbgs_first(const Level<T>& L, hipStream_t st);
+template <class T> void launch_rbgs_first_pair(const Level<T>& L, hipStream_t st);
+template <class T> void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st);
+int stencil_blocks(int nx, int ny, int nz);   // blocks (= partial sums) of a 3-D stencil launch
+constexpr int COARSE_SOLVE_MAX = 8192;        // coarsest levels up to this size: one workgroup
 template <class T> void launch_mg_residual(const Level<T>& L, hipStream_t st);
 template <class T> void launch_restrict(const Level<T>& F, const Level<T>& C, hipStream_t st);
 template <class T> void launch_prolong_add(const Level<T>& C, const Level<T>& F, hipStream_t st);

@@ -16,17 +16,15 @@
 namespace rtk {
 
 // ---------------------------------------------------------------------------
-// indexing helpers
+// indexing: stencil kernels launch a 3-D grid, x along z (fastest), y along
+// y, one grid slice per x-plane, so cell coordinates need no division.
 struct Nb {
   int xm, xp, ym, yp, zm, zp;
 };
 
-__device__ inline Nb neighbours(int idx, int nx, int ny, int nz) {
-  const int k = idx % nz;
-  const int t = idx / nz;
-  const int j = t % ny;
-  const int i = t / ny;
+__device__ inline Nb nbrs(int i, int j, int k, int nx, int ny, int nz) {
   const int sx = ny * nz;
+  const int idx = (i * ny + j) * nz + k;
   Nb n;
   n.xp = idx + (i + 1 < nx ? sx : -(nx - 1) * sx);
   n.xm = idx + (i > 0 ? -sx : (nx - 1) * sx);
@@ -37,11 +35,30 @@ __device__ inline Nb neighbours(int idx, int nx, int ny, int nz) {
   return n;
 }
 
+// coordinates of this thread in a 3-D launch over (nx, ny, ext); ok = in range
+struct C3 {
+  int i, j, k;
+  bool ok;
+};
+__device__ inline C3 coord3(int ny, int ext) {
+  C3 c;
+  c.k = blockIdx.x * blockDim.x + threadIdx.x;
+  c.j = blockIdx.y * blockDim.y + threadIdx.y;
+  c.i = blockIdx.z;
+  c.ok = c.k < ext && c.j < ny;
+  return c;
+}
+__device__ inline int block_linear() {
+  return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+}
+
 // ---------------------------------------------------------------------------
 // deterministic block reduction of NC values (result valid in thread 0)
 template <int NC>
 __device__ inline void block_reduce(double (&v)[NC], double* out) {
   __shared__ double sh[BLOCK / 64][NC];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int nthr = blockDim.x * blockDim.y;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     double x = v[c];
@@ -49,20 +66,21 @@ __device__ inline void block_reduce(double (&v)[NC], double* out) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     v[c] = x;
   }
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
   if (lane == 0) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) sh[w][c] = v[c];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
+    const int nw = (nthr + 63) >> 6;
+    const int b = block_linear();
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double s = 0.0;
-#pragma unroll
-      for (int i = 0; i < BLOCK / 64; ++i) s += sh[i][c];
-      out[blockIdx.x * NCOMP_MAX + c] = s;
+      for (int i = 0; i < nw; ++i) s += sh[i][c];
+      out[(size_t)b * NCOMP_MAX + c] = s;
     }
   }
 }
@@ -74,9 +92,10 @@ __global__ __launch_bounds__(BLOCK) void k_faces(DevParams P, const double* __re
                                                   const double* __restrict__ nH, double a,
                                                   double* __restrict__ D) {
   const int N = P.N;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  if (idx >= N) return;
-  const Nb nb = neighbours(idx, P.nx, P.ny, P.nz);
+  const C3 c = coord3(P.ny, P.nz);
+  if (!c.ok) return;
+  const int idx = (c.i * P.ny + c.j) * P.nz + c.k;
+  const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
   const double* E = Un + (NS + 1) * N;
   double x[NS];
   const int nbr[3] = {nb.xp, nb.yp, nb.zp};
@@ -114,13 +133,14 @@ __global__ __launch_bounds__(BLOCK) void k_explicit(DevParams P, const double* _
                                                      double* __restrict__ g) {
   constexpr int NV = NS + 2;
   const int N = P.N;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  if (idx >= N) return;
+  const C3 c = coord3(P.ny, P.nz);
+  if (!c.ok) return;
+  const int idx = (c.i * P.ny + c.j) * P.nz + c.k;
   double u[NV], L[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = Un[v * N + idx];
   local_ops<NS, double>(u, nH[idx], eh[idx], s.a, s.H, P, L);
-  const Nb nb = neighbours(idx, P.nx, P.ny, P.nz);
+  const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
   const double dif = diffusion_sum(Un + (NS + 1) * N, D, N, idx, nb, u[NS + 1]);
   L[NS + 1] += -dif / (s.a * s.a * P.dx * P.dx);
   const double w = s.dt * (P.theta - 1.0);
@@ -152,13 +172,15 @@ __global__ __launch_bounds__(BLOCK) void k_residual(DevParams P, const double* _
   const double dtt = s.dt * P.theta;
   const double inv_a2dx2 = 1.0 / (s.a * s.a * P.dx * P.dx);
   double acc[2] = {0.0, 0.0};
-  for (int idx = blockIdx.x * BLOCK + threadIdx.x; idx < N; idx += gridDim.x * BLOCK) {
+  const C3 c = coord3(P.ny, P.nz);
+  if (c.ok) {
+    const int idx = (c.i * P.ny + c.j) * P.nz + c.k;
     double u[NV], L[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = U[v * N + idx];
     const double ehv = eh[idx];
     local_ops<NS, double>(u, nH[idx], ehv, s.a, s.H, P, L);
-    const Nb nb = neighbours(idx, P.nx, P.ny, P.nz);
+    const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
     const double dif = diffusion_sum(U + (NS + 1) * N, D, N, idx, nb, u[NS + 1]);
     L[NS + 1] += -dif * inv_a2dx2;
 #pragma unroll
@@ -321,8 +343,9 @@ __global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __re
                                                   double* __restrict__ b) {
   constexpr int NB = NS + 1;
   const int N = P.N;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  if (idx >= N) return;
+  const C3 c = coord3(P.ny, P.nz);
+  if (!c.ok) return;
+  const int idx = (c.i * P.ny + c.j) * P.nz + c.k;
   double u[NS + 2];
 #pragma unroll
   for (int v = 0; v < NS + 2; ++v) u[v] = U[v * N + idx];
@@ -335,7 +358,7 @@ __global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __re
     B[i][1] = Uc[i];
   }
   gepp2<NB>(M, B);
-  const Nb nb = neighbours(idx, P.nx, P.ny, P.nz);
+  const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
   const double cf = s.dt * P.theta / (s.a * s.a * P.dx * P.dx);
   const double cxp = cf * D[idx], cxm = cf * D[nb.xm];
   const double cyp = cf * D[N + idx], cym = cf * D[N + nb.ym];
@@ -397,10 +420,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_dot(int nx, int ny, int nz,
                                                      const double* __restrict__ p,
                                                      double* __restrict__ q,
                                                      double* __restrict__ parts) {
-  const int N = nx * ny * nz;
   double acc[1] = {0.0};
-  for (int idx = blockIdx.x * BLOCK + threadIdx.x; idx < N; idx += gridDim.x * BLOCK) {
-    const Nb nb = neighbours(idx, nx, ny, nz);
+  const C3 c = coord3(ny, nz);
+  if (c.ok) {
+    const int idx = (c.i * ny + c.j) * nz + c.k;
+    const Nb nb = nbrs(c.i, c.j, c.k, nx, ny, nz);
     const double pv = p[idx];
     double y = diag[idx] * pv;
     y = y - cx[idx] * p[nb.xp] - cx[nb.xm] * p[nb.xm];
@@ -467,20 +491,13 @@ __global__ __launch_bounds__(BLOCK) void k_fill(long n, T* __restrict__ x, T v) 
   if (i < n) x[i] = v;
 }
 
-// one colour of a red-black Gauss-Seidel sweep; thread t owns the t-th cell of
-// that colour in z-fastest order (nz even)
+// one colour of a red-black Gauss-Seidel sweep (colour = (i+j+k) mod 2);
+// the launch's x extent is nz/2: thread kk owns the kk-th cell of the colour
+// in its z-row (nz even)
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_rbgs(Level<T> L, int colour) {
-  const int half = L.nz >> 1;
-  const int n2 = L.nx * L.ny * half;
-  const int t = blockIdx.x * BLOCK + threadIdx.x;
-  if (t >= n2) return;
-  const int row = t / half;
-  const int j = row % L.ny;
-  const int i = row / L.ny;
-  const int k = 2 * (t - row * half) + ((i + j + colour) & 1);
-  const int idx = row * L.nz + k;
-  const Nb nb = neighbours(idx, L.nx, L.ny, L.nz);
+__device__ inline void rbgs_update(const Level<T>& L, int i, int j, int k) {
+  const int idx = (i * L.ny + j) * L.nz + k;
+  const Nb nb = nbrs(i, j, k, L.nx, L.ny, L.nz);
   const T* x = L.x;
   T s = L.b[idx];
   s = s + L.cx[idx] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
@@ -489,25 +506,68 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Level<T> L, int colour) {
   L.x[idx] = s / L.diag[idx];
 }
 
-// first red half-sweep from x = 0: red cells b/diag, black cells 0
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_rbgs_first(Level<T> L) {
-  const int N = L.nx * L.ny * L.nz;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  if (idx >= N) return;
-  const int k = idx % L.nz;
-  const int t = idx / L.nz;
-  const int j = t % L.ny;
-  const int i = t / L.ny;
-  L.x[idx] = ((i + j + k) & 1) == 0 ? L.b[idx] / L.diag[idx] : T(0);
+__global__ __launch_bounds__(BLOCK) void k_rbgs(Level<T> L, int colour) {
+  const C3 c = coord3(L.ny, L.nz >> 1);
+  if (!c.ok) return;
+  const int k = 2 * c.k + ((c.i + c.j + colour) & 1);
+  rbgs_update(L, c.i, c.j, k);
+}
+
+// the first (red, black) pair from x = 0 in one pass: red cells take b/diag,
+// black cells use their red neighbours' b/diag (the values the red half-sweep
+// would have produced)
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_rbgs_first_pair(Level<T> L) {
+  const C3 c = coord3(L.ny, L.nz);
+  if (!c.ok) return;
+  const int idx = (c.i * L.ny + c.j) * L.nz + c.k;
+  if (((c.i + c.j + c.k) & 1) == 0) {
+    L.x[idx] = L.b[idx] / L.diag[idx];
+    return;
+  }
+  const Nb nb = nbrs(c.i, c.j, c.k, L.nx, L.ny, L.nz);
+  const T* b = L.b;
+  const T* d = L.diag;
+  T s = b[idx];
+  s = s + L.cx[idx] * (b[nb.xp] / d[nb.xp]) + L.cx[nb.xm] * (b[nb.xm] / d[nb.xm]);
+  s = s + L.cy[idx] * (b[nb.yp] / d[nb.yp]) + L.cy[nb.ym] * (b[nb.ym] / d[nb.ym]);
+  s = s + L.cz[idx] * (b[nb.zp] / d[nb.zp]) + L.cz[nb.zm] * (b[nb.zm] / d[nb.zm]);
+  L.x[idx] = s / d[idx];
+}
+
+// coarsest-level solve in one workgroup: `sweeps` x (red, black) from x = 0,
+// then `sweeps` x (black, red); the level is small enough to stay in L2
+template <class T>
+__global__ __launch_bounds__(1024) void k_coarse_solve(Level<T> L, int sweeps) {
+  const int half = L.nz >> 1;
+  const int n2 = L.nx * L.ny * half;
+  const int N = 2 * n2;
+  for (int idx = threadIdx.x; idx < N; idx += blockDim.x) L.x[idx] = T(0);
+  __threadfence_block();
+  __syncthreads();
+  for (int s = 0; s < 2 * sweeps; ++s) {
+    for (int h = 0; h < 2; ++h) {
+      const int colour = (s < sweeps) ? h : 1 - h;
+      for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+        const int row = t / half;
+        const int j = row % L.ny;
+        const int i = row / L.ny;
+        const int k = 2 * (t - row * half) + ((i + j + colour) & 1);
+        rbgs_update(L, i, j, k);
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+  }
 }
 
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L) {
-  const int N = L.nx * L.ny * L.nz;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  if (idx >= N) return;
-  const Nb nb = neighbours(idx, L.nx, L.ny, L.nz);
+  const C3 c = coord3(L.ny, L.nz);
+  if (!c.ok) return;
+  const int idx = (c.i * L.ny + c.j) * L.nz + c.k;
+  const Nb nb = nbrs(c.i, c.j, c.k, L.nx, L.ny, L.nz);
   const T* x = L.x;
   T y = L.diag[idx] * x[idx];
   y = y - L.cx[idx] * x[nb.xp] - L.cx[nb.xm] * x[nb.xm];
@@ -522,48 +582,46 @@ __device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - 
 // fine cells 2I-1 .. 2I+2
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C) {
-  const int Nc = C.nx * C.ny * C.nz;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  if (idx >= Nc) return;
-  const int K = idx % C.nz;
-  const int t = idx / C.nz;
-  const int J = t % C.ny;
-  const int I = t / C.ny;
+  const C3 c = coord3(C.ny, C.nz);
+  if (!c.ok) return;
+  const int I = c.i, J = c.j, K = c.k;
   const T w[4] = {T(0.125), T(0.375), T(0.375), T(0.125)};
+  int kk[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) kk[q] = wrap(2 * K - 1 + q, F.nz);
   T acc = T(0);
+#pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int i = wrap(2 * I - 1 + a, F.nx);
     T acc_j = T(0);
+#pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int j = wrap(2 * J - 1 + b, F.ny);
       const T* rr = F.r + (i * F.ny + j) * F.nz;
       T acc_k = T(0);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc_k += w[c] * rr[wrap(2 * K - 1 + c, F.nz)];
+      for (int q = 0; q < 4; ++q) acc_k += w[q] * rr[kk[q]];
       acc_j += w[b] * acc_k;
     }
     acc += w[a] * acc_j;
   }
-  C.b[idx] = acc;
+  C.b[(I * C.ny + J) * C.nz + K] = acc;
 }
 
 // x_fine += P x_coarse: cell-centred trilinear, weights 3/4 (parent) and 1/4
 // (the parent's neighbour on the child's side) per axis
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_prolong_add(Level<T> C, Level<T> F) {
-  const int Nf = F.nx * F.ny * F.nz;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  if (idx >= Nf) return;
-  const int k = idx % F.nz;
-  const int t = idx / F.nz;
-  const int j = t % F.ny;
-  const int i = t / F.ny;
+  const C3 c = coord3(F.ny, F.nz);
+  if (!c.ok) return;
+  const int i = c.i, j = c.j, k = c.k;
+  const int idx = (i * F.ny + j) * F.nz + k;
   const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
   const int I1 = wrap(I0 + ((i & 1) ? 1 : -1), C.nx);
   const int J1 = wrap(J0 + ((j & 1) ? 1 : -1), C.ny);
   const int K1 = wrap(K0 + ((k & 1) ? 1 : -1), C.nz);
   const T* x = C.x;
-  auto at = [&](int a, int b, int c) { return x[(a * C.ny + b) * C.nz + c]; };
+  auto at = [&](int a, int b, int cc) { return x[(a * C.ny + b) * C.nz + cc]; };
   const T w0 = T(0.75), w1 = T(0.25);
   const T zI0 = w0 * (w0 * at(I0, J0, K0) + w1 * at(I0, J0, K1)) +
                 w1 * (w0 * at(I0, J1, K0) + w1 * at(I0, J1, K1));
@@ -576,40 +634,37 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_add(Level<T> C, Level<T> F) {
 // (1/4) * mean of the 4 fine couplings on the coarse face; diag = local + sum
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_coarsen(Level<T> F, Level<T> C) {
-  const int Nc = C.nx * C.ny * C.nz;
-  const int idx = blockIdx.x * BLOCK + threadIdx.x;
-  if (idx >= Nc) return;
-  const int K = idx % C.nz;
-  const int t = idx / C.nz;
-  const int J = t % C.ny;
-  const int I = t / C.ny;
+  const C3 c = coord3(C.ny, C.nz);
+  if (!c.ok) return;
+  const int I = c.i, J = c.j, K = c.k;
+  const int idx = (I * C.ny + J) * C.nz + K;
   auto fi = [&](int i, int j, int k) {
     return (wrap(i, F.nx) * F.ny + wrap(j, F.ny)) * F.nz + wrap(k, F.nz);
   };
   T local = T(0);
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
-      for (int c = 0; c < 2; ++c) {
-        const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+      for (int cc = 0; cc < 2; ++cc) {
+        const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + cc;
         const int p = fi(i, j, k);
         const T cs = ((F.cx[p] + F.cx[fi(i - 1, j, k)]) + (F.cy[p] + F.cy[fi(i, j - 1, k)])) +
                      (F.cz[p] + F.cz[fi(i, j, k - 1)]);
         local += F.diag[p] - cs;
       }
   local *= T(0.125);
-  // couplings on the + faces of coarse cells (I,J,K) and of its - neighbours
-  auto face = [&](const T* c, int d, int i0, int j0, int k0) {
+  // couplings on the + faces of coarse cell (I,J,K) and of its - neighbours
+  auto face = [&](const T* cf, int d, int i0, int j0, int k0) {
     // fine + faces with index 2*I0+1 along d, 2x2 in the other directions
-    T s = T(0);
+    T sum = T(0);
     for (int u = 0; u < 2; ++u)
       for (int v = 0; v < 2; ++v) {
         int i = 2 * i0, j = 2 * j0, k = 2 * k0;
         if (d == 0) { i += 1; j += u; k += v; }
         if (d == 1) { j += 1; i += u; k += v; }
         if (d == 2) { k += 1; i += u; j += v; }
-        s += c[fi(i, j, k)];
+        sum += cf[fi(i, j, k)];
       }
-    return T(0.0625) * s;
+    return T(0.0625) * sum;
   };
   const T cxp = face(F.cx, 0, I, J, K), cxm = face(F.cx, 0, I - 1, J, K);
   const T cyp = face(F.cy, 1, I, J, K), cym = face(F.cy, 1, I, J - 1, K);
@@ -644,18 +699,34 @@ __global__ __launch_bounds__(BLOCK) void k_fold_energy(int N, double* __restrict
 // launchers
 static inline dim3 grid_for(long n) { return dim3((unsigned)((n + BLOCK - 1) / BLOCK)); }
 
+// 3-D launch over (nx, ny, ext): x along z, y along y, z over x-planes
+struct Geo {
+  dim3 g, b;
+};
+static inline Geo geo3(int nx, int ny, int ext) {
+  const int bx = ext < BLOCK ? ext : BLOCK;
+  int by = BLOCK / bx;
+  if (by > ny) by = ny;
+  return Geo{dim3((unsigned)((ext + bx - 1) / bx), (unsigned)((ny + by - 1) / by), (unsigned)nx),
+             dim3((unsigned)bx, (unsigned)by, 1)};
+}
+int stencil_blocks(int nx, int ny, int nz) {
+  const Geo q = geo3(nx, ny, nz);
+  return (int)(q.g.x * q.g.y * q.g.z);
+}
+
 void launch_faces(const DevParams& P, const double* Un, const double* nH, double a, double* D,
                   hipStream_t st) {
-  if (P.ns == 1) hipLaunchKernelGGL(k_faces<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, nH, a, D);
-  else hipLaunchKernelGGL(k_faces<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, nH, a, D);
+  const Geo q = geo3(P.nx, P.ny, P.nz);
+  if (P.ns == 1) hipLaunchKernelGGL(k_faces<1>, q.g, q.b, 0, st, P, Un, nH, a, D);
+  else hipLaunchKernelGGL(k_faces<3>, q.g, q.b, 0, st, P, Un, nH, a, D);
 }
 
 void launch_explicit(const DevParams& P, const double* Un, const double* nH, const double* eh,
                      const double* D, Step s, double* g, hipStream_t st) {
-  if (P.ns == 1)
-    hipLaunchKernelGGL(k_explicit<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, nH, eh, D, s, g);
-  else
-    hipLaunchKernelGGL(k_explicit<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, nH, eh, D, s, g);
+  const Geo q = geo3(P.nx, P.ny, P.nz);
+  if (P.ns == 1) hipLaunchKernelGGL(k_explicit<1>, q.g, q.b, 0, st, P, Un, nH, eh, D, s, g);
+  else hipLaunchKernelGGL(k_explicit<3>, q.g, q.b, 0, st, P, Un, nH, eh, D, s, g);
 }
 
 void launch_sources(const long long* cells, const double* Q, int n, double scale, double* gE,
@@ -666,11 +737,9 @@ void launch_sources(const long long* cells, const double* Q, int n, double scale
 void launch_residual(const DevParams& P, const double* U, const double* g, const double* nH,
                      const double* eh, const double* D, Step s, double* f, double* parts,
                      hipStream_t st) {
-  const int nb = reduce_blocks(P.N);
-  if (P.ns == 1)
-    hipLaunchKernelGGL(k_residual<1>, dim3(nb), dim3(BLOCK), 0, st, P, U, g, nH, eh, D, s, f, parts);
-  else
-    hipLaunchKernelGGL(k_residual<3>, dim3(nb), dim3(BLOCK), 0, st, P, U, g, nH, eh, D, s, f, parts);
+  const Geo q = geo3(P.nx, P.ny, P.nz);
+  if (P.ns == 1) hipLaunchKernelGGL(k_residual<1>, q.g, q.b, 0, st, P, U, g, nH, eh, D, s, f, parts);
+  else hipLaunchKernelGGL(k_residual<3>, q.g, q.b, 0, st, P, U, g, nH, eh, D, s, f, parts);
 }
 
 void launch_trial(const DevParams& P, const double* U, const double* ftM, const double* W,
@@ -695,12 +764,11 @@ void launch_local_jac(const DevParams& P, const double* U, const double* nH, con
 void launch_schur(const DevParams& P, const double* U, const double* f, const double* nH,
                   const double* eh, const double* D, Step s, double* ftM, double* W, double* diag,
                   double* cx, double* cy, double* cz, double* b, hipStream_t st) {
+  const Geo q = geo3(P.nx, P.ny, P.nz);
   if (P.ns == 1)
-    hipLaunchKernelGGL(k_schur<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, f, nH, eh, D, s, ftM, W,
-                       diag, cx, cy, cz, b);
+    hipLaunchKernelGGL(k_schur<1>, q.g, q.b, 0, st, P, U, f, nH, eh, D, s, ftM, W, diag, cx, cy, cz, b);
   else
-    hipLaunchKernelGGL(k_schur<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, f, nH, eh, D, s, ftM, W,
-                       diag, cx, cy, cz, b);
+    hipLaunchKernelGGL(k_schur<3>, q.g, q.b, 0, st, P, U, f, nH, eh, D, s, ftM, W, diag, cx, cy, cz, b);
 }
 
 void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out, hipStream_t st) {
@@ -716,9 +784,8 @@ void launch_cg_beta(double* sc, hipStream_t st) {
 void launch_spmv_dot(int nx, int ny, int nz, const double* diag, const double* cx,
                      const double* cy, const double* cz, const double* p, double* q,
                      double* parts, hipStream_t st) {
-  const long N = (long)nx * ny * nz;
-  hipLaunchKernelGGL(k_spmv_dot, dim3(reduce_blocks(N)), dim3(BLOCK), 0, st, nx, ny, nz, diag, cx,
-                     cy, cz, p, q, parts);
+  const Geo g = geo3(nx, ny, nz);
+  hipLaunchKernelGGL(k_spmv_dot, g.g, g.b, 0, st, nx, ny, nz, diag, cx, cy, cz, p, q, parts);
 }
 void launch_update_xr(long n, double* x, double* r, const double* p, const double* q,
                       const double* sc, double* parts, hipStream_t st) {
@@ -742,28 +809,37 @@ void launch_fill(long n, T* x, T v, hipStream_t st) {
 }
 template <class T>
 void launch_rbgs(const Level<T>& L, int colour, hipStream_t st) {
-  const long n2 = (long)L.nx * L.ny * (L.nz / 2);
-  hipLaunchKernelGGL(k_rbgs<T>, grid_for(n2), dim3(BLOCK), 0, st, L, colour);
+  const Geo q = geo3(L.nx, L.ny, L.nz / 2);
+  hipLaunchKernelGGL(k_rbgs<T>, q.g, q.b, 0, st, L, colour);
 }
 template <class T>
-void launch_rbgs_first(const Level<T>& L, hipStream_t st) {
-  hipLaunchKernelGGL(k_rbgs_first<T>, grid_for((long)L.nx * L.ny * L.nz), dim3(BLOCK), 0, st, L);
+void launch_rbgs_first_pair(const Level<T>& L, hipStream_t st) {
+  const Geo q = geo3(L.nx, L.ny, L.nz);
+  hipLaunchKernelGGL(k_rbgs_first_pair<T>, q.g, q.b, 0, st, L);
+}
+template <class T>
+void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(1024), 0, st, L, sweeps);
 }
 template <class T>
 void launch_mg_residual(const Level<T>& L, hipStream_t st) {
-  hipLaunchKernelGGL(k_mg_residual<T>, grid_for((long)L.nx * L.ny * L.nz), dim3(BLOCK), 0, st, L);
+  const Geo q = geo3(L.nx, L.ny, L.nz);
+  hipLaunchKernelGGL(k_mg_residual<T>, q.g, q.b, 0, st, L);
 }
 template <class T>
 void launch_restrict(const Level<T>& F, const Level<T>& C, hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict<T>, grid_for((long)C.nx * C.ny * C.nz), dim3(BLOCK), 0, st, F, C);
+  const Geo q = geo3(C.nx, C.ny, C.nz);
+  hipLaunchKernelGGL(k_restrict<T>, q.g, q.b, 0, st, F, C);
 }
 template <class T>
 void launch_prolong_add(const Level<T>& C, const Level<T>& F, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong_add<T>, grid_for((long)F.nx * F.ny * F.nz), dim3(BLOCK), 0, st, C, F);
+  const Geo q = geo3(F.nx, F.ny, F.nz);
+  hipLaunchKernelGGL(k_prolong_add<T>, q.g, q.b, 0, st, C, F);
 }
 template <class T>
 void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarsen<T>, grid_for((long)C.nx * C.ny * C.nz), dim3(BLOCK), 0, st, F, C);
+  const Geo q = geo3(C.nx, C.ny, C.nz);
+  hipLaunchKernelGGL(k_coarsen<T>, q.g, q.b, 0, st, F, C);
 }
 void launch_fold_energy(int N, double* U, double* eh, hipStream_t st) {
   hipLaunchKernelGGL(k_fold_energy, grid_for(N), dim3(BLOCK), 0, st, N, U, eh);
@@ -778,7 +854,8 @@ void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st) {
 #define RT_INST(T)                                                                   \
   template void launch_fill<T>(long, T*, T, hipStream_t);                            \
   template void launch_rbgs<T>(const Level<T>&, int, hipStream_t);                   \
-  template void launch_rbgs_first<T>(const Level<T>&, hipStream_t);                  \
+  template void launch_rbgs_first_pair<T>(const Level<T>&, hipStream_t);             \
+  template void launch_coarse_solve<T>(const Level<T>&, int, hipStream_t);           \
   template void launch_mg_residual<T>(const Level<T>&, hipStream_t);                 \
   template void launch_restrict<T>(const Level<T>&, const Level<T>&, hipStream_t);   \
   template void launch_prolong_add<T>(const Level<T>&, const Level<T>&, hipStream_t); \
