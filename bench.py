@@ -5,13 +5,17 @@ A step is one full implicit time step of the 256^3 periodic hydrogen problem
 (centred 5e48 photons/s source in a 13.2 kpc box, dt = 1e11 s, theta = 1):
 time-level set-up, Newton iterations with Schur elimination, MG-PCG and line
 search until the RMS residual is below 1e-6, then the energy fold.  Inputs
-stay resident in HBM; W warm-up steps run first, then K steps are timed, each
+stay resident in HBM; W warm-up steps run first (default 20: past the
+start-up transient of the 200-step trajectory), then K steps are timed, each
 from the state the previous one produced.
 
-Modes: plain (FP64 V-cycle) and mixed (FP32 V-cycle inside FP64 Newton/CG).
-The JSON line reports the headline mode in `value` and every mode in
-`modes`; `roofline` covers the kernel class with the largest share of the
-timed region, timed with HIP events on the library's stream; `cpu_baseline`
+Modes: plain (FP64 V-cycle, previous-state guess), mixed (FP32 V-cycle
+inside FP64 Newton/CG), learned and mixed+learned (the better, by initial
+residual, of the previous state and the convolutional network's guess; the
+network is trained first, untimed, on 200-step plain-method trajectories at
+128^3 with the same cell size and time step).  The JSON line reports the
+headline mode (mixed+learned) in `value` and every mode in `modes`;
+`roofline` covers the kernel class with the largest share of the timed region, timed with HIP events on the library's stream; `cpu_baseline`
 times the CPU FP64 oracle on a bounded sample of the same problem.
 """
 from __future__ import annotations
@@ -46,13 +50,60 @@ def rbgs_bytes(counts_per_vcycle, w):
     return first * 1.5 * w + regular * 5.0 * w
 
 
-def run_mode(mode, steps, warmup, n=256):
+def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None):
+    """Train the learned-guess network on plain-method trajectories."""
+    import numpy as np
+    import synth
+    from paper_0901_1110_amd.binding import RtNet
+    from paper_0901_1110_amd.driver import generate_trajectory, init_net_params, train_net
+
+    t0 = time.perf_counter()
+    base = synth.CFG_256.replace(n=n_train, mg_levels=4)
+    media = [base, base.replace(sigma_ln=1.0, nsources=4, centred=False, seed=100,
+                                logQ_range=(48.0, 48.7))]
+    trajs = []
+    for w in media:
+        ts = time.perf_counter()
+        trajs.append(generate_trajectory(w, steps))
+        st = trajs[-1]["stats"]
+        if log:
+            log("trajectory %s: %d steps in %.1f s, Newton its %d, CG its %d, max CG/Newton %.1f"
+                % (w.name + ("" if w.sigma_ln == 0 else "_lognormal"), steps,
+                   time.perf_counter() - ts, sum(s["newton_its"] for s in st),
+                   sum(s["cg_its_total"] for s in st),
+                   max(s["cg_its_total"] / max(1, s["newton_its"]) for s in st)))
+    t1 = time.perf_counter()
+    net = RtNet(1, (n_train,) * 3)
+    net.set_params(init_net_params(net.nin, net.nout, seed=0))
+    hist = train_net(net, trajs, epochs=epochs, lr=lr, seed=0, log=log)
+    t2 = time.perf_counter()
+    theta = net.get_params()
+    info_score = getattr(net, "best_score", None)
+    del trajs
+    info = dict(train_grid=n_train, trajectory_steps=steps, trajectories=len(media),
+                epochs=epochs, lr=lr, loss_first=hist[0], loss_last=hist[-1],
+                selected_guess_score=info_score,
+                trajectory_s=round(t1 - t0, 2), train_s=round(t2 - t1, 2))
+    out = os.path.join(ROOT, "gpurun_out")
+    if os.path.isdir(out):
+        np.save(os.path.join(out, "net_params.npy"), theta)
+    return theta, info
+
+
+def run_mode(mode, steps, warmup, n=256, theta=None):
     import torch
     import synth
-    from paper_0901_1110_amd.driver import Simulation
+    from paper_0901_1110_amd.binding import RtNet
+    from paper_0901_1110_amd.driver import LearnedSimulation, Simulation
 
-    w = synth.CFG_256.replace(n=n, mg_fp32=1 if mode == "mixed" else 0)
-    sim = Simulation(w)
+    w = synth.CFG_256.replace(n=n, mg_fp32=1 if mode.startswith("mixed") else 0)
+    if mode.endswith("learned"):
+        net = RtNet(1, (n, n, n))
+        net.set_params(theta)
+        sim = LearnedSimulation(w, net)
+        warmup = max(warmup, 2)
+    else:
+        sim = Simulation(w)
     for _ in range(warmup):
         st = sim.step()
         if st["status"] != 0:
@@ -83,9 +134,12 @@ def run_mode(mode, steps, warmup, n=256):
     res = dict(mode=mode, cells=N, steps=steps, wall_s=wall, event_ms=gpu_ms,
                value=N * steps / wall, ms_per_step=1e3 * wall / steps,
                newton_its=newton, cg_its=cg, vcycles=vc,
-               cell_newton_its_per_s=N * newton / wall, kernels=kt)
+               cell_newton_its_per_s=N * newton / wall, kernels=kt,
+               network_guess_used=sum(s["used_alt_guess"] for s in stats),
+               fnorm0_mean=sum(min(s["fnorm_guess"], s["fnorm_alt"]) if s["fnorm_alt"] >= 0
+                               else s["fnorm_guess"] for s in stats) / len(stats))
     # roofline of the dominant kernel class
-    wbytes = 4.0 if mode == "mixed" else 8.0
+    wbytes = 4.0 if mode.startswith("mixed") else 8.0
     p = sim.grid.params
     per_vc = (1, 2 * p.mg_pre - 1 + 2 * p.mg_post) if p.mg_pre > 0 else (0, 2 * p.mg_post)
     dom = max(kt, key=lambda k: kt[k][1])
@@ -135,9 +189,11 @@ def cpu_baseline(n=64, budget_s=30.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--modes", default="plain,mixed")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--modes", default="plain,mixed,learned,mixed+learned")
+    ap.add_argument("--train-epochs", type=int, default=8)
+    ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -147,29 +203,39 @@ def main():
         sys.exit(2)
     modes = [m for m in args.modes.split(",") if m]
     results = {}
+    theta, train_info = None, None
+    if any(m.endswith("learned") for m in modes):
+        print("# training the learned guess (untimed)", file=sys.stderr, flush=True)
+        theta, train_info = train_guess(steps=args.train_steps, epochs=args.train_epochs,
+                                        log=lambda s: print("#   " + s, file=sys.stderr, flush=True))
+        print("# trained: %s" % train_info, file=sys.stderr, flush=True)
     for mode in modes:
         print("# mode %s: %d warm-up + %d timed steps at %d^3" % (mode, args.warmup, args.steps, args.n),
               file=sys.stderr, flush=True)
-        results[mode] = run_mode(mode, args.steps, args.warmup, args.n)
+        results[mode] = run_mode(mode, args.steps, args.warmup, args.n, theta)
         print("# %s: %.3e cell-updates/s, %.1f ms/step" % (mode, results[mode]["value"],
                                                           results[mode]["ms_per_step"]),
               file=sys.stderr, flush=True)
-    head = "mixed" if "mixed" in results else modes[0]
+    head = next((m for m in ("mixed+learned", "mixed", "learned") if m in results), modes[0])
     H = results[head]
     line = {
         "metric": METRIC, "value": H["value"], "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": H["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+f32" if head == "mixed" else "f64", "data": "synthetic",
+        "dtype": "f64+f32" if head.startswith("mixed") else "f64",
+        "data": "synthetic",
         "config": {"workload": "hii_256: %d^3 periodic hydrogen, centred 5e48 photons/s source, "
                                "13.2 kpc box, dt=1e11 s, theta=1, Newton tol 1e-6, PCG rtol 1e-8, "
                                "5-level V-cycle RB-GS 2+2" % args.n,
                    "mode": head, "grid": args.n, "parallelism": "single GPU"},
         "roofline": H.get("roofline"),
         "modes": {k: {kk: v[kk] for kk in ("value", "ms_per_step", "newton_its", "cg_its",
-                                           "vcycles", "cell_newton_its_per_s")}
+                                           "vcycles", "cell_newton_its_per_s",
+                                           "network_guess_used", "fnorm0_mean")}
                   for k, v in results.items()},
     }
+    if train_info:
+        line["learned_training"] = train_info
     if "plain" in results and head != "plain":
         line["speedup_vs_plain"] = H["value"] / results["plain"]["value"]
     if not args.no_cpu_baseline:

@@ -215,6 +215,47 @@ int rt_timing(rt_grid* g, int32_t enable, rt_kernel_timing* out);
 int rt_spectrum_constants(int32_t grey, double T_B, double* K_gamma3, double* K_kappa3,
                           double* K_heat3, double* hnu_mean);
 
+/* ---- learned Newton initial guess (beside the paper's method) ------------
+ * A 4-layer 3x3x3 periodic convolution network (channels nin -> 16 -> 16 ->
+ * 16 -> nout, LeakyReLU 0.01 between layers) maps two time levels to a guess
+ * of the next one; BF16 weights and activations, FP32 accumulation (MFMA).
+ * Features per cell, for levels n and n-1: log10(E/u_E), e/u_e, logit(x_i)/10
+ * (x clipped to [1e-12, 1 - 1e-12], E floored at 1e-10 u_E), plus
+ * log10(n_H / nH_mean): nin = 2 (nspecies + 2) + 1.  Outputs (nout =
+ * nspecies + 2): a correction to the linear extrapolation 2 t^n - t^(n-1) of
+ * t = (log10 E/u_E, e/u_e, logit x_i / 10); the guess is the inverse
+ * transform of their sum, with e_c = e - e_h.  Parameters (host FP32, flat): per
+ * layer the weights in (offset, co, ci) order, offset o = (dx,dy,dz) =
+ * (o/9 - 1, (o/3)%3 - 1, o%3 - 1), then the co biases.  Requires nz % 16 == 0
+ * and nx, ny >= 3.  The caller owns the device workspace. */
+typedef struct rt_net rt_net;
+int rt_net_workspace_bytes(int32_t nspecies, int32_t nx, int32_t ny, int32_t nz, uint64_t* bytes);
+int rt_net_create(int32_t nspecies, int32_t nx, int32_t ny, int32_t nz, void* d_ws,
+                  uint64_t ws_bytes, void* hip_stream, rt_net** out);
+int rt_net_destroy(rt_net* n);
+const char* rt_net_last_error(const rt_net* n);
+int rt_net_num_params(const rt_net* n);
+/* Set (and reset the Adam state) / read the FP32 master parameters. */
+int rt_net_set_params(rt_net* n, const float* h_theta, int32_t count);
+int rt_net_get_params(rt_net* n, float* h_theta, int32_t count);
+/* Guess d_Uguess [nv][N] from levels n (d_Un, total specific energy d_en) and
+ * n-1 (d_Unm1, d_enm1); d_eh is the e_h of the coming step (for e_c). */
+int rt_net_forward(rt_net* n, const double* d_Un, const double* d_Unm1, const double* d_en,
+                   const double* d_enm1, const double* d_nH, double nH_mean, double u_e,
+                   double u_E, const double* d_eh, double* d_Uguess);
+/* Copies of the last network output [nout][N] (FP32) and of the BF16 input
+ * features widened to FP32 [16][N] (either pointer may be NULL). */
+int rt_net_get_output(rt_net* n, float* d_out, float* d_feat);
+/* One training sample (levels n-1, n with converged level n+1 as target):
+ * mean squared error (radiation channel weighted per cell by E^n/u_E over its
+ * box mean, capped at 100; other channels by 1) to *h_loss, gradient to h_grad
+ * (host, may be NULL); lr > 0 then applies one Adam step (beta 0.9/0.999,
+ * eps 1e-8) on the gradient clipped to global norm 1. */
+int rt_net_train_step(rt_net* n, const double* d_Un, const double* d_Unm1, const double* d_en,
+                      const double* d_enm1, const double* d_nH, double nH_mean, double u_e,
+                      double u_E, const double* d_Unp1, const double* d_enp1, float lr,
+                      float* h_loss, float* h_grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,6 +101,17 @@ SIGNATURES = {
     "rt_fold_energy": [_P, _P, _P],
     "rt_timing": [_P, _I, ctypes.POINTER(RtKernelTiming)],
     "rt_spectrum_constants": [_I, _D, _P, _P, _P, ctypes.POINTER(_D)],
+    "rt_net_workspace_bytes": [_I, _I, _I, _I, ctypes.POINTER(ctypes.c_uint64)],
+    "rt_net_create": [_I, _I, _I, _I, _P, ctypes.c_uint64, _P, ctypes.POINTER(_P)],
+    "rt_net_destroy": [_P],
+    "rt_net_last_error": [_P],
+    "rt_net_num_params": [_P],
+    "rt_net_set_params": [_P, _P, _I],
+    "rt_net_get_params": [_P, _P, _I],
+    "rt_net_forward": [_P, _P, _P, _P, _P, _P, _D, _D, _D, _P, _P],
+    "rt_net_get_output": [_P, _P, _P],
+    "rt_net_train_step": [_P, _P, _P, _P, _P, _P, _D, _D, _D, _P, _P, ctypes.c_float,
+                          ctypes.POINTER(ctypes.c_float), _P],
 }
 
 
@@ -113,7 +124,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name, args in SIGNATURES.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = ctypes.c_char_p if name == "rt_last_error" else ctypes.c_int
+        fn.restype = ctypes.c_char_p if name.endswith("last_error") else ctypes.c_int
     return lib
 
 
@@ -327,3 +338,80 @@ class RtGrid:
         if code == RT_EINVAL or code == RT_EDEVICE or (raise_on_fail and code != RT_OK):
             self._check(code, "rt_newton_step")
         return st.as_dict()
+
+
+class RtNet:
+    """Owner of an rt_net (learned initial guess) and its device workspace."""
+
+    def __init__(self, nspecies, shape, device="cuda", stream=None):
+        L = lib()
+        nx, ny, nz = shape
+        nbytes = ctypes.c_uint64()
+        st = L.rt_net_workspace_bytes(nspecies, nx, ny, nz, ctypes.byref(nbytes))
+        if st != RT_OK:
+            raise RtError(st, "rt_net_workspace_bytes: unsupported shape %s" % (shape,))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        st = L.rt_net_create(nspecies, nx, ny, nz, _ptr(self.ws), self.ws.numel(),
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != RT_OK:
+            raise RtError(st, "rt_net_create")
+        self.h = h
+        self.ns = nspecies
+        self.shape = tuple(shape)
+        self.N = nx * ny * nz
+        self.nin = 2 * (nspecies + 2) + 1
+        self.nout = nspecies + 2
+        self.P = L.rt_net_num_params(h)
+
+    def _check(self, st, name):
+        if st != RT_OK:
+            raise RtError(st, "%s: %s" % (name, lib().rt_net_last_error(self.h).decode()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rt_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        import numpy as np
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        self._check(lib().rt_net_set_params(self.h, t.ctypes.data_as(ctypes.c_void_p), int(t.size)),
+                    "rt_net_set_params")
+
+    def get_params(self):
+        import numpy as np
+        t = np.empty(self.P, dtype=np.float32)
+        self._check(lib().rt_net_get_params(self.h, t.ctypes.data_as(ctypes.c_void_p), self.P),
+                    "rt_net_get_params")
+        return t
+
+    def forward(self, Un, Unm1, en, enm1, nH, nH_mean, u_e, u_E, eh, Uguess):
+        self._check(lib().rt_net_forward(self.h, _ptr(Un), _ptr(Unm1), _ptr(en), _ptr(enm1),
+                                         _ptr(nH), float(nH_mean), float(u_e), float(u_E),
+                                         _ptr(eh), _ptr(Uguess)), "rt_net_forward")
+        return Uguess
+
+    def get_output(self):
+        out = torch.empty((self.nout,) + self.shape, dtype=torch.float32, device=self.device)
+        feat = torch.empty((16,) + self.shape, dtype=torch.float32, device=self.device)
+        self._check(lib().rt_net_get_output(self.h, _ptr(out), _ptr(feat)), "rt_net_get_output")
+        return out, feat
+
+    def train_step(self, Un, Unm1, en, enm1, nH, nH_mean, u_e, u_E, Unp1, enp1, lr, want_grad=False):
+        import numpy as np
+        loss = ctypes.c_float()
+        grad = np.empty(self.P, dtype=np.float32) if want_grad else None
+        self._check(lib().rt_net_train_step(
+            self.h, _ptr(Un), _ptr(Unm1), _ptr(en), _ptr(enm1), _ptr(nH), float(nH_mean),
+            float(u_e), float(u_E), _ptr(Unp1), _ptr(enp1), float(lr), ctypes.byref(loss),
+            grad.ctypes.data_as(ctypes.c_void_p) if want_grad else None), "rt_net_train_step")
+        return (loss.value, grad) if want_grad else loss.value

@@ -201,12 +201,14 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
         L.cz = c.take<double>(n); L.x = c.take<double>(n); L.b = c.take<double>(n);
         L.r = c.take<double>(n);
       }
+      L.x2 = c.take<double>(n);
       w->L64.push_back(L);
     } else {
       Level<float> L{nx, ny, nz};
       L.diag = c.take<float>(n); L.cx = c.take<float>(n); L.cy = c.take<float>(n);
       L.cz = c.take<float>(n); L.x = c.take<float>(n); L.b = c.take<float>(n);
       L.r = c.take<float>(n);
+      L.x2 = c.take<float>(n);
       w->L32.push_back(L);
     }
     nx /= 2; ny /= 2; nz /= 2;
@@ -231,8 +233,38 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l) {
     return;
   }
   const int pre = coarsest ? p.mg_coarse_sweeps : p.mg_pre;
+  const int post = coarsest ? p.mg_coarse_sweeps : p.mg_post;
+  const bool fused = pre > 0 && pair_fits(L.nx, L.ny, L.nz);
+  if (fused) {
+    // (red, black) pairs from x = 0, then (black, red) pairs after the
+    // coarse-grid correction, ping-ponging between x and x2 so that the
+    // result ends in L.x
+    T* out = L.x;
+    T* alt = L.x2;
+    const int swaps = (pre - 1) + post;
+    T* cur = (swaps % 2 == 0) ? out : alt;
+    T* oth = (cur == out) ? alt : out;
+    TK(g, kc, launch_rbgs_first_pair<T>(L, cur, st));
+    for (int s = 1; s < pre; ++s) {
+      TK(g, kc, launch_rbgs_pair<T>(L, cur, oth, 0, st));
+      std::swap(cur, oth);
+    }
+    if (!coarsest) {
+      Level<T> Lc = L;
+      Lc.x = cur;
+      TK(g, RT_K_MG_TRANSFER, launch_mg_residual<T>(Lc, st));
+      TK(g, RT_K_MG_TRANSFER, launch_restrict<T>(Lc, Ls[l + 1], st));
+      vcycle<T>(g, Ls, l + 1);
+      TK(g, RT_K_MG_TRANSFER, launch_prolong_add<T>(Ls[l + 1], Lc, st));
+    }
+    for (int s = 0; s < post; ++s) {
+      TK(g, kc, launch_rbgs_pair<T>(L, cur, oth, 1, st));
+      std::swap(cur, oth);
+    }
+    return;
+  }
   if (pre > 0) {
-    TK(g, kc, launch_rbgs_first_pair<T>(L, st));   // (red, black) from x = 0
+    TK(g, kc, launch_rbgs_first_pair<T>(L, L.x, st));   // (red, black) from x = 0
     for (int s = 1; s < pre; ++s) {
       TK(g, kc, launch_rbgs<T>(L, 0, st));
       TK(g, kc, launch_rbgs<T>(L, 1, st));
@@ -246,7 +278,6 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l) {
     vcycle<T>(g, Ls, l + 1);
     TK(g, RT_K_MG_TRANSFER, launch_prolong_add<T>(Ls[l + 1], L, st));
   }
-  const int post = coarsest ? p.mg_coarse_sweeps : p.mg_post;
   for (int s = 0; s < post; ++s) {
     TK(g, kc, launch_rbgs<T>(L, 1, st));
     TK(g, kc, launch_rbgs<T>(L, 0, st));

@@ -68,10 +68,14 @@ struct Level {
   int nx, ny, nz;
   T *diag, *cx, *cy, *cz;   // operator
   T *x, *b, *r;             // solution, right side, residual scratch
+  T* x2;                    // second solution buffer for the fused red-black pairs
 };
 template <class T> void launch_fill(long n, T* x, T v, hipStream_t st);
 template <class T> void launch_rbgs(const Level<T>& L, int colour, hipStream_t st);
-template <class T> void launch_rbgs_first_pair(const Level<T>& L, hipStream_t st);
+template <class T> void launch_rbgs_first_pair(const Level<T>& L, T* xo, hipStream_t st);
+template <class T>
+void launch_rbgs_pair(const Level<T>& L, const T* xin, T* xout, int c0, hipStream_t st);
+bool pair_fits(int nx, int ny, int nz);   // the fused-pair tiling divides this level
 template <class T> void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st);
 int stencil_blocks(int nx, int ny, int nz);   // blocks (= partial sums) of a 3-D stencil launch
 constexpr int COARSE_SOLVE_MAX = 8192;        // coarsest levels up to this size: one workgroup

@@ -491,6 +491,8 @@ __global__ __launch_bounds__(BLOCK) void k_fill(long n, T* __restrict__ x, T v) 
   if (i < n) x[i] = v;
 }
 
+__device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
 // one colour of a red-black Gauss-Seidel sweep (colour = (i+j+k) mod 2);
 // the launch's x extent is nz/2: thread kk owns the kk-th cell of the colour
 // in its z-row (nz even)
@@ -518,12 +520,12 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Level<T> L, int colour) {
 // black cells use their red neighbours' b/diag (the values the red half-sweep
 // would have produced)
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_rbgs_first_pair(Level<T> L) {
+__global__ __launch_bounds__(BLOCK) void k_rbgs_first_pair(Level<T> L, T* __restrict__ xo) {
   const C3 c = coord3(L.ny, L.nz);
   if (!c.ok) return;
   const int idx = (c.i * L.ny + c.j) * L.nz + c.k;
   if (((c.i + c.j + c.k) & 1) == 0) {
-    L.x[idx] = L.b[idx] / L.diag[idx];
+    xo[idx] = L.b[idx] / L.diag[idx];
     return;
   }
   const Nb nb = nbrs(c.i, c.j, c.k, L.nx, L.ny, L.nz);
@@ -533,7 +535,7 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs_first_pair(Level<T> L) {
   s = s + L.cx[idx] * (b[nb.xp] / d[nb.xp]) + L.cx[nb.xm] * (b[nb.xm] / d[nb.xm]);
   s = s + L.cy[idx] * (b[nb.yp] / d[nb.yp]) + L.cy[nb.ym] * (b[nb.ym] / d[nb.ym]);
   s = s + L.cz[idx] * (b[nb.zp] / d[nb.zp]) + L.cz[nb.zm] * (b[nb.zm] / d[nb.zm]);
-  L.x[idx] = s / d[idx];
+  xo[idx] = s / d[idx];
 }
 
 // coarsest-level solve in one workgroup: `sweeps` x (red, black) from x = 0,
@@ -562,6 +564,88 @@ __global__ __launch_bounds__(1024) void k_coarse_solve(Level<T> L, int sweeps) {
   }
 }
 
+// One fused (c0, c1) red-black pair -- a c0 half-sweep followed by a c1
+// half-sweep -- in a single pass over the level.  A block owns a TJ x TK
+// column of rows and marches through PI x-planes, keeping four planes of the
+// input x (halo 2 in y and z) and three planes of new c0 values (halo 1) in
+// LDS; new c1 values need the new c0 values of their six neighbours, which
+// the block computes itself on its halo ring (redundantly with the
+// neighbouring block).  x is double-buffered (xin -> xout), so no block reads
+// a value another block has already overwritten, and the arithmetic is that
+// of the two half-sweeps, term for term.
+template <class T, int TK, int TJ, int PI>
+__global__ __launch_bounds__(256) void k_rbgs_pair(Level<T> L, const T* __restrict__ xin,
+                                                   T* __restrict__ xout, int c0) {
+  constexpr int RK = TK + 4, RJ = TJ + 4;   // input window (halo 2)
+  constexpr int QK = TK + 2, QJ = TJ + 2;   // new c0 values (halo 1)
+  __shared__ T xs[4][RJ][RK];
+  __shared__ T cs[3][QJ][QK];
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const int k0 = blockIdx.x * TK, j0 = blockIdx.y * TJ, i0 = blockIdx.z * PI;
+  const int tid = threadIdx.x;
+  auto gidx = [&](int i, int j, int k) {
+    return (wrap(i, nx) * ny + wrap(j, ny)) * nz + wrap(k, nz);
+  };
+  auto slot = [](int i) { return (i + 8) & 3; };
+  auto cslot = [](int i) { return (i + 9) % 3; };
+  auto load_plane = [&](int i) {
+    const int sl = slot(i);
+    for (int t = tid; t < RJ * RK; t += 256) {
+      const int jj = t / RK, kk = t - jj * RK;
+      xs[sl][jj][kk] = xin[gidx(i, j0 + jj - 2, k0 + kk - 2)];
+    }
+  };
+  // new c0 values of plane i on the halo-1 region
+  auto c0_plane = [&](int i) {
+    const int sm = slot(i - 1), s0 = slot(i), sp = slot(i + 1), q = cslot(i);
+    for (int t = tid; t < QJ * (QK / 2); t += 256) {
+      const int jj = t / (QK / 2);
+      const int j = j0 + jj - 1;
+      // first region column kk whose cell has colour c0
+      const int par = (c0 - i - j - (k0 - 1)) & 1;
+      const int kk = 2 * (t - jj * (QK / 2)) + par;
+      const int k = k0 + kk - 1;
+      const int g = gidx(i, j, k);
+      T sum = L.b[g];
+      sum = sum + L.cx[g] * xs[sp][jj + 1][kk + 1] + L.cx[gidx(i - 1, j, k)] * xs[sm][jj + 1][kk + 1];
+      sum = sum + L.cy[g] * xs[s0][jj + 2][kk + 1] + L.cy[gidx(i, j - 1, k)] * xs[s0][jj][kk + 1];
+      sum = sum + L.cz[g] * xs[s0][jj + 1][kk + 2] + L.cz[gidx(i, j, k - 1)] * xs[s0][jj + 1][kk];
+      cs[q][jj][kk] = sum / L.diag[g];
+    }
+  };
+  load_plane(i0 - 2);
+  load_plane(i0 - 1);
+  load_plane(i0);
+  load_plane(i0 + 1);
+  __syncthreads();
+  c0_plane(i0 - 1);
+  c0_plane(i0);
+  // the first load of the loop overwrites the slot of plane i0 - 2, which
+  // c0_plane(i0 - 1) reads: every thread must be past it
+  __syncthreads();
+  const int tj = tid / TK, tk = tid - tj * TK;
+  for (int i = i0; i < i0 + PI; ++i) {
+    load_plane(i + 2);
+    __syncthreads();
+    c0_plane(i + 1);
+    __syncthreads();
+    const int j = j0 + tj, k = k0 + tk;
+    const int g = (i * ny + j) * nz + k;
+    const int qm = cslot(i - 1), q0 = cslot(i), qp = cslot(i + 1);
+    T val;
+    if (((i + j + k) & 1) == c0) {
+      val = cs[q0][tj + 1][tk + 1];
+    } else {
+      T sum = L.b[g];
+      sum = sum + L.cx[g] * cs[qp][tj + 1][tk + 1] + L.cx[gidx(i - 1, j, k)] * cs[qm][tj + 1][tk + 1];
+      sum = sum + L.cy[g] * cs[q0][tj + 2][tk + 1] + L.cy[gidx(i, j - 1, k)] * cs[q0][tj][tk + 1];
+      sum = sum + L.cz[g] * cs[q0][tj + 1][tk + 2] + L.cz[gidx(i, j, k - 1)] * cs[q0][tj + 1][tk];
+      val = sum / L.diag[g];
+    }
+    xout[g] = val;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L) {
   const C3 c = coord3(L.ny, L.nz);
@@ -575,8 +659,6 @@ __global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L) {
   y = y - L.cz[idx] * x[nb.zp] - L.cz[nb.zm] * x[nb.zm];
   L.r[idx] = L.b[idx] - y;
 }
-
-__device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // b_coarse = R r_fine with R = P^T / 8: weights (1,3,3,1)/8 per axis over
 // fine cells 2I-1 .. 2I+2
@@ -813,9 +895,18 @@ void launch_rbgs(const Level<T>& L, int colour, hipStream_t st) {
   hipLaunchKernelGGL(k_rbgs<T>, q.g, q.b, 0, st, L, colour);
 }
 template <class T>
-void launch_rbgs_first_pair(const Level<T>& L, hipStream_t st) {
+void launch_rbgs_first_pair(const Level<T>& L, T* xo, hipStream_t st) {
   const Geo q = geo3(L.nx, L.ny, L.nz);
-  hipLaunchKernelGGL(k_rbgs_first_pair<T>, q.g, q.b, 0, st, L);
+  hipLaunchKernelGGL(k_rbgs_first_pair<T>, q.g, q.b, 0, st, L, xo);
+}
+constexpr int PAIR_TK = 32, PAIR_TJ = 8, PAIR_PI = 16;
+bool pair_fits(int nx, int ny, int nz) {
+  return nz % PAIR_TK == 0 && ny % PAIR_TJ == 0 && nx % PAIR_PI == 0;
+}
+template <class T>
+void launch_rbgs_pair(const Level<T>& L, const T* xin, T* xout, int c0, hipStream_t st) {
+  const dim3 g(L.nz / PAIR_TK, L.ny / PAIR_TJ, L.nx / PAIR_PI);
+  hipLaunchKernelGGL((k_rbgs_pair<T, PAIR_TK, PAIR_TJ, PAIR_PI>), g, dim3(256), 0, st, L, xin, xout, c0);
 }
 template <class T>
 void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st) {
@@ -854,7 +945,8 @@ void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st) {
 #define RT_INST(T)                                                                   \
   template void launch_fill<T>(long, T*, T, hipStream_t);                            \
   template void launch_rbgs<T>(const Level<T>&, int, hipStream_t);                   \
-  template void launch_rbgs_first_pair<T>(const Level<T>&, hipStream_t);             \
+  template void launch_rbgs_first_pair<T>(const Level<T>&, T*, hipStream_t);         \
+  template void launch_rbgs_pair<T>(const Level<T>&, const T*, T*, int, hipStream_t); \
   template void launch_coarse_solve<T>(const Level<T>&, int, hipStream_t);           \
   template void launch_mg_residual<T>(const Level<T>&, hipStream_t);                 \
   template void launch_restrict<T>(const Level<T>&, const Level<T>&, hipStream_t);   \

@@ -1,0 +1,178 @@
+"""Learned initial guess on the GPU: BF16-MFMA network against the FP64
+reference network of the oracle, training, and the measured gain.
+
+Parity uses the same BF16-rounded weights and the GPU's BF16 input features
+on both sides; the GPU also rounds hidden activations and back-propagated
+gradients to BF16 (FP32 accumulation), so outputs and gradients agree to a
+normwise 2e-2 (BF16 unit roundoff 3.9e-3, four layers, K <= 432).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import conv as C
+from paper_0901_1110_amd.binding import RtNet
+from paper_0901_1110_amd.driver import (LearnedSimulation, Simulation, generate_trajectory,
+                                        init_net_params, train_net)
+from tests.gpu_cases import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(a):
+    """Round float32 values to bfloat16 (nearest even), returned as float64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def random_levels(ns, n, seed):
+    rng = np.random.default_rng(seed)
+    Un, nH, eh = synth.random_physical_state(n, ns, rng)
+    Unm1, _, ehm1 = synth.random_physical_state(n, ns, rng)
+    Unp1, _, ehp1 = synth.random_physical_state(n, ns, rng)
+    return dict(Un=Un, Unm1=Unm1, Unp1=Unp1, en=eh, enm1=ehm1, enp1=ehp1, nH=nH)
+
+
+def weights_bf16(theta, nin, nout):
+    """The network as the GPU holds it: BF16 weights, FP32 biases."""
+    out, p = [], 0
+    th = theta.astype(np.float64).copy()
+    for ci, co in C.layer_shapes(nin, nout):
+        nW = 27 * ci * co
+        th[p:p + nW] = bf16_round(theta[p:p + nW])
+        th[p + nW:p + nW + co] = theta[p + nW:p + nW + co].astype(np.float32)
+        p += nW + co
+    return th
+
+
+@pytest.mark.parametrize("ns", [1, 3])
+def test_forward_and_decode_parity(ns):
+    n = 16
+    L = random_levels(ns, n, 10 + ns)
+    u_e, u_E = synth.E_GAS_1E4K_X09999, 1e-20
+    net = RtNet(ns, (n, n, n))
+    theta = C.init_params(net.nin, net.nout, seed=3, last_scale=0.5).astype(np.float32)
+    # a non-trivial last layer so that outputs are O(1)
+    net.set_params(theta)
+    Ug = torch.empty((ns + 2, n, n, n), dtype=torch.float64, device="cuda")
+    d = {k: dev(v) for k, v in L.items()}
+    nH_mean = float(L["nH"].mean())
+    net.forward(d["Un"], d["Unm1"], d["en"], d["enm1"], d["nH"], nH_mean, u_e, u_E, d["en"], Ug)
+    out, feat = [host(t).astype(np.float64) for t in net.get_output()]
+    # features: the oracle's definition, to one BF16 rounding
+    f_o = C.features(L["Un"], L["Unm1"], L["en"], L["enm1"], L["nH"], u_e, u_E, ns)
+    nin = net.nin
+    assert np.all(np.abs(feat[:nin] - f_o) <= 2 ** -7 * np.abs(f_o) + 1e-30)
+    assert np.all(feat[nin:] == 0)
+    # forward on identical BF16 inputs and weights
+    th = weights_bf16(theta, net.nin, net.nout)
+    out_o, _ = C.forward(th, feat[:nin], net.nin, net.nout)
+    err = np.linalg.norm(out - out_o) / np.linalg.norm(out_o)
+    assert err <= 2e-2, err
+    # decode of the GPU output
+    U_o = C.decode(out, L["Un"], L["Unm1"], L["en"], L["enm1"], L["en"], u_e, u_E, ns)
+    Ug = host(Ug)
+    for v in range(ns + 2):
+        scale = np.max(np.abs(U_o[v])) if v else u_e
+        assert np.max(np.abs(Ug[v] - U_o[v])) <= 1e-9 * scale, v
+
+
+@pytest.mark.parametrize("ns", [1, 3])
+def test_gradient_parity(ns):
+    n = 16
+    L = random_levels(ns, n, 20 + ns)
+    u_e, u_E = synth.E_GAS_1E4K_X09999, 1e-20
+    net = RtNet(ns, (n, n, n))
+    theta = C.init_params(net.nin, net.nout, seed=5, last_scale=0.5).astype(np.float32)
+    net.set_params(theta)
+    d = {k: dev(v) for k, v in L.items()}
+    nH_mean = float(L["nH"].mean())
+    loss, grad = net.train_step(d["Un"], d["Unm1"], d["en"], d["enm1"], d["nH"], nH_mean, u_e,
+                                u_E, d["Unp1"], d["enp1"], 0.0, want_grad=True)
+    _, feat = [host(t).astype(np.float64) for t in net.get_output()]
+    target = C.target(L["Unp1"], L["enp1"], L["Un"], L["Unm1"], L["en"], L["enm1"], u_e, u_E, ns)
+    th = weights_bf16(theta, net.nin, net.nout)
+    loss_o, grad_o = C.loss_and_grad(th, feat[:net.nin], target.astype(np.float32).astype(np.float64),
+                                     net.nin, net.nout, C.loss_weights(L["Un"], u_E, net.nout))
+    assert abs(loss / loss_o - 1) <= 2e-2, (loss, loss_o)
+    p = 0
+    for li, (ci, co) in enumerate(C.layer_shapes(net.nin, net.nout)):
+        nW = 27 * ci * co
+        for sl in (slice(p, p + nW), slice(p + nW, p + nW + co)):
+            g, go = grad[sl].astype(np.float64), grad_o[sl]
+            err = np.linalg.norm(g - go) / np.linalg.norm(go)
+            assert err <= 2e-2, (li, err)
+        p += nW + co
+    # the same call with lr = 0 leaves the parameters unchanged
+    assert np.array_equal(net.get_params(), theta)
+
+
+def test_training_reduces_loss():
+    w = synth.CFG_256.replace(n=32, mg_levels=3)
+    T = generate_trajectory(w, 12)
+    net = RtNet(1, (32, 32, 32))
+    net.set_params(init_net_params(net.nin, net.nout, seed=0))
+    hist = train_net(net, [T], epochs=6, lr=3e-4, seed=0, select=False)
+    assert min(hist[1:]) < 0.7 * hist[0], hist
+
+
+def test_learned_guess_gain():
+    """Train on one medium, run a held-out medium: report what the network
+    gains (Newton iterations, initial residual, fallback rate); every step
+    still meets the unchanged FP64 tolerance."""
+    n = 64
+    train_w = synth.CFG_256.replace(n=n, mg_levels=4)
+    held_w = synth.CFG_256.replace(n=n, mg_levels=4, sigma_ln=1.0, nsources=4, centred=False,
+                                   seed=200, Q=0.0, logQ_range=(48.0, 48.7))
+    trajs = [generate_trajectory(train_w, 40),
+             generate_trajectory(train_w.replace(sigma_ln=1.0, nsources=4, centred=False,
+                                                 seed=101, logQ_range=(48.0, 48.7)), 40)]
+    net = RtNet(1, (n, n, n))
+    net.set_params(init_net_params(net.nin, net.nout, seed=0))
+    hist = train_net(net, trajs, epochs=10, lr=3e-4, seed=0)
+    del trajs
+    steps = 16
+    plain = Simulation(held_w)
+    learned = LearnedSimulation(held_w, net)
+    # the untrained network: its zero last layer proposes the linear extrapolation
+    net0 = RtNet(1, (n, n, n))
+    net0.set_params(init_net_params(net0.nin, net0.nout, seed=0))
+    extrap = LearnedSimulation(held_w, net0)
+    rec = dict(plain=[], learned=[], extrapolation=[], loss=hist)
+    for k in range(steps):
+        sp = plain.step()
+        sl = learned.step()
+        sx = extrap.step()
+        rec["extrapolation"].append(dict(its=sx["newton_its"], used=sx["used_alt_guess"],
+                                         f_alt=sx["fnorm_alt"]))
+        extrap.advance()
+        assert sp["status"] == 0 and sl["status"] == 0
+        assert sp["fnorm_final"] < held_w.newton_tol and sl["fnorm_final"] < held_w.newton_tol
+        rec["plain"].append(dict(its=sp["newton_its"], f0=sp["fnorm_guess"]))
+        rec["learned"].append(dict(its=sl["newton_its"], f0=min(sl["fnorm_guess"],
+                                                                sl["fnorm_alt"] if sl["fnorm_alt"] >= 0
+                                                                else sl["fnorm_guess"]),
+                                   used=sl["used_alt_guess"]))
+        plain.advance()
+        learned.advance()
+    its_p = sum(r["its"] for r in rec["plain"][2:])
+    its_l = sum(r["its"] for r in rec["learned"][2:])
+    used = sum(r["used"] for r in rec["learned"][2:])
+    its_x = sum(r["its"] for r in rec["extrapolation"][2:])
+    rec["summary"] = dict(newton_its_plain=its_p, newton_its_learned=its_l,
+                          newton_its_extrapolation=its_x,
+                          steps_with_network_guess=used, steps_compared=steps - 2)
+    out = os.path.join(os.path.dirname(os.path.dirname(__file__)), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "learned_gain_test.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+    print("learned-guess gain:", rec["summary"])
+    # the fallback keeps the method at least as good: never worse initial residual
+    for rp, rl in zip(rec["plain"], rec["learned"]):
+        assert rl["f0"] <= rp["f0"] * (1 + 1e-12)
+    assert its_l <= its_p * 1.05 + 1
