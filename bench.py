@@ -81,7 +81,8 @@ def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None):
     info_score = getattr(net, "best_score", None)
     del trajs
     info = dict(train_grid=n_train, trajectory_steps=steps, trajectories=len(media),
-                epochs=epochs, lr=lr, loss_first=hist[0], loss_last=hist[-1],
+                epochs=epochs, lr=lr, loss_first=hist[0] if hist else None,
+                loss_last=hist[-1] if hist else None,
                 selected_guess_score=info_score,
                 trajectory_s=round(t1 - t0, 2), train_s=round(t2 - t1, 2))
     out = os.path.join(ROOT, "gpurun_out")
@@ -196,11 +197,23 @@ def main():
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("# copy calibration: 3 x %d bytes read + written" % (8 << 28), file=sys.stderr,
+              flush=True)
+        del a, b
     modes = [m for m in args.modes.split(",") if m]
     results = {}
     theta, train_info = None, None

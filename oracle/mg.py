@@ -7,7 +7,12 @@ reference to a library, so its definition here is a stated reading:
 Hierarchy (periodic, n_{l+1} = n_l / 2), built once per Schur matrix:
   local_l   = diag_l - sum over the 6 faces of c_l
   local_l+1 = mean of local_l over the 8 children
-  c^d_l+1   = (1/4) * mean of the 4 fine c^d on the coarse face (I, I + e_d)
+  c^d_l+1   = (1/4) * mean over the 4 fine columns crossing the coarse face
+              (I, I + e_d) of the series (weighted harmonic) coupling of the
+              three fine faces 2I, 2I+1, 2I+2 along d, weights 1/4, 1/2, 1/4:
+              the path between the two coarse centres crosses half of the
+              first segment, the whole middle one and half of the last;
+              equal fine couplings c give c/4 (rediscretization at 2h)
   diag_l+1  = local_l+1 + sum over the 6 faces of c_l+1
 Smoother: red-black Gauss-Seidel, colour (i + j + k) mod 2 (red = 0),
   x_P <- (b_P + sum_faces c_f x_nbr) / diag_P.
@@ -45,12 +50,17 @@ def coarsen(op):
         local_c = _pair_mean(local_c, ax)            # mean over the 8 children
     cc = []
     for d, c in enumerate(cs):
-        # fine + faces lying on the coarse + face have fine index 2I+1 along d
-        on_face = np.take(c, np.arange(1, c.shape[d], 2), axis=d)
+        n = c.shape[d]
+        ca = np.take(c, np.arange(0, n, 2), axis=d)              # face 2I
+        cb = np.take(c, np.arange(1, n, 2), axis=d)              # face 2I+1
+        cc_ = np.take(c, (np.arange(0, n, 2) + 2) % n, axis=d)   # face 2I+2
+        with np.errstate(divide="ignore"):
+            inv = 0.25 / ca + 0.5 / cb + 0.25 / cc_
+        series = np.where(np.isfinite(inv) & (inv > 0), 1.0 / np.where(inv > 0, inv, 1.0), 0.0)
         for ax in range(3):
             if ax != d:
-                on_face = _pair_mean(on_face, ax)    # mean of the 4 fine faces
-        cc.append(0.25 * on_face)
+                series = _pair_mean(series, ax)      # parallel: mean over the 4 columns
+        cc.append(0.25 * series)
     csum_c = sum(c + np.roll(c, 1, axis=d) for d, c in enumerate(cc))
     return (local_c + csum_c, cc[0], cc[1], cc[2])
 

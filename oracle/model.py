@@ -36,7 +36,7 @@ HNU_HEII = 54.4 * EV
 SIGMA_HI = 6.30e-18          # threshold cross sections (cm^2), readings
 SIGMA_HEI = 7.42e-18
 SIGMA_HEII = 1.575e-18
-KAPPA_FLOOR_CELLS = 1.0e-6   # face opacity floor: 1e-6 per proper cell width
+KAPPA_FLOOR_CELLS = 1.0e-3   # face opacity floor: 1e-3 per proper cell width
 E_FLOOR = 1.0e-300           # guards E_face in R = |dE| / E
 
 

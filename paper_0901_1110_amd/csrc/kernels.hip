@@ -712,8 +712,9 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_add(Level<T> C, Level<T> F) {
   F.x[idx] = F.x[idx] + (w0 * zI0 + w1 * zI1);
 }
 
-// coarse operator: mean local part over the 8 children; face couplings
-// (1/4) * mean of the 4 fine couplings on the coarse face; diag = local + sum
+// coarse operator: mean local part over the 8 children; face couplings from
+// the series (harmonic) coupling along the normal, mean over the 2x2 fine
+// columns, times 1/4; diag = local + sum
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_coarsen(Level<T> F, Level<T> C) {
   const C3 c = coord3(C.ny, C.nz);
@@ -734,17 +735,26 @@ __global__ __launch_bounds__(BLOCK) void k_coarsen(Level<T> F, Level<T> C) {
         local += F.diag[p] - cs;
       }
   local *= T(0.125);
-  // couplings on the + faces of coarse cell (I,J,K) and of its - neighbours
+  // couplings on the + faces of coarse cell (I,J,K) and of its - neighbours:
+  // per fine column crossing the coarse face, the series coupling of fine
+  // faces 2I0, 2I0+1, 2I0+2 along d (weights 1/4, 1/2, 1/4), then the mean
+  // over the 2x2 columns, times 1/4
   auto face = [&](const T* cf, int d, int i0, int j0, int k0) {
-    // fine + faces with index 2*I0+1 along d, 2x2 in the other directions
     T sum = T(0);
     for (int u = 0; u < 2; ++u)
       for (int v = 0; v < 2; ++v) {
-        int i = 2 * i0, j = 2 * j0, k = 2 * k0;
-        if (d == 0) { i += 1; j += u; k += v; }
-        if (d == 1) { j += 1; i += u; k += v; }
-        if (d == 2) { k += 1; i += u; j += v; }
-        sum += cf[fi(i, j, k)];
+        T inv = T(0);
+        bool zero = false;
+        for (int m = 0; m < 3; ++m) {
+          int i = 2 * i0, j = 2 * j0, k = 2 * k0;
+          if (d == 0) { i += m; j += u; k += v; }
+          if (d == 1) { j += m; i += u; k += v; }
+          if (d == 2) { k += m; i += u; j += v; }
+          const T cv = cf[fi(i, j, k)];
+          if (!(cv > T(0))) zero = true;
+          else inv += (m == 1 ? T(0.5) : T(0.25)) / cv;
+        }
+        sum += zero ? T(0) : T(1) / inv;
       }
     return T(0.0625) * sum;
   };

@@ -28,7 +28,7 @@ constexpr double M_HYD = 1.6735575e-24;
 constexpr double GAMMA_GAS = 5.0 / 3.0;
 constexpr double T_EXP = -0.7;
 constexpr double BETA_COOL = 0.75;
-constexpr double KAPPA_FLOOR = 1.0e-6;   // face opacity floor per proper cell width
+constexpr double KAPPA_FLOOR = 1.0e-3;   // face opacity floor per proper cell width
 constexpr double E_TINY = 1.0e-300;
 
 // Parameters copied to the device by value with every launch.

@@ -144,8 +144,7 @@ def train_net(net, trajectories, epochs, lr=3e-4, seed=0, log=None, select=True)
         if log:
             log(msg)
     if select:
-        theta = best[1]
-        net.set_params(theta)
+        net.set_params(best[1])
         net.best_score = best[0]
     return history
 
