@@ -27,7 +27,8 @@
  *   Memory   the caller allocates every device array, including the
  *            workspace sized by rt_workspace_bytes; the library never
  *            allocates or frees device memory.  It owns only the small host
- *            object behind rt_grid.  Pointers passed to rt_set_medium must
+ *            object behind rt_grid and a few pinned host bytes for scalar
+ *            read-back.  Pointers passed to rt_set_medium must
  *            stay valid while the grid uses them.
  *   Streams  every call enqueues on the hipStream_t given to rt_create_grid.
  *            Calls that return host scalars synchronise that stream; others
@@ -80,6 +81,11 @@ typedef struct rt_params {
   int32_t mg_coarse_sweeps; /* coarsest level: this many (red,black) then (black,red) */
   int32_t mg_fp32;          /* 1: V-cycle in FP32 (Newton, CG, local solves stay FP64) */
   int32_t max_sources;      /* capacity of the point-source list */
+  double  pcg_forcing;      /* inexact-Newton forcing factor (Sec. 3.2.1): when > 0
+                               the CG solve of Newton iteration k also stops once
+                               ||J S_k + f(U_k)||_2 = ||r||_2 <= pcg_forcing
+                               ||f(U_k)||_2 (the paper's delta_k = 1e-6 ||f||);
+                               0 keeps the relative test above alone */
 } rt_params;
 
 /* Scale factor a and adot/a at t^n (old) and t^{n+1} (new). */
@@ -209,6 +215,12 @@ typedef struct rt_kernel_timing {
  * starts collection; enable = 0 stops it, synchronises, and fills *out (may
  * be NULL).  Timing adds two event records per launch. */
 int rt_timing(rt_grid* g, int32_t enable, rt_kernel_timing* out);
+
+/* Restrict per-launch timing to the kernel classes whose bit (1 << class) is
+ * set in `mask` (the default is every class), so that a measurement of one
+ * class does not pay two event records on every other launch.  Takes effect
+ * for launches after the call; RT_EINVAL for a null grid. */
+int rt_timing_classes(rt_grid* g, uint32_t mask);
 
 /* Spectrum constants of Sec. 3.2.5 (Eq. 45) for a monochromatic 13.6 eV
  * (grey = 0) or a T_B blackbody (grey = 1) spectrum, by host quadrature. */

@@ -20,7 +20,8 @@ Transfers: cell-centred trilinear prolongation P (weights 3/4, 1/4 per axis)
   and restriction R = P^T / 8.
 V(l): x = 0; nu1 x (red, black); r = b - A x; V(l+1) on R r; x += P e;
   nu2 x (black, red).  Coarsest: k x (red, black) then k x (black, red).
-PCG: flexible (Polak-Ribiere) beta, x0 = 0, stop when ||r||_2 <= rtol ||b||_2.
+PCG: flexible (Polak-Ribiere) beta, x0 = 0, stop when ||r||_2 <= rtol ||b||_2
+  or, in a Newton step with a forcing factor, ||r||_2 <= forcing ||f(U_k)||_2.
 """
 from __future__ import annotations
 
@@ -143,8 +144,9 @@ def vcycle(b, ops, model, level=0, dtype=np.float64):
     return x
 
 
-def pcg(op, b, model, rtol=None, maxit=None, precond=True):
-    """Flexible PCG on S s = b; returns (s, iterations, ||r||/||b||)."""
+def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0):
+    """Flexible PCG on S s = b; stops at ||r||_2 <= max(rtol ||b||_2, atol).
+    Returns (s, iterations, ||r||/||b||)."""
     rtol = model.pcg_rtol if rtol is None else rtol
     maxit = model.pcg_maxit if maxit is None else maxit
     ops = hierarchy(op, model.mg_levels) if precond else None
@@ -171,7 +173,7 @@ def pcg(op, b, model, rtol=None, maxit=None, precond=True):
         r_old = r
         r = r - alpha * q
         rn = np.sqrt(np.sum(r * r))
-        if rn <= rtol * bn:
+        if rn <= max(rtol * bn, atol):
             return x, k, rn / bn
         z = V(r)
         rho_new = np.sum(z * r)

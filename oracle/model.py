@@ -67,6 +67,7 @@ class Model:
     mg_post: int = 2
     mg_coarse_sweeps: int = 8
     mg_fp32: int = 0
+    pcg_forcing: float = 0.0 # inexact-Newton forcing factor (Sec. 3.2.1), 0: off
 
     @property
     def nv(self):
@@ -137,5 +138,5 @@ def model_from_workload(w, **overrides) -> Model:
               newton_maxit=w.newton_maxit, pcg_rtol=w.pcg_rtol,
               pcg_maxit=w.pcg_maxit, mg_levels=w.mg_levels, mg_pre=w.mg_pre,
               mg_post=w.mg_post, mg_coarse_sweeps=w.mg_coarse_sweeps,
-              mg_fp32=w.mg_fp32)
+              mg_fp32=w.mg_fp32, pcg_forcing=w.pcg_forcing)
     return dataclasses.replace(m, **overrides) if overrides else m

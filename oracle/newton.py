@@ -99,7 +99,12 @@ def newton_step(Un, U0, nH, eh, src_cells, src_Q, dt, cosmo, model,
         if linear == "direct":
             sE, its = direct_solve(op, sch["b"]), 0
         else:
-            sE, its, _ = mg.pcg(op, sch["b"], model)
+            # inexact Newton (Sec. 3.2.1): with a forcing factor the linear
+            # solve may also stop at ||J S + f|| <= forcing ||f(U_k)||; the
+            # local rows are solved exactly, so ||J S + f||_2 is the Schur
+            # residual norm, and ||f||_2 = sqrt(size) times the RMS norm
+            atol = model.pcg_forcing * fn * np.sqrt(f.size)
+            sE, its, _ = mg.pcg(op, sch["b"], model, atol=atol)
         step = jacobian.recover(sE, sch) * scales
         st["cg_its"].append(its)
         lam = 1.0

@@ -35,7 +35,7 @@ class RtParams(ctypes.Structure):
         ("pcg_rtol", ctypes.c_double), ("pcg_maxit", ctypes.c_int32),
         ("mg_levels", ctypes.c_int32), ("mg_pre", ctypes.c_int32), ("mg_post", ctypes.c_int32),
         ("mg_coarse_sweeps", ctypes.c_int32), ("mg_fp32", ctypes.c_int32),
-        ("max_sources", ctypes.c_int32),
+        ("max_sources", ctypes.c_int32), ("pcg_forcing", ctypes.c_double),
     ]
 
 
@@ -100,6 +100,7 @@ SIGNATURES = {
                        ctypes.POINTER(RtNewtonStats)],
     "rt_fold_energy": [_P, _P, _P],
     "rt_timing": [_P, _I, ctypes.POINTER(RtKernelTiming)],
+    "rt_timing_classes": [_P, ctypes.c_uint32],
     "rt_spectrum_constants": [_I, _D, _P, _P, _P, ctypes.POINTER(_D)],
     "rt_net_workspace_bytes": [_I, _I, _I, _I, ctypes.POINTER(ctypes.c_uint64)],
     "rt_net_create": [_I, _I, _I, _I, _P, ctypes.c_uint64, _P, ctypes.POINTER(_P)],
@@ -187,6 +188,7 @@ def params_from_workload(w, **overrides) -> RtParams:
     p.mg_levels, p.mg_pre, p.mg_post = w.mg_levels, w.mg_pre, w.mg_post
     p.mg_coarse_sweeps, p.mg_fp32 = w.mg_coarse_sweeps, w.mg_fp32
     p.max_sources = max(64, w.nsources)
+    p.pcg_forcing = w.pcg_forcing
     for k, v in overrides.items():
         if k in ("K_gamma", "K_kappa", "K_heat"):
             getattr(p, k)[:] = list(v)
@@ -325,6 +327,16 @@ class RtGrid:
         self._check(lib().rt_timing(self.h, 1 if enable else 0, None if enable else ctypes.byref(out)),
                     "rt_timing")
         return None if enable else out.as_dict()
+
+    def rt_timing_classes(self, classes=None):
+        """Time only the named kernel classes (None: all) from now on."""
+        if classes is None:
+            mask = 0xFFFFFFFF
+        else:
+            mask = 0
+            for c in classes:
+                mask |= 1 << RT_K_NAMES.index(c)
+        self._check(lib().rt_timing_classes(self.h, mask), "rt_timing_classes")
 
     def rt_fold_energy(self, U, eh):
         return self._check(lib().rt_fold_energy(self.h, _ptr(U), _ptr(eh)), "rt_fold_energy")

@@ -5,6 +5,7 @@
 // iteration (8-16 byte copies).  CG's alpha and beta stay on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -55,6 +56,7 @@ struct Workspace {
 
 struct Timer {
   bool on = false;
+  uint32_t mask = 0xffffffffu;            // classes recorded while on
   std::vector<hipEvent_t> pool;           // events, reused across collections
   std::vector<int> cls;                   // class of each recorded launch
   size_t used = 0;
@@ -72,6 +74,8 @@ struct rt_grid {
   bool have_tl = false;     // time-level face coefficients present
   bool mg_stale = true;     // coarse operators need rebuilding
   bool have_op = false;     // a Schur matrix is present
+  double* hpin = nullptr;   // pinned host scalars for asynchronous read-back
+  hipEvent_t ev_rd = nullptr;
   std::string err;
 };
 
@@ -92,7 +96,7 @@ int fail(rt_grid* g, int code, const char* fmt, ...) {
 // record a start event (returns the slot) / stop event around a launch
 inline long tstart(rt_grid* g, int cls) {
   Timer& t = g->tm;
-  if (!t.on) return -1;
+  if (!t.on || !((t.mask >> cls) & 1u)) return -1;
   if (t.used + 2 > t.pool.size()) {
     const size_t grow = t.pool.size() < 1024 ? 1024 : t.pool.size();
     for (size_t i = 0; i < grow; ++i) {
@@ -151,6 +155,7 @@ int validate(const rt_params* p, std::string* why) {
   if (p->pcg_maxit < 0 || p->mg_pre < 0 || p->mg_post < 0 || p->mg_coarse_sweeps < 1)
     return bad("negative solver counts");
   if (p->max_sources < 0) return bad("max_sources < 0");
+  if (!(p->pcg_forcing >= 0.0) || !std::isfinite(p->pcg_forcing)) return bad("pcg_forcing must be finite and >= 0");
   if (p->limiter_mode != 0 && p->limiter_mode != 1) return bad("limiter_mode must be 0 or 1");
   return RT_OK;
 }
@@ -201,14 +206,12 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
         L.cz = c.take<double>(n); L.x = c.take<double>(n); L.b = c.take<double>(n);
         L.r = c.take<double>(n);
       }
-      L.x2 = c.take<double>(n);
       w->L64.push_back(L);
     } else {
       Level<float> L{nx, ny, nz};
       L.diag = c.take<float>(n); L.cx = c.take<float>(n); L.cy = c.take<float>(n);
       L.cz = c.take<float>(n); L.x = c.take<float>(n); L.b = c.take<float>(n);
       L.r = c.take<float>(n);
-      L.x2 = c.take<float>(n);
       w->L32.push_back(L);
     }
     nx /= 2; ny /= 2; nz /= 2;
@@ -220,51 +223,30 @@ Step step_new(double dt, const rt_cosmo* c) { return Step{dt, c->a_new, c->H_new
 
 // ---------------------------------------------------------------------------
 // multigrid
+// b64 / out64 (finest level of the FP32 cycle only): the right side is read
+// from, and the result written to, FP64 vectors by the first and the last
+// smoothing launch themselves
 template <class T>
-void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l) {
+void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, const double* b64 = nullptr,
+            double* out64 = nullptr) {
   const rt_params& p = g->prm;
   hipStream_t st = g->st;
   Level<T>& L = Ls[l];
   const bool coarsest = (l + 1 == (int)Ls.size());
   const int kc = l == 0 ? RT_K_RBGS_FINE : RT_K_RBGS_COARSE;
   const long n = (long)L.nx * L.ny * L.nz;
+  if (coarsest && n <= COARSE_LDS_MAX) {
+    TK(g, kc, launch_coarse_solve_lds<T>(L, p.mg_coarse_sweeps, st));
+    return;
+  }
   if (coarsest && n <= COARSE_SOLVE_MAX) {
     TK(g, kc, launch_coarse_solve<T>(L, p.mg_coarse_sweeps, st));
     return;
   }
   const int pre = coarsest ? p.mg_coarse_sweeps : p.mg_pre;
   const int post = coarsest ? p.mg_coarse_sweeps : p.mg_post;
-  const bool fused = pre > 0 && pair_fits(L.nx, L.ny, L.nz);
-  if (fused) {
-    // (red, black) pairs from x = 0, then (black, red) pairs after the
-    // coarse-grid correction, ping-ponging between x and x2 so that the
-    // result ends in L.x
-    T* out = L.x;
-    T* alt = L.x2;
-    const int swaps = (pre - 1) + post;
-    T* cur = (swaps % 2 == 0) ? out : alt;
-    T* oth = (cur == out) ? alt : out;
-    TK(g, kc, launch_rbgs_first_pair<T>(L, cur, st));
-    for (int s = 1; s < pre; ++s) {
-      TK(g, kc, launch_rbgs_pair<T>(L, cur, oth, 0, st));
-      std::swap(cur, oth);
-    }
-    if (!coarsest) {
-      Level<T> Lc = L;
-      Lc.x = cur;
-      TK(g, RT_K_MG_TRANSFER, launch_mg_residual<T>(Lc, st));
-      TK(g, RT_K_MG_TRANSFER, launch_restrict<T>(Lc, Ls[l + 1], st));
-      vcycle<T>(g, Ls, l + 1);
-      TK(g, RT_K_MG_TRANSFER, launch_prolong_add<T>(Ls[l + 1], Lc, st));
-    }
-    for (int s = 0; s < post; ++s) {
-      TK(g, kc, launch_rbgs_pair<T>(L, cur, oth, 1, st));
-      std::swap(cur, oth);
-    }
-    return;
-  }
   if (pre > 0) {
-    TK(g, kc, launch_rbgs_first_pair<T>(L, L.x, st));   // (red, black) from x = 0
+    TK(g, kc, launch_rbgs_first_pair<T>(L, L.x, b64, st));   // (red, black) from x = 0
     for (int s = 1; s < pre; ++s) {
       TK(g, kc, launch_rbgs<T>(L, 0, st));
       TK(g, kc, launch_rbgs<T>(L, 1, st));
@@ -276,11 +258,16 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l) {
     TK(g, RT_K_MG_TRANSFER, launch_mg_residual<T>(L, st));
     TK(g, RT_K_MG_TRANSFER, launch_restrict<T>(L, Ls[l + 1], st));
     vcycle<T>(g, Ls, l + 1);
-    TK(g, RT_K_MG_TRANSFER, launch_prolong_add<T>(Ls[l + 1], L, st));
+    // the post-smoothing starts with black: only red cells need the correction
+    TK(g, RT_K_MG_TRANSFER, launch_prolong_add<T>(Ls[l + 1], L, post > 0 ? 0 : -1, st));
   }
   for (int s = 0; s < post; ++s) {
     TK(g, kc, launch_rbgs<T>(L, 1, st));
-    TK(g, kc, launch_rbgs<T>(L, 0, st));
+    if (out64 && s + 1 == post) {
+      TK(g, kc, launch_rbgs_out64<T>(L, 0, out64, st));
+    } else {
+      TK(g, kc, launch_rbgs<T>(L, 0, st));
+    }
   }
 }
 
@@ -313,9 +300,20 @@ void apply_vcycle(rt_grid* g, const double* r, double* z) {
     vcycle<double>(g, w.L64, 0);
   } else {
     Level<float>& L0 = w.L32[0];
-    TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
-    vcycle<float>(g, w.L32, 0);
-    TK(g, RT_K_MG_TRANSFER, launch_cvt_f2d(N, L0.x, z, g->st));
+    const long n0 = (long)L0.nx * L0.ny * L0.nz;
+    // the fused output needs the finest level to be smoothed (not the
+    // coarsest-level solve) with post-sweeps
+    const bool fused = w.L32.size() > 1 && g->prm.mg_pre > 0 && g->prm.mg_post > 0 && n0 > 0;
+    if (fused) {
+      // the conversion of r stays a pass of its own: read at seven points
+      // by the first pair, FP64 r costs more than it saves
+      TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
+      vcycle<float>(g, w.L32, 0, nullptr, z);
+    } else {
+      TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
+      vcycle<float>(g, w.L32, 0);
+      TK(g, RT_K_MG_TRANSFER, launch_cvt_f2d(N, L0.x, z, g->st));
+    }
   }
 }
 
@@ -331,7 +329,8 @@ void finish_reduce(rt_grid* g, int n_items_blocks, int ncomp, int slot) {
 }
 
 // PCG on the workspace Schur matrix: solve S x = b (x in w.x)
-int pcg(rt_grid* g, const double* b, double* x, double rtol, int maxit, int* iters,
+// stops at ||r||_2 <= max(rtol ||b||_2, atol)
+int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int maxit, int* iters,
         double* relres, int* vcycles) {
   Workspace& w = g->w;
   const long N = g->P.N;
@@ -342,6 +341,7 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, int maxit, int* ite
   finish_reduce(g, nparts, 1, S_BB);
   RTCHK(read_scalars(g, w.sc + S_BB, h, 1));
   const double bn = std::sqrt(h[0]);
+  const double thr = std::max(rtol * bn, atol);
   TK(g, RT_K_CG_VECTOR, launch_fill<double>(N, x, 0.0, g->st));
   *iters = 0;
   *relres = 0.0;
@@ -356,6 +356,20 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, int maxit, int* ite
   TK(g, RT_K_CG_VECTOR, launch_dot1(N, w.r, w.z, w.parts, g->st));
   finish_reduce(g, nparts, 1, S_RHO);
   HIPCHK(g, hipMemcpyAsync(w.p, w.z, N * sizeof(double), hipMemcpyDeviceToDevice, g->st));
+  // The tail of an iteration (V-cycle, dots, new direction) writes only z, p
+  // and CG scalars, so while the last residual is still far above the
+  // tolerance it is enqueued before this iteration's residual norm has come
+  // back to the host: the device never idles on the read-back.  If that norm
+  // turns out converged, the enqueued tail is discarded work and x is final.
+  constexpr double LOOKAHEAD = 30.0;
+  auto tail = [&]() {
+    apply_vcycle(g, w.r, w.z);
+    ++*vcycles;
+    TK(g, RT_K_CG_VECTOR, launch_dot2(N, w.z, w.r, w.q, w.parts, g->st));
+    finish_reduce(g, nparts, 2, S_ZR);
+    TK(g, RT_K_REDUCE, launch_cg_beta(w.sc, g->st));
+    TK(g, RT_K_CG_VECTOR, launch_update_p(N, w.p, w.z, w.sc, g->st));
+  };
   double rn = bn;
   int k = 0;
   for (k = 1; k <= maxit; ++k) {
@@ -364,17 +378,16 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, int maxit, int* ite
     TK(g, RT_K_REDUCE, launch_cg_alpha(w.sc, g->st));
     TK(g, RT_K_CG_VECTOR, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st));
     finish_reduce(g, nparts, 1, S_RR);
-    RTCHK(read_scalars(g, w.sc + S_RR, h, 1));
-    rn = std::sqrt(h[0]);
+    HIPCHK(g, hipMemcpyAsync(g->hpin, w.sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, g->st));
+    HIPCHK(g, hipEventRecord(g->ev_rd, g->st));
+    const bool ahead = k < maxit && rn > LOOKAHEAD * thr;
+    if (ahead) tail();
+    HIPCHK(g, hipEventSynchronize(g->ev_rd));
+    rn = std::sqrt(g->hpin[0]);
     if (!std::isfinite(rn)) return fail(g, RT_ENONFINITE, "non-finite CG residual");
-    if (rn <= rtol * bn) break;
+    if (rn <= thr) break;
     if (k == maxit) break;
-    apply_vcycle(g, w.r, w.z);
-    ++*vcycles;
-    TK(g, RT_K_CG_VECTOR, launch_dot2(N, w.z, w.r, w.q, w.parts, g->st));
-    finish_reduce(g, nparts, 2, S_ZR);
-    TK(g, RT_K_REDUCE, launch_cg_beta(w.sc, g->st));
-    TK(g, RT_K_CG_VECTOR, launch_update_p(N, w.p, w.z, w.sc, g->st));
+    if (!ahead) tail();
   }
   *iters = k > maxit ? maxit : k;
   *relres = rn / bn;
@@ -463,6 +476,13 @@ int rt_create_grid(const rt_params* p, void* d_ws, uint64_t ws_bytes, void* hip_
   P.alpha0[0] = 2.59e-13;                            // case-B HII at 1e4 K
   P.alpha0[1] = 2.72e-13;                            // HeII (placeholder datum)
   P.alpha0[2] = 2.0 * 2.59e-13 * std::pow(4.0, 0.7); // HeIII, hydrogenic Z = 2
+  if (hipHostMalloc(reinterpret_cast<void**>(&g->hpin), 4 * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_rd, hipEventDisableTiming) != hipSuccess) {
+    if (g->hpin) hipHostFree(g->hpin);
+    delete g;
+    return RT_EDEVICE;
+  }
   *out = g;
   return RT_OK;
 }
@@ -470,6 +490,8 @@ int rt_create_grid(const rt_params* p, void* d_ws, uint64_t ws_bytes, void* hip_
 int rt_destroy_grid(rt_grid* g) {
   if (g) {
     for (hipEvent_t e : g->tm.pool) hipEventDestroy(e);
+    if (g->ev_rd) hipEventDestroy(g->ev_rd);
+    if (g->hpin) hipHostFree(g->hpin);
   }
   delete g;
   return RT_OK;
@@ -600,7 +622,7 @@ int rt_mg_pcg_solve(rt_grid* g, const double* d_b, double* d_sE, double rtol, in
   if (!d_b || !d_sE || maxit < 0 || !(rtol >= 0)) return fail(g, RT_EINVAL, "bad argument");
   int its = 0, vc = 0;
   double rr = 0;
-  RTCHK(pcg(g, d_b, d_sE, rtol, maxit, &its, &rr, &vc));
+  RTCHK(pcg(g, d_b, d_sE, rtol, 0.0, maxit, &its, &rr, &vc));
   if (h_iters) *h_iters = its;
   if (h_relres) *h_relres = rr;
   return RT_OK;
@@ -650,7 +672,10 @@ int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_
     g->have_op = true;
     int its = 0, vc = 0;
     double rr = 0;
-    status = pcg(g, w.b, w.x, g->prm.pcg_rtol, g->prm.pcg_maxit, &its, &rr, &vc);
+    // ||J S + f||_2 equals the Schur residual norm (the local rows are solved
+    // exactly), and ||f||_2 = sqrt(N nv) times the RMS norm
+    const double atol = g->prm.pcg_forcing * fn * std::sqrt((double)P.N * P.nv);
+    status = pcg(g, w.b, w.x, g->prm.pcg_rtol, atol, g->prm.pcg_maxit, &its, &rr, &vc);
     if (status != RT_OK) break;
     st.cg_its[k] = its;
     st.cg_its_total += its;
@@ -715,6 +740,12 @@ int rt_timing(rt_grid* g, int32_t enable, rt_kernel_timing* out) {
   }
   t.used = 0;
   t.cls.clear();
+  return RT_OK;
+}
+
+int rt_timing_classes(rt_grid* g, uint32_t mask) {
+  if (!g) return RT_EINVAL;
+  g->tm.mask = mask;
   return RT_OK;
 }
 

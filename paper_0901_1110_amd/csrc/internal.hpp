@@ -68,20 +68,25 @@ struct Level {
   int nx, ny, nz;
   T *diag, *cx, *cy, *cz;   // operator
   T *x, *b, *r;             // solution, right side, residual scratch
-  T* x2;                    // second solution buffer for the fused red-black pairs
 };
 template <class T> void launch_fill(long n, T* x, T v, hipStream_t st);
 template <class T> void launch_rbgs(const Level<T>& L, int colour, hipStream_t st);
-template <class T> void launch_rbgs_first_pair(const Level<T>& L, T* xo, hipStream_t st);
+// first (red, black) pair from x = 0; b64 non-null: right side read from FP64
+// and its rounding stored to L.b
 template <class T>
-void launch_rbgs_pair(const Level<T>& L, const T* xin, T* xout, int c0, hipStream_t st);
-bool pair_fits(int nx, int ny, int nz);   // the fused-pair tiling divides this level
+void launch_rbgs_first_pair(const Level<T>& L, T* xo, const double* b64, hipStream_t st);
+// half-sweep whose result (both colours) goes widened to out64 instead of x
+template <class T> void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, hipStream_t st);
 template <class T> void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st);
+// coarsest solve with the level in registers and LDS (n <= COARSE_LDS_MAX)
+template <class T> void launch_coarse_solve_lds(const Level<T>& L, int sweeps, hipStream_t st);
+constexpr int COARSE_LDS_MAX = 4096;
 int stencil_blocks(int nx, int ny, int nz);   // blocks (= partial sums) of a 3-D stencil launch
 constexpr int COARSE_SOLVE_MAX = 8192;        // coarsest levels up to this size: one workgroup
 template <class T> void launch_mg_residual(const Level<T>& L, hipStream_t st);
 template <class T> void launch_restrict(const Level<T>& F, const Level<T>& C, hipStream_t st);
-template <class T> void launch_prolong_add(const Level<T>& C, const Level<T>& F, hipStream_t st);
+// colour >= 0: correct only the cells of that colour
+template <class T> void launch_prolong_add(const Level<T>& C, const Level<T>& F, int colour, hipStream_t st);
 template <class T> void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st);
 void launch_fold_energy(int N, double* U, double* eh, hipStream_t st);
 void launch_cvt_d2f(long n, const double* a, float* b, hipStream_t st);

@@ -386,8 +386,16 @@ __global__ __launch_bounds__(1024) void k_final_reduce(const double* __restrict_
                                                        double* __restrict__ out) {
   __shared__ double sh[1024 / 64][NCOMP_MAX];
   for (int c = 0; c < ncomp; ++c) {
-    double x = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 1024) x += parts[i * NCOMP_MAX + c];
+    // eight independent chains (fixed assignment and combine order), so the
+    // loads of a thread are in flight together
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = threadIdx.x;
+    for (; i + 7 * 1024 < nparts; i += 8 * 1024) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += parts[(i + u * 1024) * NCOMP_MAX + c];
+    }
+    for (int u = 0; i < nparts; i += 1024, ++u) a[u] += parts[i * NCOMP_MAX + c];
+    double x = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][c] = x;
@@ -516,25 +524,52 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Level<T> L, int colour) {
   rbgs_update(L, c.i, c.j, k);
 }
 
+// the last half-sweep of a V-cycle with the result widened into a FP64
+// vector: the thread of cell k also copies its pair partner k ^ 1 (the other
+// colour, final already), so out64 receives every cell and x is not stored
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_rbgs_out64(Level<T> L, int colour,
+                                                      double* __restrict__ out64) {
+  const C3 c = coord3(L.ny, L.nz >> 1);
+  if (!c.ok) return;
+  const int i = c.i, j = c.j;
+  const int k = 2 * c.k + ((i + j + colour) & 1);
+  const int idx = (i * L.ny + j) * L.nz + k;
+  const Nb nb = nbrs(i, j, k, L.nx, L.ny, L.nz);
+  const T* x = L.x;
+  T s = L.b[idx];
+  s = s + L.cx[idx] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
+  s = s + L.cy[idx] * x[nb.yp] + L.cy[nb.ym] * x[nb.ym];
+  s = s + L.cz[idx] * x[nb.zp] + L.cz[nb.zm] * x[nb.zm];
+  out64[idx] = (double)(s / L.diag[idx]);
+  const int part = idx + ((k & 1) ? -1 : 1);
+  out64[part] = (double)x[part];
+}
+
 // the first (red, black) pair from x = 0 in one pass: red cells take b/diag,
 // black cells use their red neighbours' b/diag (the values the red half-sweep
 // would have produced)
+// With b64 given, the right side is read from that FP64 vector and its
+// rounding to T is also stored to L.b for the passes that follow.
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_rbgs_first_pair(Level<T> L, T* __restrict__ xo) {
+__global__ __launch_bounds__(BLOCK) void k_rbgs_first_pair(Level<T> L, T* __restrict__ xo,
+                                                           const double* __restrict__ b64) {
   const C3 c = coord3(L.ny, L.nz);
   if (!c.ok) return;
   const int idx = (c.i * L.ny + c.j) * L.nz + c.k;
+  auto B = [&](int g) -> T { return b64 ? (T)b64[g] : L.b[g]; };
+  const T bv = B(idx);
+  if (b64) L.b[idx] = bv;
   if (((c.i + c.j + c.k) & 1) == 0) {
-    xo[idx] = L.b[idx] / L.diag[idx];
+    xo[idx] = bv / L.diag[idx];
     return;
   }
   const Nb nb = nbrs(c.i, c.j, c.k, L.nx, L.ny, L.nz);
-  const T* b = L.b;
   const T* d = L.diag;
-  T s = b[idx];
-  s = s + L.cx[idx] * (b[nb.xp] / d[nb.xp]) + L.cx[nb.xm] * (b[nb.xm] / d[nb.xm]);
-  s = s + L.cy[idx] * (b[nb.yp] / d[nb.yp]) + L.cy[nb.ym] * (b[nb.ym] / d[nb.ym]);
-  s = s + L.cz[idx] * (b[nb.zp] / d[nb.zp]) + L.cz[nb.zm] * (b[nb.zm] / d[nb.zm]);
+  T s = bv;
+  s = s + L.cx[idx] * (B(nb.xp) / d[nb.xp]) + L.cx[nb.xm] * (B(nb.xm) / d[nb.xm]);
+  s = s + L.cy[idx] * (B(nb.yp) / d[nb.yp]) + L.cy[nb.ym] * (B(nb.ym) / d[nb.ym]);
+  s = s + L.cz[idx] * (B(nb.zp) / d[nb.zp]) + L.cz[nb.zm] * (B(nb.zm) / d[nb.zm]);
   xo[idx] = s / d[idx];
 }
 
@@ -564,86 +599,68 @@ __global__ __launch_bounds__(1024) void k_coarse_solve(Level<T> L, int sweeps) {
   }
 }
 
-// One fused (c0, c1) red-black pair -- a c0 half-sweep followed by a c1
-// half-sweep -- in a single pass over the level.  A block owns a TJ x TK
-// column of rows and marches through PI x-planes, keeping four planes of the
-// input x (halo 2 in y and z) and three planes of new c0 values (halo 1) in
-// LDS; new c1 values need the new c0 values of their six neighbours, which
-// the block computes itself on its halo ring (redundantly with the
-// neighbouring block).  x is double-buffered (xin -> xout), so no block reads
-// a value another block has already overwritten, and the arithmetic is that
-// of the two half-sweeps, term for term.
-template <class T, int TK, int TJ, int PI>
-__global__ __launch_bounds__(256) void k_rbgs_pair(Level<T> L, const T* __restrict__ xin,
-                                                   T* __restrict__ xout, int c0) {
-  constexpr int RK = TK + 4, RJ = TJ + 4;   // input window (halo 2)
-  constexpr int QK = TK + 2, QJ = TJ + 2;   // new c0 values (halo 1)
-  __shared__ T xs[4][RJ][RK];
-  __shared__ T cs[3][QJ][QK];
+// coarsest-level solve in one workgroup with the level held on chip: each
+// thread keeps the right side and the seven coefficients of its cells in
+// registers and x lives in LDS, so the 4*sweeps half-sweeps touch no memory
+constexpr int CS_THREADS = 512, CS_CPT = 4;   // up to 2 * 512 * 4 = 4096 cells
+template <class T>
+__global__ __launch_bounds__(CS_THREADS) void k_coarse_solve_lds(Level<T> L, int sweeps) {
+  __shared__ T xs[2 * CS_THREADS * CS_CPT];
   const int nx = L.nx, ny = L.ny, nz = L.nz;
-  const int k0 = blockIdx.x * TK, j0 = blockIdx.y * TJ, i0 = blockIdx.z * PI;
+  const int half = nz >> 1;
+  const int n2 = nx * ny * half;
   const int tid = threadIdx.x;
-  auto gidx = [&](int i, int j, int k) {
-    return (wrap(i, nx) * ny + wrap(j, ny)) * nz + wrap(k, nz);
-  };
-  auto slot = [](int i) { return (i + 8) & 3; };
-  auto cslot = [](int i) { return (i + 9) % 3; };
-  auto load_plane = [&](int i) {
-    const int sl = slot(i);
-    for (int t = tid; t < RJ * RK; t += 256) {
-      const int jj = t / RK, kk = t - jj * RK;
-      xs[sl][jj][kk] = xin[gidx(i, j0 + jj - 2, k0 + kk - 2)];
+  T cb[2][CS_CPT], cd[2][CS_CPT], c6[2][CS_CPT][6];
+  int nb6[2][CS_CPT][6], own[2][CS_CPT];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int m = 0; m < CS_CPT; ++m) {
+      const int t = tid + m * CS_THREADS;
+      own[c][m] = -1;
+      if (t < n2) {
+        const int row = t / half;
+        const int j = row % ny;
+        const int i = row / ny;
+        const int k = 2 * (t - row * half) + ((i + j + c) & 1);
+        const int idx = (i * ny + j) * nz + k;
+        const Nb nb = nbrs(i, j, k, nx, ny, nz);
+        own[c][m] = idx;
+        cb[c][m] = L.b[idx];
+        cd[c][m] = L.diag[idx];
+        c6[c][m][0] = L.cx[idx];   nb6[c][m][0] = nb.xp;
+        c6[c][m][1] = L.cx[nb.xm]; nb6[c][m][1] = nb.xm;
+        c6[c][m][2] = L.cy[idx];   nb6[c][m][2] = nb.yp;
+        c6[c][m][3] = L.cy[nb.ym]; nb6[c][m][3] = nb.ym;
+        c6[c][m][4] = L.cz[idx];   nb6[c][m][4] = nb.zp;
+        c6[c][m][5] = L.cz[nb.zm]; nb6[c][m][5] = nb.zm;
+      }
     }
-  };
-  // new c0 values of plane i on the halo-1 region
-  auto c0_plane = [&](int i) {
-    const int sm = slot(i - 1), s0 = slot(i), sp = slot(i + 1), q = cslot(i);
-    for (int t = tid; t < QJ * (QK / 2); t += 256) {
-      const int jj = t / (QK / 2);
-      const int j = j0 + jj - 1;
-      // first region column kk whose cell has colour c0
-      const int par = (c0 - i - j - (k0 - 1)) & 1;
-      const int kk = 2 * (t - jj * (QK / 2)) + par;
-      const int k = k0 + kk - 1;
-      const int g = gidx(i, j, k);
-      T sum = L.b[g];
-      sum = sum + L.cx[g] * xs[sp][jj + 1][kk + 1] + L.cx[gidx(i - 1, j, k)] * xs[sm][jj + 1][kk + 1];
-      sum = sum + L.cy[g] * xs[s0][jj + 2][kk + 1] + L.cy[gidx(i, j - 1, k)] * xs[s0][jj][kk + 1];
-      sum = sum + L.cz[g] * xs[s0][jj + 1][kk + 2] + L.cz[gidx(i, j, k - 1)] * xs[s0][jj + 1][kk];
-      cs[q][jj][kk] = sum / L.diag[g];
-    }
-  };
-  load_plane(i0 - 2);
-  load_plane(i0 - 1);
-  load_plane(i0);
-  load_plane(i0 + 1);
-  __syncthreads();
-  c0_plane(i0 - 1);
-  c0_plane(i0);
-  // the first load of the loop overwrites the slot of plane i0 - 2, which
-  // c0_plane(i0 - 1) reads: every thread must be past it
-  __syncthreads();
-  const int tj = tid / TK, tk = tid - tj * TK;
-  for (int i = i0; i < i0 + PI; ++i) {
-    load_plane(i + 2);
-    __syncthreads();
-    c0_plane(i + 1);
-    __syncthreads();
-    const int j = j0 + tj, k = k0 + tk;
-    const int g = (i * ny + j) * nz + k;
-    const int qm = cslot(i - 1), q0 = cslot(i), qp = cslot(i + 1);
-    T val;
-    if (((i + j + k) & 1) == c0) {
-      val = cs[q0][tj + 1][tk + 1];
-    } else {
-      T sum = L.b[g];
-      sum = sum + L.cx[g] * cs[qp][tj + 1][tk + 1] + L.cx[gidx(i - 1, j, k)] * cs[qm][tj + 1][tk + 1];
-      sum = sum + L.cy[g] * cs[q0][tj + 2][tk + 1] + L.cy[gidx(i, j - 1, k)] * cs[q0][tj][tk + 1];
-      sum = sum + L.cz[g] * cs[q0][tj + 1][tk + 2] + L.cz[gidx(i, j, k - 1)] * cs[q0][tj + 1][tk];
-      val = sum / L.diag[g];
-    }
-    xout[g] = val;
   }
+  for (int t = tid; t < 2 * n2; t += CS_THREADS) xs[t] = T(0);
+  __syncthreads();
+  for (int s = 0; s < 2 * sweeps; ++s) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int colour = (s < sweeps) ? h : 1 - h;
+#pragma unroll
+      for (int m = 0; m < CS_CPT; ++m) {
+        // both colours are unrolled so the arrays stay in registers
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          if (c == colour && own[c][m] >= 0) {
+            T sum = cb[c][m];
+            sum = sum + c6[c][m][0] * xs[nb6[c][m][0]] + c6[c][m][1] * xs[nb6[c][m][1]];
+            sum = sum + c6[c][m][2] * xs[nb6[c][m][2]] + c6[c][m][3] * xs[nb6[c][m][3]];
+            sum = sum + c6[c][m][4] * xs[nb6[c][m][4]] + c6[c][m][5] * xs[nb6[c][m][5]];
+            xs[own[c][m]] = sum / cd[c][m];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = tid; t < 2 * n2; t += CS_THREADS) L.x[t] = xs[t];
 }
 
 template <class T>
@@ -691,12 +708,15 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C) {
 }
 
 // x_fine += P x_coarse: cell-centred trilinear, weights 3/4 (parent) and 1/4
-// (the parent's neighbour on the child's side) per axis
+// (the parent's neighbour on the child's side) per axis.  With colour >= 0
+// only the cells of that colour are corrected: a post-smoothing that begins
+// with the other colour overwrites those cells without reading them.
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_prolong_add(Level<T> C, Level<T> F) {
-  const C3 c = coord3(F.ny, F.nz);
+__global__ __launch_bounds__(BLOCK) void k_prolong_add(Level<T> C, Level<T> F, int colour) {
+  const C3 c = coord3(F.ny, colour >= 0 ? F.nz >> 1 : F.nz);
   if (!c.ok) return;
-  const int i = c.i, j = c.j, k = c.k;
+  const int i = c.i, j = c.j;
+  const int k = colour >= 0 ? 2 * c.k + ((i + j + colour) & 1) : c.k;
   const int idx = (i * F.ny + j) * F.nz + k;
   const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
   const int I1 = wrap(I0 + ((i & 1) ? 1 : -1), C.nx);
@@ -905,18 +925,18 @@ void launch_rbgs(const Level<T>& L, int colour, hipStream_t st) {
   hipLaunchKernelGGL(k_rbgs<T>, q.g, q.b, 0, st, L, colour);
 }
 template <class T>
-void launch_rbgs_first_pair(const Level<T>& L, T* xo, hipStream_t st) {
+void launch_rbgs_first_pair(const Level<T>& L, T* xo, const double* b64, hipStream_t st) {
   const Geo q = geo3(L.nx, L.ny, L.nz);
-  hipLaunchKernelGGL(k_rbgs_first_pair<T>, q.g, q.b, 0, st, L, xo);
-}
-constexpr int PAIR_TK = 32, PAIR_TJ = 8, PAIR_PI = 16;
-bool pair_fits(int nx, int ny, int nz) {
-  return nz % PAIR_TK == 0 && ny % PAIR_TJ == 0 && nx % PAIR_PI == 0;
+  hipLaunchKernelGGL(k_rbgs_first_pair<T>, q.g, q.b, 0, st, L, xo, b64);
 }
 template <class T>
-void launch_rbgs_pair(const Level<T>& L, const T* xin, T* xout, int c0, hipStream_t st) {
-  const dim3 g(L.nz / PAIR_TK, L.ny / PAIR_TJ, L.nx / PAIR_PI);
-  hipLaunchKernelGGL((k_rbgs_pair<T, PAIR_TK, PAIR_TJ, PAIR_PI>), g, dim3(256), 0, st, L, xin, xout, c0);
+void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, hipStream_t st) {
+  const Geo q = geo3(L.nx, L.ny, L.nz / 2);
+  hipLaunchKernelGGL(k_rbgs_out64<T>, q.g, q.b, 0, st, L, colour, out64);
+}
+template <class T>
+void launch_coarse_solve_lds(const Level<T>& L, int sweeps, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_solve_lds<T>, dim3(1), dim3(CS_THREADS), 0, st, L, sweeps);
 }
 template <class T>
 void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st) {
@@ -933,9 +953,9 @@ void launch_restrict(const Level<T>& F, const Level<T>& C, hipStream_t st) {
   hipLaunchKernelGGL(k_restrict<T>, q.g, q.b, 0, st, F, C);
 }
 template <class T>
-void launch_prolong_add(const Level<T>& C, const Level<T>& F, hipStream_t st) {
-  const Geo q = geo3(F.nx, F.ny, F.nz);
-  hipLaunchKernelGGL(k_prolong_add<T>, q.g, q.b, 0, st, C, F);
+void launch_prolong_add(const Level<T>& C, const Level<T>& F, int colour, hipStream_t st) {
+  const Geo q = geo3(F.nx, F.ny, colour >= 0 ? F.nz / 2 : F.nz);
+  hipLaunchKernelGGL(k_prolong_add<T>, q.g, q.b, 0, st, C, F, colour);
 }
 template <class T>
 void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st) {
@@ -955,12 +975,13 @@ void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st) {
 #define RT_INST(T)                                                                   \
   template void launch_fill<T>(long, T*, T, hipStream_t);                            \
   template void launch_rbgs<T>(const Level<T>&, int, hipStream_t);                   \
-  template void launch_rbgs_first_pair<T>(const Level<T>&, T*, hipStream_t);         \
-  template void launch_rbgs_pair<T>(const Level<T>&, const T*, T*, int, hipStream_t); \
+  template void launch_rbgs_first_pair<T>(const Level<T>&, T*, const double*, hipStream_t); \
+  template void launch_rbgs_out64<T>(const Level<T>&, int, double*, hipStream_t); \
   template void launch_coarse_solve<T>(const Level<T>&, int, hipStream_t);           \
+  template void launch_coarse_solve_lds<T>(const Level<T>&, int, hipStream_t); \
   template void launch_mg_residual<T>(const Level<T>&, hipStream_t);                 \
   template void launch_restrict<T>(const Level<T>&, const Level<T>&, hipStream_t);   \
-  template void launch_prolong_add<T>(const Level<T>&, const Level<T>&, hipStream_t); \
+  template void launch_prolong_add<T>(const Level<T>&, const Level<T>&, int, hipStream_t); \
   template void launch_coarsen<T>(const Level<T>&, const Level<T>&, hipStream_t);
 RT_INST(double)
 RT_INST(float)

@@ -81,6 +81,7 @@ class Workload:
     newton_maxit: int = 20
     pcg_rtol: float = 1.0e-8
     pcg_maxit: int = 200
+    pcg_forcing: float = 0.0   # > 0: CG also stops at ||r|| <= pcg_forcing ||f(U_k)||
     mg_levels: int = 3
     mg_pre: int = 2
     mg_post: int = 2

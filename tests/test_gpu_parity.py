@@ -180,6 +180,12 @@ def test_newton_steps_256_spacing():
     newton_parity(w, synth.initial_state(w), steps=3)
 
 
+def test_newton_steps_256_spacing_forcing():
+    """The paper's inexact-Newton forcing delta_k = 1e-6 ||f(U_k)|| on both sides."""
+    w = synth.CFG_256.replace(n=64, mg_levels=4, pcg_forcing=1e-6)
+    newton_parity(w, synth.initial_state(w), steps=3)
+
+
 def test_newton_steps_expanding_lognormal():
     """Expanding lognormal medium with 16 sources (32^3 cut of the 128^3 workload)."""
     w = synth.CFG_COSMO.replace(n=32, mg_levels=3, dx=synth.CFG_COSMO.dx)
