@@ -81,11 +81,10 @@ typedef struct rt_params {
   int32_t mg_coarse_sweeps; /* coarsest level: this many (red,black) then (black,red) */
   int32_t mg_fp32;          /* 1: V-cycle in FP32 (Newton, CG, local solves stay FP64) */
   int32_t max_sources;      /* capacity of the point-source list */
-  double  pcg_forcing;      /* inexact-Newton forcing factor (Sec. 3.2.1): when > 0
-                               the CG solve of Newton iteration k also stops once
-                               ||J S_k + f(U_k)||_2 = ||r||_2 <= pcg_forcing
-                               ||f(U_k)||_2 (the paper's delta_k = 1e-6 ||f||);
-                               0 keeps the relative test above alone */
+  double  pcg_forcing;      /* inexact-Newton forcing (Sec. 3.2.1); > 0: the CG solve */
+                            /* of Newton iteration k also stops once ||r||_2 =       */
+                            /* ||J S_k + f(U_k)||_2 <= pcg_forcing ||f(U_k)||_2 (the  */
+                            /* paper's delta_k = 1e-6 ||f||); 0: relative test alone */
 } rt_params;
 
 /* Scale factor a and adot/a at t^n (old) and t^{n+1} (new). */
