@@ -47,6 +47,21 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0}
 
 
+# HBM traffic per launch of the finest-level FP32 smoother class at 256^3 with
+# V(2,2), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by
+# what the counters read for a plain 2 GiB device copy (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0), averaged over one V-cycle's 7 launches.  It belongs to the
+# kernel source it was measured on and is reported as null for any other.
+PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "bytes_per_launch": 6.049e8,
+                             "kernels_sha256": "a4c0ec13ade1a0037a439159b879ff8035a3a0256fa392e0931770880fc9fa57"}}
+
+
+def kernels_sha256():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_0901_1110_amd", "csrc", "kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
 def rbgs_fine_per_vcycle(pre, post, w):
     """(launches, algorithmic bytes per cell) of the fine-level smoothing in one V-cycle."""
     if pre > 0:
@@ -164,9 +179,15 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0):
         total_bytes = None
     if total_bytes is not None and ms > 0:
         achieved = total_bytes / (ms * 1e-3) / 1e9
+        tr = PMC_TRAFFIC.get(dom)
+        traffic = None
+        if (tr and tr["w"] == wbytes and tr["n"] == n and tr["pre_post"] == (p.mg_pre, p.mg_post)
+                and kernels_sha256() == tr["kernels_sha256"]):
+            traffic = tr["bytes_per_launch"]
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                           "algorithmic_bytes_per_launch": round(total_bytes / cnt),
                            "launches": cnt, "avg_launch_us": round(1e3 * ms / cnt, 2),
                            "share_of_timed": round(ms / gpu_ms, 3)}
     del sim
@@ -174,7 +195,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0):
     return res
 
 
-def cpu_baseline(n=64, budget_s=30.0):
+def cpu_baseline(n=128, budget_s=30.0):
     """The oracle on a bounded sample: the first implicit step of the same
     256^3-spacing problem on an n^3 periodic box around the source."""
     from threadpoolctl import threadpool_limits

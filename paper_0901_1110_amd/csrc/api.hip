@@ -106,13 +106,16 @@ inline long tstart(rt_grid* g, int cls) {
     }
   }
   const long slot = (long)t.used;
-  hipEventRecord(t.pool[t.used], g->st);
+  if (hipEventRecord(t.pool[t.used], g->st) != hipSuccess) {
+    t.on = false;   // timing stops; the launch itself goes ahead
+    return -1;
+  }
   t.used += 2;
   t.cls.push_back(cls);
   return slot;
 }
 inline void tstop(rt_grid* g, long slot) {
-  if (slot >= 0) hipEventRecord(g->tm.pool[slot + 1], g->st);
+  if (slot >= 0) (void)hipEventRecord(g->tm.pool[slot + 1], g->st);
 }
 #define TK(g, cls, expr)               \
   do {                                 \
@@ -479,7 +482,7 @@ int rt_create_grid(const rt_params* p, void* d_ws, uint64_t ws_bytes, void* hip_
   if (hipHostMalloc(reinterpret_cast<void**>(&g->hpin), 4 * sizeof(double), hipHostMallocDefault) !=
           hipSuccess ||
       hipEventCreateWithFlags(&g->ev_rd, hipEventDisableTiming) != hipSuccess) {
-    if (g->hpin) hipHostFree(g->hpin);
+    if (g->hpin) (void)hipHostFree(g->hpin);
     delete g;
     return RT_EDEVICE;
   }
@@ -489,9 +492,9 @@ int rt_create_grid(const rt_params* p, void* d_ws, uint64_t ws_bytes, void* hip_
 
 int rt_destroy_grid(rt_grid* g) {
   if (g) {
-    for (hipEvent_t e : g->tm.pool) hipEventDestroy(e);
-    if (g->ev_rd) hipEventDestroy(g->ev_rd);
-    if (g->hpin) hipHostFree(g->hpin);
+    for (hipEvent_t e : g->tm.pool) (void)hipEventDestroy(e);
+    if (g->ev_rd) (void)hipEventDestroy(g->ev_rd);
+    if (g->hpin) (void)hipHostFree(g->hpin);
   }
   delete g;
   return RT_OK;
