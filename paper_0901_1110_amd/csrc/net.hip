@@ -464,8 +464,9 @@ int nfail(rt_net* n, int code, const char* msg) {
   } while (0)
 
 bool geom_ok(int nx, int ny, int nz) {
+  // cell indices are 32-bit; every channel or field offset is formed in size_t
   return nx >= 3 && ny >= 3 && nz >= 16 && nz % 16 == 0 &&
-         (double)nx * ny * nz < 2147483647.0 / CH;
+         (double)nx * ny * nz < 2147483647.0;
 }
 
 inline unsigned nb(long n, int b) { return (unsigned)((n + b - 1) / b); }
