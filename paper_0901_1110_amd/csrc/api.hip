@@ -163,6 +163,13 @@ int validate(const rt_params* p, std::string* why) {
   return RT_OK;
 }
 
+// The finest level of the FP32 cycle is smoothed with pre- and post-sweeps
+// (not handled by the coarsest-level solve): it is stored colour-split, and
+// its last half-sweep writes the FP64 result directly.
+bool fp32_fused(const rt_params* p) {
+  return p->mg_fp32 && p->mg_levels > 1 && p->mg_pre > 0 && p->mg_post > 0;
+}
+
 size_t carve(const rt_params* p, char* base, Workspace* w) {
   Carver c{base, 0, base == nullptr};
   const size_t N = (size_t)p->nx * p->ny * p->nz;
@@ -215,6 +222,7 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
       L.diag = c.take<float>(n); L.cx = c.take<float>(n); L.cy = c.take<float>(n);
       L.cz = c.take<float>(n); L.x = c.take<float>(n); L.b = c.take<float>(n);
       L.r = c.take<float>(n);
+      L.split = (l == 0 && fp32_fused(p)) ? 1 : 0;
       w->L32.push_back(L);
     }
     nx /= 2; ny /= 2; nz /= 2;
@@ -226,12 +234,10 @@ Step step_new(double dt, const rt_cosmo* c) { return Step{dt, c->a_new, c->H_new
 
 // ---------------------------------------------------------------------------
 // multigrid
-// b64 / out64 (finest level of the FP32 cycle only): the right side is read
-// from, and the result written to, FP64 vectors by the first and the last
-// smoothing launch themselves
+// out64 (finest level of the FP32 cycle only): the last smoothing launch
+// writes the result widened to this FP64 vector itself
 template <class T>
-void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, const double* b64 = nullptr,
-            double* out64 = nullptr) {
+void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, double* out64 = nullptr) {
   const rt_params& p = g->prm;
   hipStream_t st = g->st;
   Level<T>& L = Ls[l];
@@ -249,7 +255,7 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, const double* b64 = nu
   const int pre = coarsest ? p.mg_coarse_sweeps : p.mg_pre;
   const int post = coarsest ? p.mg_coarse_sweeps : p.mg_post;
   if (pre > 0) {
-    TK(g, kc, launch_rbgs_first_pair<T>(L, L.x, b64, st));   // (red, black) from x = 0
+    TK(g, kc, launch_rbgs_first_pair<T>(L, L.x, st));   // (red, black) from x = 0
     for (int s = 1; s < pre; ++s) {
       TK(g, kc, launch_rbgs<T>(L, 0, st));
       TK(g, kc, launch_rbgs<T>(L, 1, st));
@@ -282,10 +288,10 @@ int build_hierarchy(rt_grid* g) {
     for (size_t l = 1; l < w.L64.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<double>(w.L64[l - 1], w.L64[l], g->st));
   } else {
     Level<float>& L0 = w.L32[0];
-    TK(g, RT_K_MG_SETUP, launch_cvt_d2f(N, w.diag, L0.diag, g->st));
-    TK(g, RT_K_MG_SETUP, launch_cvt_d2f(N, w.cx, L0.cx, g->st));
-    TK(g, RT_K_MG_SETUP, launch_cvt_d2f(N, w.cy, L0.cy, g->st));
-    TK(g, RT_K_MG_SETUP, launch_cvt_d2f(N, w.cz, L0.cz, g->st));
+    TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.diag, L0.diag, g->st));
+    TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cx, L0.cx, g->st));
+    TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cy, L0.cy, g->st));
+    TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cz, L0.cz, g->st));
     for (size_t l = 1; l < w.L32.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<float>(w.L32[l - 1], w.L32[l], g->st));
   }
   g->mg_stale = false;
@@ -303,15 +309,11 @@ void apply_vcycle(rt_grid* g, const double* r, double* z) {
     vcycle<double>(g, w.L64, 0);
   } else {
     Level<float>& L0 = w.L32[0];
-    const long n0 = (long)L0.nx * L0.ny * L0.nz;
-    // the fused output needs the finest level to be smoothed (not the
-    // coarsest-level solve) with post-sweeps
-    const bool fused = w.L32.size() > 1 && g->prm.mg_pre > 0 && g->prm.mg_post > 0 && n0 > 0;
-    if (fused) {
-      // the conversion of r stays a pass of its own: read at seven points
-      // by the first pair, FP64 r costs more than it saves
-      TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
-      vcycle<float>(g, w.L32, 0, nullptr, z);
+    if (fp32_fused(&g->prm)) {
+      // r is converted (into the colour-split layout) by a pass of its own:
+      // read at seven points by the first pair, FP64 r costs more than it saves
+      TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f_level(L0, r, L0.b, g->st));
+      vcycle<float>(g, w.L32, 0, z);
     } else {
       TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
       vcycle<float>(g, w.L32, 0);

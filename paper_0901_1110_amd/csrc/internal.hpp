@@ -68,13 +68,12 @@ struct Level {
   int nx, ny, nz;
   T *diag, *cx, *cy, *cz;   // operator
   T *x, *b, *r;             // solution, right side, residual scratch
+  int split = 0;            // 1: colour-split rows (finest level of the FP32 cycle)
 };
 template <class T> void launch_fill(long n, T* x, T v, hipStream_t st);
 template <class T> void launch_rbgs(const Level<T>& L, int colour, hipStream_t st);
-// first (red, black) pair from x = 0; b64 non-null: right side read from FP64
-// and its rounding stored to L.b
-template <class T>
-void launch_rbgs_first_pair(const Level<T>& L, T* xo, const double* b64, hipStream_t st);
+// first (red, black) pair from x = 0
+template <class T> void launch_rbgs_first_pair(const Level<T>& L, T* xo, hipStream_t st);
 // half-sweep whose result (both colours) goes widened to out64 instead of x
 template <class T> void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, hipStream_t st);
 template <class T> void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st);
@@ -90,6 +89,8 @@ template <class T> void launch_prolong_add(const Level<T>& C, const Level<T>& F,
 template <class T> void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st);
 void launch_fold_energy(int N, double* U, double* eh, hipStream_t st);
 void launch_cvt_d2f(long n, const double* a, float* b, hipStream_t st);
+// FP64 natural field -> FP32 field in the layout of level L
+void launch_cvt_d2f_level(const Level<float>& L, const double* a, float* b, hipStream_t st);
 void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st);
 
 }  // namespace rtk

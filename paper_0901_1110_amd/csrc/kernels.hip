@@ -501,76 +501,101 @@ __global__ __launch_bounds__(BLOCK) void k_fill(long n, T* __restrict__ x, T v) 
 
 __device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Finest-level layout of the FP32 V-cycle.  Natural: cell (i,j,k) at
+// (i*ny + j)*nz + k.  Colour-split (SF): each z-row holds its colour-0 cells,
+// then its colour-1 cells, each half in k order, so cell (i,j,k) sits at
+// (i*ny + j)*nz + ((i+j+k) & 1)*(nz/2) + k/2.  A half-sweep then touches dense
+// half-rows only: the six neighbours of a cell have the other colour and sit
+// at k/2 (the z neighbours at k/2 or the place next to it) of that colour's
+// half of the same or an adjacent row.
+template <bool SF>
+__device__ inline int lidx(int i, int j, int k, int ny, int nz) {
+  if constexpr (SF) return (i * ny + j) * nz + ((i + j + k) & 1) * (nz >> 1) + (k >> 1);
+  else return (i * ny + j) * nz + k;
+}
+struct Nb7 {
+  int c, xm, xp, ym, yp, zm, zp;
+};
+template <bool SF>
+__device__ inline Nb7 nbrs7(int i, int j, int k, int nx, int ny, int nz) {
+  if constexpr (!SF) {
+    const Nb n = nbrs(i, j, k, nx, ny, nz);
+    return Nb7{(i * ny + j) * nz + k, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp};
+  } else {
+    const int ip = i + 1 < nx ? i + 1 : 0, im = i > 0 ? i - 1 : nx - 1;
+    const int jp = j + 1 < ny ? j + 1 : 0, jm = j > 0 ? j - 1 : ny - 1;
+    const int kp = k + 1 < nz ? k + 1 : 0, km = k > 0 ? k - 1 : nz - 1;
+    return Nb7{lidx<true>(i, j, k, ny, nz),  lidx<true>(im, j, k, ny, nz),
+               lidx<true>(ip, j, k, ny, nz), lidx<true>(i, jm, k, ny, nz),
+               lidx<true>(i, jp, k, ny, nz), lidx<true>(i, j, km, ny, nz),
+               lidx<true>(i, j, kp, ny, nz)};
+  }
+}
+
 // one colour of a red-black Gauss-Seidel sweep (colour = (i+j+k) mod 2);
 // the launch's x extent is nz/2: thread kk owns the kk-th cell of the colour
 // in its z-row (nz even)
-template <class T>
+template <class T, bool SF = false>
 __device__ inline void rbgs_update(const Level<T>& L, int i, int j, int k) {
-  const int idx = (i * L.ny + j) * L.nz + k;
-  const Nb nb = nbrs(i, j, k, L.nx, L.ny, L.nz);
+  const Nb7 nb = nbrs7<SF>(i, j, k, L.nx, L.ny, L.nz);
   const T* x = L.x;
-  T s = L.b[idx];
-  s = s + L.cx[idx] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
-  s = s + L.cy[idx] * x[nb.yp] + L.cy[nb.ym] * x[nb.ym];
-  s = s + L.cz[idx] * x[nb.zp] + L.cz[nb.zm] * x[nb.zm];
-  L.x[idx] = s / L.diag[idx];
+  T s = L.b[nb.c];
+  s = s + L.cx[nb.c] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
+  s = s + L.cy[nb.c] * x[nb.yp] + L.cy[nb.ym] * x[nb.ym];
+  s = s + L.cz[nb.c] * x[nb.zp] + L.cz[nb.zm] * x[nb.zm];
+  L.x[nb.c] = s / L.diag[nb.c];
 }
 
-template <class T>
+template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_rbgs(Level<T> L, int colour) {
   const C3 c = coord3(L.ny, L.nz >> 1);
   if (!c.ok) return;
   const int k = 2 * c.k + ((c.i + c.j + colour) & 1);
-  rbgs_update(L, c.i, c.j, k);
+  rbgs_update<T, SF>(L, c.i, c.j, k);
 }
 
 // the last half-sweep of a V-cycle with the result widened into a FP64
-// vector: the thread of cell k also copies its pair partner k ^ 1 (the other
-// colour, final already), so out64 receives every cell and x is not stored
-template <class T>
+// vector (natural layout): the thread of cell k also copies its pair partner
+// k ^ 1 (the other colour, final already), so out64 receives every cell and x
+// is not stored
+template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_rbgs_out64(Level<T> L, int colour,
                                                       double* __restrict__ out64) {
   const C3 c = coord3(L.ny, L.nz >> 1);
   if (!c.ok) return;
   const int i = c.i, j = c.j;
   const int k = 2 * c.k + ((i + j + colour) & 1);
-  const int idx = (i * L.ny + j) * L.nz + k;
-  const Nb nb = nbrs(i, j, k, L.nx, L.ny, L.nz);
+  const int row = (i * L.ny + j) * L.nz;
+  const Nb7 nb = nbrs7<SF>(i, j, k, L.nx, L.ny, L.nz);
   const T* x = L.x;
-  T s = L.b[idx];
-  s = s + L.cx[idx] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
-  s = s + L.cy[idx] * x[nb.yp] + L.cy[nb.ym] * x[nb.ym];
-  s = s + L.cz[idx] * x[nb.zp] + L.cz[nb.zm] * x[nb.zm];
-  out64[idx] = (double)(s / L.diag[idx]);
-  const int part = idx + ((k & 1) ? -1 : 1);
-  out64[part] = (double)x[part];
+  T s = L.b[nb.c];
+  s = s + L.cx[nb.c] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
+  s = s + L.cy[nb.c] * x[nb.yp] + L.cy[nb.ym] * x[nb.ym];
+  s = s + L.cz[nb.c] * x[nb.zp] + L.cz[nb.zm] * x[nb.zm];
+  out64[row + k] = (double)(s / L.diag[nb.c]);
+  out64[row + (k ^ 1)] = (double)x[lidx<SF>(i, j, k ^ 1, L.ny, L.nz)];
 }
 
 // the first (red, black) pair from x = 0 in one pass: red cells take b/diag,
 // black cells use their red neighbours' b/diag (the values the red half-sweep
 // would have produced)
-// With b64 given, the right side is read from that FP64 vector and its
-// rounding to T is also stored to L.b for the passes that follow.
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_rbgs_first_pair(Level<T> L, T* __restrict__ xo,
-                                                           const double* __restrict__ b64) {
+template <class T, bool SF>
+__global__ __launch_bounds__(BLOCK) void k_rbgs_first_pair(Level<T> L, T* __restrict__ xo) {
   const C3 c = coord3(L.ny, L.nz);
   if (!c.ok) return;
-  const int idx = (c.i * L.ny + c.j) * L.nz + c.k;
-  auto B = [&](int g) -> T { return b64 ? (T)b64[g] : L.b[g]; };
-  const T bv = B(idx);
-  if (b64) L.b[idx] = bv;
+  const T* b = L.b;
+  const T* d = L.diag;
   if (((c.i + c.j + c.k) & 1) == 0) {
-    xo[idx] = bv / L.diag[idx];
+    const int idx = lidx<SF>(c.i, c.j, c.k, L.ny, L.nz);
+    xo[idx] = b[idx] / d[idx];
     return;
   }
-  const Nb nb = nbrs(c.i, c.j, c.k, L.nx, L.ny, L.nz);
-  const T* d = L.diag;
-  T s = bv;
-  s = s + L.cx[idx] * (B(nb.xp) / d[nb.xp]) + L.cx[nb.xm] * (B(nb.xm) / d[nb.xm]);
-  s = s + L.cy[idx] * (B(nb.yp) / d[nb.yp]) + L.cy[nb.ym] * (B(nb.ym) / d[nb.ym]);
-  s = s + L.cz[idx] * (B(nb.zp) / d[nb.zp]) + L.cz[nb.zm] * (B(nb.zm) / d[nb.zm]);
-  xo[idx] = s / d[idx];
+  const Nb7 nb = nbrs7<SF>(c.i, c.j, c.k, L.nx, L.ny, L.nz);
+  T s = b[nb.c];
+  s = s + L.cx[nb.c] * (b[nb.xp] / d[nb.xp]) + L.cx[nb.xm] * (b[nb.xm] / d[nb.xm]);
+  s = s + L.cy[nb.c] * (b[nb.yp] / d[nb.yp]) + L.cy[nb.ym] * (b[nb.ym] / d[nb.ym]);
+  s = s + L.cz[nb.c] * (b[nb.zp] / d[nb.zp]) + L.cz[nb.zm] * (b[nb.zm] / d[nb.zm]);
+  xo[nb.c] = s / d[nb.c];
 }
 
 // coarsest-level solve in one workgroup: `sweeps` x (red, black) from x = 0,
@@ -663,12 +688,12 @@ __global__ __launch_bounds__(CS_THREADS) void k_coarse_solve_lds(Level<T> L, int
   for (int t = tid; t < 2 * n2; t += CS_THREADS) L.x[t] = xs[t];
 }
 
-template <class T>
+template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L) {
   const C3 c = coord3(L.ny, L.nz);
   if (!c.ok) return;
-  const int idx = (c.i * L.ny + c.j) * L.nz + c.k;
-  const Nb nb = nbrs(c.i, c.j, c.k, L.nx, L.ny, L.nz);
+  const Nb7 nb = nbrs7<SF>(c.i, c.j, c.k, L.nx, L.ny, L.nz);
+  const int idx = nb.c;
   const T* x = L.x;
   T y = L.diag[idx] * x[idx];
   y = y - L.cx[idx] * x[nb.xp] - L.cx[nb.xm] * x[nb.xm];
@@ -679,7 +704,7 @@ __global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L) {
 
 // b_coarse = R r_fine with R = P^T / 8: weights (1,3,3,1)/8 per axis over
 // fine cells 2I-1 .. 2I+2
-template <class T>
+template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C) {
   const C3 c = coord3(C.ny, C.nz);
   if (!c.ok) return;
@@ -696,10 +721,9 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int j = wrap(2 * J - 1 + b, F.ny);
-      const T* rr = F.r + (i * F.ny + j) * F.nz;
       T acc_k = T(0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc_k += w[q] * rr[kk[q]];
+      for (int q = 0; q < 4; ++q) acc_k += w[q] * F.r[lidx<SF>(i, j, kk[q], F.ny, F.nz)];
       acc_j += w[b] * acc_k;
     }
     acc += w[a] * acc_j;
@@ -711,13 +735,13 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C) {
 // (the parent's neighbour on the child's side) per axis.  With colour >= 0
 // only the cells of that colour are corrected: a post-smoothing that begins
 // with the other colour overwrites those cells without reading them.
-template <class T>
+template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_prolong_add(Level<T> C, Level<T> F, int colour) {
   const C3 c = coord3(F.ny, colour >= 0 ? F.nz >> 1 : F.nz);
   if (!c.ok) return;
   const int i = c.i, j = c.j;
   const int k = colour >= 0 ? 2 * c.k + ((i + j + colour) & 1) : c.k;
-  const int idx = (i * F.ny + j) * F.nz + k;
+  const int idx = lidx<SF>(i, j, k, F.ny, F.nz);
   const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
   const int I1 = wrap(I0 + ((i & 1) ? 1 : -1), C.nx);
   const int J1 = wrap(J0 + ((j & 1) ? 1 : -1), C.ny);
@@ -735,14 +759,14 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_add(Level<T> C, Level<T> F, i
 // coarse operator: mean local part over the 8 children; face couplings from
 // the series (harmonic) coupling along the normal, mean over the 2x2 fine
 // columns, times 1/4; diag = local + sum
-template <class T>
+template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_coarsen(Level<T> F, Level<T> C) {
   const C3 c = coord3(C.ny, C.nz);
   if (!c.ok) return;
   const int I = c.i, J = c.j, K = c.k;
   const int idx = (I * C.ny + J) * C.nz + K;
   auto fi = [&](int i, int j, int k) {
-    return (wrap(i, F.nx) * F.ny + wrap(j, F.ny)) * F.nz + wrap(k, F.nz);
+    return lidx<SF>(wrap(i, F.nx), wrap(j, F.ny), wrap(k, F.nz), F.ny, F.nz);
   };
   T local = T(0);
   for (int a = 0; a < 2; ++a)
@@ -785,6 +809,15 @@ __global__ __launch_bounds__(BLOCK) void k_coarsen(Level<T> F, Level<T> C) {
   C.cy[idx] = cyp;
   C.cz[idx] = czp;
   C.diag[idx] = local + (((cxp + cxm) + (cyp + cym)) + (czp + czm));
+}
+
+// FP64 natural -> FP32 colour-split finest level
+__global__ __launch_bounds__(BLOCK) void k_cvt_d2f_split(int nx, int ny, int nz,
+                                                          const double* __restrict__ a,
+                                                          float* __restrict__ b) {
+  const C3 c = coord3(ny, nz);
+  if (!c.ok) return;
+  b[lidx<true>(c.i, c.j, c.k, ny, nz)] = (float)a[(c.i * ny + c.j) * nz + c.k];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cvt_d2f(long n, const double* __restrict__ a,
@@ -919,20 +952,27 @@ template <class T>
 void launch_fill(long n, T* x, T v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<T>, grid_for(n), dim3(BLOCK), 0, st, n, x, v);
 }
+// a finest level of the FP32 cycle may be colour-split (Level::split); the
+// launchers pick the matching instantiation
+#define RT_LAYOUT(L, KERN, T, ...)                                                     \
+  do {                                                                                 \
+    if ((L).split) hipLaunchKernelGGL((KERN<T, true>), __VA_ARGS__);                   \
+    else hipLaunchKernelGGL((KERN<T, false>), __VA_ARGS__);                            \
+  } while (0)
 template <class T>
 void launch_rbgs(const Level<T>& L, int colour, hipStream_t st) {
   const Geo q = geo3(L.nx, L.ny, L.nz / 2);
-  hipLaunchKernelGGL(k_rbgs<T>, q.g, q.b, 0, st, L, colour);
+  RT_LAYOUT(L, k_rbgs, T, q.g, q.b, 0, st, L, colour);
 }
 template <class T>
-void launch_rbgs_first_pair(const Level<T>& L, T* xo, const double* b64, hipStream_t st) {
+void launch_rbgs_first_pair(const Level<T>& L, T* xo, hipStream_t st) {
   const Geo q = geo3(L.nx, L.ny, L.nz);
-  hipLaunchKernelGGL(k_rbgs_first_pair<T>, q.g, q.b, 0, st, L, xo, b64);
+  RT_LAYOUT(L, k_rbgs_first_pair, T, q.g, q.b, 0, st, L, xo);
 }
 template <class T>
 void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, hipStream_t st) {
   const Geo q = geo3(L.nx, L.ny, L.nz / 2);
-  hipLaunchKernelGGL(k_rbgs_out64<T>, q.g, q.b, 0, st, L, colour, out64);
+  RT_LAYOUT(L, k_rbgs_out64, T, q.g, q.b, 0, st, L, colour, out64);
 }
 template <class T>
 void launch_coarse_solve_lds(const Level<T>& L, int sweeps, hipStream_t st) {
@@ -945,22 +985,31 @@ void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st) {
 template <class T>
 void launch_mg_residual(const Level<T>& L, hipStream_t st) {
   const Geo q = geo3(L.nx, L.ny, L.nz);
-  hipLaunchKernelGGL(k_mg_residual<T>, q.g, q.b, 0, st, L);
+  RT_LAYOUT(L, k_mg_residual, T, q.g, q.b, 0, st, L);
 }
 template <class T>
 void launch_restrict(const Level<T>& F, const Level<T>& C, hipStream_t st) {
   const Geo q = geo3(C.nx, C.ny, C.nz);
-  hipLaunchKernelGGL(k_restrict<T>, q.g, q.b, 0, st, F, C);
+  RT_LAYOUT(F, k_restrict, T, q.g, q.b, 0, st, F, C);
 }
 template <class T>
 void launch_prolong_add(const Level<T>& C, const Level<T>& F, int colour, hipStream_t st) {
   const Geo q = geo3(F.nx, F.ny, colour >= 0 ? F.nz / 2 : F.nz);
-  hipLaunchKernelGGL(k_prolong_add<T>, q.g, q.b, 0, st, C, F, colour);
+  RT_LAYOUT(F, k_prolong_add, T, q.g, q.b, 0, st, C, F, colour);
 }
 template <class T>
 void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st) {
   const Geo q = geo3(C.nx, C.ny, C.nz);
-  hipLaunchKernelGGL(k_coarsen<T>, q.g, q.b, 0, st, F, C);
+  RT_LAYOUT(F, k_coarsen, T, q.g, q.b, 0, st, F, C);
+}
+void launch_cvt_d2f_level(const Level<float>& L, const double* a, float* b, hipStream_t st) {
+  if (L.split) {
+    const Geo q = geo3(L.nx, L.ny, L.nz);
+    hipLaunchKernelGGL(k_cvt_d2f_split, q.g, q.b, 0, st, L.nx, L.ny, L.nz, a, b);
+  } else {
+    const long n = (long)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_cvt_d2f, grid_for(n), dim3(BLOCK), 0, st, n, a, b);
+  }
 }
 void launch_fold_energy(int N, double* U, double* eh, hipStream_t st) {
   hipLaunchKernelGGL(k_fold_energy, grid_for(N), dim3(BLOCK), 0, st, N, U, eh);
@@ -975,7 +1024,7 @@ void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st) {
 #define RT_INST(T)                                                                   \
   template void launch_fill<T>(long, T*, T, hipStream_t);                            \
   template void launch_rbgs<T>(const Level<T>&, int, hipStream_t);                   \
-  template void launch_rbgs_first_pair<T>(const Level<T>&, T*, const double*, hipStream_t); \
+  template void launch_rbgs_first_pair<T>(const Level<T>&, T*, hipStream_t);         \
   template void launch_rbgs_out64<T>(const Level<T>&, int, double*, hipStream_t); \
   template void launch_coarse_solve<T>(const Level<T>&, int, hipStream_t);           \
   template void launch_coarse_solve_lds<T>(const Level<T>&, int, hipStream_t); \
