@@ -513,6 +513,18 @@ __device__ inline int lidx(int i, int j, int k, int ny, int nz) {
   if constexpr (SF) return (i * ny + j) * nz + ((i + j + k) & 1) * (nz >> 1) + (k >> 1);
   else return (i * ny + j) * nz + k;
 }
+// k of the cell stored at place q of row (i, j): threads that walk a row in
+// storage order touch consecutive addresses
+template <bool SF>
+__device__ inline int stored_k(int i, int j, int q, int nz) {
+  if constexpr (SF) {
+    const int hz = nz >> 1;
+    const int c = q >= hz ? 1 : 0;
+    return 2 * (q - c * hz) + ((c + i + j) & 1);
+  } else {
+    return q;
+  }
+}
 struct Nb7 {
   int c, xm, xp, ym, yp, zm, zp;
 };
@@ -583,14 +595,15 @@ template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_rbgs_first_pair(Level<T> L, T* __restrict__ xo) {
   const C3 c = coord3(L.ny, L.nz);
   if (!c.ok) return;
+  const int k = stored_k<SF>(c.i, c.j, c.k, L.nz);
   const T* b = L.b;
   const T* d = L.diag;
-  if (((c.i + c.j + c.k) & 1) == 0) {
-    const int idx = lidx<SF>(c.i, c.j, c.k, L.ny, L.nz);
+  if (((c.i + c.j + k) & 1) == 0) {
+    const int idx = lidx<SF>(c.i, c.j, k, L.ny, L.nz);
     xo[idx] = b[idx] / d[idx];
     return;
   }
-  const Nb7 nb = nbrs7<SF>(c.i, c.j, c.k, L.nx, L.ny, L.nz);
+  const Nb7 nb = nbrs7<SF>(c.i, c.j, k, L.nx, L.ny, L.nz);
   T s = b[nb.c];
   s = s + L.cx[nb.c] * (b[nb.xp] / d[nb.xp]) + L.cx[nb.xm] * (b[nb.xm] / d[nb.xm]);
   s = s + L.cy[nb.c] * (b[nb.yp] / d[nb.yp]) + L.cy[nb.ym] * (b[nb.ym] / d[nb.ym]);
@@ -692,7 +705,7 @@ template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L) {
   const C3 c = coord3(L.ny, L.nz);
   if (!c.ok) return;
-  const Nb7 nb = nbrs7<SF>(c.i, c.j, c.k, L.nx, L.ny, L.nz);
+  const Nb7 nb = nbrs7<SF>(c.i, c.j, stored_k<SF>(c.i, c.j, c.k, L.nz), L.nx, L.ny, L.nz);
   const int idx = nb.c;
   const T* x = L.x;
   T y = L.diag[idx] * x[idx];
@@ -740,7 +753,7 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_add(Level<T> C, Level<T> F, i
   const C3 c = coord3(F.ny, colour >= 0 ? F.nz >> 1 : F.nz);
   if (!c.ok) return;
   const int i = c.i, j = c.j;
-  const int k = colour >= 0 ? 2 * c.k + ((i + j + colour) & 1) : c.k;
+  const int k = colour >= 0 ? 2 * c.k + ((i + j + colour) & 1) : stored_k<SF>(i, j, c.k, F.nz);
   const int idx = lidx<SF>(i, j, k, F.ny, F.nz);
   const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
   const int I1 = wrap(I0 + ((i & 1) ? 1 : -1), C.nx);
@@ -817,7 +830,8 @@ __global__ __launch_bounds__(BLOCK) void k_cvt_d2f_split(int nx, int ny, int nz,
                                                           float* __restrict__ b) {
   const C3 c = coord3(ny, nz);
   if (!c.ok) return;
-  b[lidx<true>(c.i, c.j, c.k, ny, nz)] = (float)a[(c.i * ny + c.j) * nz + c.k];
+  const int k = stored_k<true>(c.i, c.j, c.k, nz);
+  b[(c.i * ny + c.j) * nz + c.k] = (float)a[(c.i * ny + c.j) * nz + k];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cvt_d2f(long n, const double* __restrict__ a,
