@@ -58,58 +58,99 @@ __device__ inline int off_cell(const Geo& g, int i, int j, int k, int o) {
 }
 
 // --------------------------------------------------------------------------
-// forward / data-gradient convolution: one wave per 16 cells x 16 channels.
+// forward / data-gradient convolution, marching through x-planes.  A block
+// owns a TJ x TK (y, z) tile and walks PI consecutive x-planes; the input of
+// three planes over the tile plus a one-cell halo sits in LDS (slot = plane
+// mod 3, 32 B per cell), so each input cell is fetched from memory about
+// once per plane rather than once per kernel offset, and every lane keeps
+// its 27 weight fragments (MFMA A operands) in registers.  A wave computes
+// 16 (co) x 16 (cells along z) tiles with 27 MFMAs in offset order.
 // mode 0: forward, out = act(bias + W * in); act = LeakyReLU if leaky.
 // mode 1: data gradient, out = (sum_o Wt_o g[cell + off_o]) * leaky'(hprev),
-//         Wt_o = W_{26-o}^T.
+//         Wt_o = W_{26-o}^T (both modes read the source at +off_o).
 // last: write FP32 SoA [nout][N] instead of BF16 channels-last.
-__global__ __launch_bounds__(256) void k_conv(Geo g, const bf16* __restrict__ in,
+struct Tile {
+  int TJ, TK, PI, ntj, ntk;
+};
+__global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restrict__ in,
                                               const bf16* __restrict__ W,     // [27][16][16]
                                               const float* __restrict__ bias, int mode,
                                               int leaky, const bf16* __restrict__ hprev,
                                               bf16* __restrict__ out, float* __restrict__ out32,
                                               int nout) {
+  extern __shared__ __align__(16) char lds[];
+  const int RJ = T.TJ + 2, RK = T.TK + 2;
   const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int cpr = g.nz >> 4;                        // 16-cell chunks per row
-  if (wave >= g.N / 16) return;
-  const int row = wave / cpr;
-  const int k = ((wave - row * cpr) << 4) + (lane & 15);
-  const int j = row % g.ny;
-  const int i = row / g.ny;
-  const int cell = row * g.nz + k;
+  const int wv = threadIdx.x >> 6;
   const int q = lane >> 4;                          // channel quad
-  v4f acc = {0.f, 0.f, 0.f, 0.f};
-  // data gradient: gin[Q] = sum_o W_{26-o}^T g[Q + off_o] (off_{26-o} = -off_o),
-  // so both modes read the source at +off_o and differ only in the weights
-#pragma unroll 3
-  for (int o = 0; o < NOFF; ++o) {
-    const int src = off_cell(g, i, j, k, o);
-    const v4s b = *reinterpret_cast<const v4s*>(in + (size_t)src * CH + 4 * q);
-    const v4s a = *reinterpret_cast<const v4s*>(W + (o * CH + (lane & 15)) * CH + 4 * q);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-  }
-  float v[4] = {acc[0], acc[1], acc[2], acc[3]};
-  if (mode == 0) {
+  const int col = lane & 15;
+  int blk = blockIdx.x;
+  const int tk = blk % T.ntk;
+  blk /= T.ntk;
+  const int tj = blk % T.ntj;
+  const int i0 = (blk / T.ntj) * T.PI;
+  const int j0 = tj * T.TJ, k0 = tk * T.TK;
+  v4s a[NOFF];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      v[t] += bias[4 * q + t];
-      if (leaky) v[t] = v[t] > 0.f ? v[t] : LEAK * v[t];
+  for (int o = 0; o < NOFF; ++o)
+    a[o] = *reinterpret_cast<const v4s*>(W + (o * CH + col) * CH + 4 * q);
+  const int slot_bytes = RJ * RK * 32;
+  auto slot = [&](int p) { return lds + ((p % 3 + 3) % 3) * slot_bytes; };
+  auto load_plane = [&](int p) {
+    const int ip = wrapi(p, g.nx);
+    char* s = slot(p);
+    for (int t = threadIdx.x; t < RJ * RK * 2; t += 256) {
+      const int cr = t >> 1, h = t & 1;
+      const int r = cr / RK, c = cr - r * RK;
+      const int j = wrapi(j0 - 1 + r, g.ny), k = wrapi(k0 - 1 + c, g.nz);
+      const size_t src = ((size_t)(ip * g.ny + j) * g.nz + k) * CH + 8 * h;
+      *reinterpret_cast<uint4*>(s + cr * 32 + 16 * h) = *reinterpret_cast<const uint4*>(in + src);
     }
-  } else if (hprev) {
-    const v4s hp = *reinterpret_cast<const v4s*>(hprev + (size_t)cell * CH + 4 * q);
+  };
+  const int cpr = T.TK >> 4;                        // 16-cell chunks per tile row
+  const int nch = T.TJ * cpr;
+  load_plane(i0 - 1);
+  load_plane(i0);
+  for (int i = i0; i < i0 + T.PI; ++i) {
+    load_plane(i + 1);   // the slot of plane i - 2, read last by plane i - 1
+    __syncthreads();
+    for (int ch = wv; ch < nch; ch += 4) {
+      const int jj = ch / cpr;
+      const int kc = (ch - jj * cpr) << 4;
+      v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] *= bf2f((bf16)hp[t]) > 0.f ? 1.f : LEAK;
-  }
-  if (out32) {
+      for (int o = 0; o < NOFF; ++o) {
+        const int di = o / 9 - 1, dj = (o / 3) % 3 - 1, dk = o % 3 - 1;
+        const char* s = slot(i + di);
+        const v4s b = *reinterpret_cast<const v4s*>(
+            s + ((jj + 1 + dj) * RK + (kc + col + 1 + dk)) * 32 + 8 * q);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[o], b, acc, 0, 0, 0);
+      }
+      const int cell = (i * g.ny + j0 + jj) * g.nz + k0 + kc + col;
+      float v[4] = {acc[0], acc[1], acc[2], acc[3]};
+      if (mode == 0) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (4 * q + t < nout) out32[(size_t)(4 * q + t) * g.N + cell] = v[t];
-  } else {
-    v4s r;
+        for (int t = 0; t < 4; ++t) {
+          v[t] += bias[4 * q + t];
+          if (leaky) v[t] = v[t] > 0.f ? v[t] : LEAK * v[t];
+        }
+      } else if (hprev) {
+        const v4s hp = *reinterpret_cast<const v4s*>(hprev + (size_t)cell * CH + 4 * q);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) r[t] = (short)f2bf(v[t]);
-    *reinterpret_cast<v4s*>(out + (size_t)cell * CH + 4 * q) = r;
+        for (int t = 0; t < 4; ++t) v[t] *= bf2f((bf16)hp[t]) > 0.f ? 1.f : LEAK;
+      }
+      if (out32) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (4 * q + t < nout) out32[(size_t)(4 * q + t) * g.N + cell] = v[t];
+      } else {
+        v4s r;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) r[t] = (short)f2bf(v[t]);
+        *reinterpret_cast<v4s*>(out + (size_t)cell * CH + 4 * q) = r;
+      }
+    }
+    __syncthreads();     // plane i's slots are read: plane i + 2 may replace i - 1
   }
 }
 
@@ -478,10 +519,32 @@ void pack_all(rt_net* n) {
                        n->bias + 16 * l);
 }
 
+// tile of the plane-marching convolution: TK in {64, 32, 16} dividing nz,
+// TJ in {4, 2, 1} dividing ny, and the longest march in {16, 8, 4, 2}
+// dividing nx that still leaves at least 512 blocks
+Tile conv_tile(const Geo& g) {
+  Tile t;
+  t.TK = g.nz % 64 == 0 ? 64 : (g.nz % 32 == 0 ? 32 : 16);
+  t.TJ = g.ny % 4 == 0 ? 4 : (g.ny % 2 == 0 ? 2 : 1);
+  t.ntj = g.ny / t.TJ;
+  t.ntk = g.nz / t.TK;
+  t.PI = 1;
+  for (int c : {16, 8, 4, 2}) {
+    if (g.nx % c == 0 && (long)t.ntj * t.ntk * (g.nx / c) >= 512) {
+      t.PI = c;
+      break;
+    }
+  }
+  return t;
+}
+
 void launch_conv(rt_net* n, const bf16* in, int layer, int mode, int leaky, const bf16* hprev,
                  bf16* out, float* out32) {
   const bf16* W = (mode == 0 ? n->Wf : n->Wt) + layer * NOFF * 256;
-  hipLaunchKernelGGL(k_conv, dim3(nb(n->g.N / 16, 4)), dim3(256), 0, n->st, n->g, in, W,
+  const Tile t = conv_tile(n->g);
+  const unsigned blocks = (unsigned)((long)t.ntj * t.ntk * (n->g.nx / t.PI));
+  const size_t lds = (size_t)3 * (t.TJ + 2) * (t.TK + 2) * 32;
+  hipLaunchKernelGGL(k_conv, dim3(blocks), dim3(256), lds, n->st, n->g, t, in, W,
                      n->bias + 16 * layer, mode, leaky, hprev, out, out32, n->nout);
 }
 
