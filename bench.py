@@ -43,6 +43,8 @@ HBM_PEAK_GBS = 8000.0
 #              the other colour's x, write the colour's x              = (3 + 1) w + 1 w = 5 w
 #              first (red, black) pair from x = 0, one launch: diag, b,
 #              the 3 couplings, write x                                = 6 w
+#              FP32 cycle's last half-sweep: 4 w, write z (FP64, both
+#              colours), read r and q (FP64) for the CG dots           = 4 w + 24 B
 # (w = 4 B for the FP32 V-cycle, 8 B for FP64)
 BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0}
 
@@ -63,9 +65,15 @@ def kernels_sha256():
 
 
 def rbgs_fine_per_vcycle(pre, post, w):
-    """(launches, algorithmic bytes per cell) of the fine-level smoothing in one V-cycle."""
+    """(launches, algorithmic bytes per cell) of the fine-level smoothing in one
+    V-cycle of the CG loop; in the FP32 cycle the last half-sweep writes the
+    FP64 result and forms the CG dots (pre, post > 0 there)."""
     if pre > 0:
-        return 1 + 2 * (pre - 1) + 2 * post, 6.0 * w + (2 * (pre - 1) + 2 * post) * 5.0 * w
+        launches = 1 + 2 * (pre - 1) + 2 * post
+        b = 6.0 * w + (2 * (pre - 1) + 2 * post) * 5.0 * w
+        if w == 4.0 and post > 0:
+            b += (4.0 * w + 24.0) - 5.0 * w
+        return launches, b
     return 2 * post, 2 * post * 5.0 * w
 
 

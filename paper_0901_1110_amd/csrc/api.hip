@@ -237,7 +237,8 @@ Step step_new(double dt, const rt_cosmo* c) { return Step{dt, c->a_new, c->H_new
 // out64 (finest level of the FP32 cycle only): the last smoothing launch
 // writes the result widened to this FP64 vector itself
 template <class T>
-void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, double* out64 = nullptr) {
+void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, double* out64 = nullptr,
+            const double* r64 = nullptr, const double* q64 = nullptr, double* parts = nullptr) {
   const rt_params& p = g->prm;
   hipStream_t st = g->st;
   Level<T>& L = Ls[l];
@@ -273,7 +274,7 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, double* out64 = nullpt
   for (int s = 0; s < post; ++s) {
     TK(g, kc, launch_rbgs<T>(L, 1, st));
     if (out64 && s + 1 == post) {
-      TK(g, kc, launch_rbgs_out64<T>(L, 0, out64, st));
+      TK(g, kc, launch_rbgs_out64<T>(L, 0, out64, r64, q64, parts, st));
     } else {
       TK(g, kc, launch_rbgs<T>(L, 0, st));
     }
@@ -299,27 +300,34 @@ int build_hierarchy(rt_grid* g) {
   return RT_OK;
 }
 
-// z = V r on the current hierarchy
-void apply_vcycle(rt_grid* g, const double* r, double* z) {
+// z = V r on the current hierarchy.  With dots set, the FP32 cycle's last
+// half-sweep also leaves the block partials of z.r and z.q (q = w.q) in
+// w.parts and the call returns their count; otherwise it returns 0.
+int apply_vcycle(rt_grid* g, const double* r, double* z, bool dots = false) {
   Workspace& w = g->w;
   const long N = g->P.N;
   if (!g->prm.mg_fp32) {
     w.L64[0].b = const_cast<double*>(r);
     w.L64[0].x = z;
     vcycle<double>(g, w.L64, 0);
-  } else {
-    Level<float>& L0 = w.L32[0];
-    if (fp32_fused(&g->prm)) {
-      // r is converted (into the colour-split layout) by a pass of its own:
-      // read at seven points by the first pair, FP64 r costs more than it saves
-      TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f_level(L0, r, L0.b, g->st));
-      vcycle<float>(g, w.L32, 0, z);
-    } else {
-      TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
-      vcycle<float>(g, w.L32, 0);
-      TK(g, RT_K_MG_TRANSFER, launch_cvt_f2d(N, L0.x, z, g->st));
-    }
+    return 0;
   }
+  Level<float>& L0 = w.L32[0];
+  if (fp32_fused(&g->prm)) {
+    // r is converted (into the colour-split layout) by a pass of its own:
+    // read at seven points by the first pair, FP64 r costs more than it saves
+    TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f_level(L0, r, L0.b, g->st));
+    if (dots) {
+      vcycle<float>(g, w.L32, 0, z, r, w.q, w.parts);
+      return stencil_blocks(L0.nx, L0.ny, L0.nz / 2);
+    }
+    vcycle<float>(g, w.L32, 0, z);
+    return 0;
+  }
+  TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
+  vcycle<float>(g, w.L32, 0);
+  TK(g, RT_K_MG_TRANSFER, launch_cvt_f2d(N, L0.x, z, g->st));
+  return 0;
 }
 
 int read_scalars(rt_grid* g, const double* d, double* h, int n) {
@@ -368,10 +376,14 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   // turns out converged, the enqueued tail is discarded work and x is final.
   constexpr double LOOKAHEAD = 30.0;
   auto tail = [&]() {
-    apply_vcycle(g, w.r, w.z);
+    const int nd = apply_vcycle(g, w.r, w.z, true);
     ++*vcycles;
-    TK(g, RT_K_CG_VECTOR, launch_dot2(N, w.z, w.r, w.q, w.parts, g->st));
-    finish_reduce(g, nparts, 2, S_ZR);
+    if (nd > 0) {
+      finish_reduce(g, nd, 2, S_ZR);
+    } else {
+      TK(g, RT_K_CG_VECTOR, launch_dot2(N, w.z, w.r, w.q, w.parts, g->st));
+      finish_reduce(g, nparts, 2, S_ZR);
+    }
     TK(g, RT_K_REDUCE, launch_cg_beta(w.sc, g->st));
     TK(g, RT_K_CG_VECTOR, launch_update_p(N, w.p, w.z, w.sc, g->st));
   };

@@ -74,8 +74,11 @@ template <class T> void launch_fill(long n, T* x, T v, hipStream_t st);
 template <class T> void launch_rbgs(const Level<T>& L, int colour, hipStream_t st);
 // first (red, black) pair from x = 0
 template <class T> void launch_rbgs_first_pair(const Level<T>& L, T* xo, hipStream_t st);
-// half-sweep whose result (both colours) goes widened to out64 instead of x
-template <class T> void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, hipStream_t st);
+// half-sweep whose result (both colours) goes widened to out64 instead of x;
+// parts non-null: also the block partials of out64.r64 and out64.q64
+template <class T>
+void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, const double* r64,
+                       const double* q64, double* parts, hipStream_t st);
 template <class T> void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st);
 // coarsest solve with the level in registers and LDS (n <= COARSE_LDS_MAX)
 template <class T> void launch_coarse_solve_lds(const Level<T>& L, int sweeps, hipStream_t st);

@@ -569,23 +569,36 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs(Level<T> L, int colour) {
 // the last half-sweep of a V-cycle with the result widened into a FP64
 // vector (natural layout): the thread of cell k also copies its pair partner
 // k ^ 1 (the other colour, final already), so out64 receives every cell and x
-// is not stored
+// is not stored.  With parts given, the block partials of out64.r64 and
+// out64.q64 (the CG dots that follow the V-cycle) are formed on the way.
 template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_rbgs_out64(Level<T> L, int colour,
-                                                      double* __restrict__ out64) {
+                                                      double* __restrict__ out64,
+                                                      const double* __restrict__ r64,
+                                                      const double* __restrict__ q64,
+                                                      double* __restrict__ parts) {
+  double acc[2] = {0.0, 0.0};
   const C3 c = coord3(L.ny, L.nz >> 1);
-  if (!c.ok) return;
-  const int i = c.i, j = c.j;
-  const int k = 2 * c.k + ((i + j + colour) & 1);
-  const int row = (i * L.ny + j) * L.nz;
-  const Nb7 nb = nbrs7<SF>(i, j, k, L.nx, L.ny, L.nz);
-  const T* x = L.x;
-  T s = L.b[nb.c];
-  s = s + L.cx[nb.c] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
-  s = s + L.cy[nb.c] * x[nb.yp] + L.cy[nb.ym] * x[nb.ym];
-  s = s + L.cz[nb.c] * x[nb.zp] + L.cz[nb.zm] * x[nb.zm];
-  out64[row + k] = (double)(s / L.diag[nb.c]);
-  out64[row + (k ^ 1)] = (double)x[lidx<SF>(i, j, k ^ 1, L.ny, L.nz)];
+  if (c.ok) {
+    const int i = c.i, j = c.j;
+    const int k = 2 * c.k + ((i + j + colour) & 1);
+    const int row = (i * L.ny + j) * L.nz;
+    const Nb7 nb = nbrs7<SF>(i, j, k, L.nx, L.ny, L.nz);
+    const T* x = L.x;
+    T s = L.b[nb.c];
+    s = s + L.cx[nb.c] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
+    s = s + L.cy[nb.c] * x[nb.yp] + L.cy[nb.ym] * x[nb.ym];
+    s = s + L.cz[nb.c] * x[nb.zp] + L.cz[nb.zm] * x[nb.zm];
+    const double z0 = (double)(s / L.diag[nb.c]);
+    const double z1 = (double)x[lidx<SF>(i, j, k ^ 1, L.ny, L.nz)];
+    out64[row + k] = z0;
+    out64[row + (k ^ 1)] = z1;
+    if (parts) {
+      acc[0] = z0 * r64[row + k] + z1 * r64[row + (k ^ 1)];
+      acc[1] = z0 * q64[row + k] + z1 * q64[row + (k ^ 1)];
+    }
+  }
+  if (parts) block_reduce<2>(acc, parts);
 }
 
 // the first (red, black) pair from x = 0 in one pass: red cells take b/diag,
@@ -984,9 +997,10 @@ void launch_rbgs_first_pair(const Level<T>& L, T* xo, hipStream_t st) {
   RT_LAYOUT(L, k_rbgs_first_pair, T, q.g, q.b, 0, st, L, xo);
 }
 template <class T>
-void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, hipStream_t st) {
+void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, const double* r64,
+                       const double* q64, double* parts, hipStream_t st) {
   const Geo q = geo3(L.nx, L.ny, L.nz / 2);
-  RT_LAYOUT(L, k_rbgs_out64, T, q.g, q.b, 0, st, L, colour, out64);
+  RT_LAYOUT(L, k_rbgs_out64, T, q.g, q.b, 0, st, L, colour, out64, r64, q64, parts);
 }
 template <class T>
 void launch_coarse_solve_lds(const Level<T>& L, int sweeps, hipStream_t st) {
@@ -1039,7 +1053,7 @@ void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st) {
   template void launch_fill<T>(long, T*, T, hipStream_t);                            \
   template void launch_rbgs<T>(const Level<T>&, int, hipStream_t);                   \
   template void launch_rbgs_first_pair<T>(const Level<T>&, T*, hipStream_t);         \
-  template void launch_rbgs_out64<T>(const Level<T>&, int, double*, hipStream_t); \
+  template void launch_rbgs_out64<T>(const Level<T>&, int, double*, const double*, const double*, double*, hipStream_t); \
   template void launch_coarse_solve<T>(const Level<T>&, int, hipStream_t);           \
   template void launch_coarse_solve_lds<T>(const Level<T>&, int, hipStream_t); \
   template void launch_mg_residual<T>(const Level<T>&, hipStream_t);                 \
