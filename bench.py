@@ -54,8 +54,8 @@ BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0
 # what the counters read for a plain 2 GiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0), averaged over one V-cycle's 7 launches.  It belongs to the
 # kernel source it was measured on and is reported as null for any other.
-PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "bytes_per_launch": 6.049e8,
-                             "kernels_sha256": "a4c0ec13ade1a0037a439159b879ff8035a3a0256fa392e0931770880fc9fa57"}}
+PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "bytes_per_launch": 4.375e8,
+                             "kernels_sha256": "ff574398d9996a21cec12b41d0fe264d78d775efedefe6bdf6610914bdec351c"}}
 
 
 def kernels_sha256():
