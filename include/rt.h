@@ -85,6 +85,12 @@ typedef struct rt_params {
                             /* of Newton iteration k also stops once ||r||_2 =       */
                             /* ||J S_k + f(U_k)||_2 <= pcg_forcing ||f(U_k)||_2 (the  */
                             /* paper's delta_k = 1e-6 ||f||); 0: relative test alone */
+  int32_t box_size;         /* > 0: add to every V-cycle a subdomain correction: a */
+                            /* box of box_size^3 cells centred on each source,    */
+                            /* solved by box_inner PCG iterations with its own    */
+                            /* box_levels-level V-cycle (0: V-cycle alone)        */
+  int32_t box_levels;
+  int32_t box_inner;
 } rt_params;
 
 /* Scale factor a and adot/a at t^n (old) and t^{n+1} (new). */
@@ -198,10 +204,11 @@ enum {
   RT_K_RBGS_FINE,       /* red-black Gauss-Seidel half sweep, finest level */
   RT_K_RBGS_COARSE,     /* same, coarser levels */
   RT_K_MG_TRANSFER,     /* multigrid residual, restriction, prolongation */
-  RT_K_MG_SETUP,        /* coarse operators and precision conversion */
+  RT_K_MG_SETUP,        /* coarse and box operators, precision conversion */
   RT_K_SPMV,            /* Schur matrix-vector product + dot */
   RT_K_CG_VECTOR,       /* CG updates and dots */
   RT_K_REDUCE,          /* final reductions and CG scalars */
+  RT_K_BOX,             /* source-subdomain correction (one entry per graph replay) */
   RT_K_OTHER,
   RT_K_COUNT
 };
@@ -220,6 +227,15 @@ int rt_timing(rt_grid* g, int32_t enable, rt_kernel_timing* out);
  * class does not pay two event records on every other launch.  Takes effect
  * for launches after the call; RT_EINVAL for a null grid. */
 int rt_timing_classes(rt_grid* g, uint32_t mask);
+
+/* The source-subdomain correction (box_size > 0) issues a few hundred small
+ * launches per V-cycle; by default the library captures them once into a
+ * HIP graph (on a private stream) and replays it, re-capturing when the
+ * number of sources changes.  enable = 0 issues them one by one instead:
+ * the same kernels in the same order, so the results are identical.  A
+ * timed correction counts as one RT_K_BOX entry per replay.  RT_EINVAL for
+ * a null grid. */
+int rt_use_graphs(rt_grid* g, int32_t enable);
 
 /* Spectrum constants of Sec. 3.2.5 (Eq. 45) for a monochromatic 13.6 eV
  * (grey = 0) or a T_B blackbody (grey = 1) spectrum, by host quadrature. */

@@ -22,6 +22,7 @@ V(l): x = 0; nu1 x (red, black); r = b - A x; V(l+1) on R r; x += P e;
   nu2 x (black, red).  Coarsest: k x (red, black) then k x (black, red).
 PCG: flexible (Polak-Ribiere) beta, x0 = 0, stop when ||r||_2 <= rtol ||b||_2
   or, in a Newton step with a forcing factor, ||r||_2 <= forcing ||f(U_k)||_2.
+  Optional source-subdomain correction added to the V-cycle (see pcg).
 """
 from __future__ import annotations
 
@@ -144,18 +145,85 @@ def vcycle(b, ops, model, level=0, dtype=np.float64):
     return x
 
 
-def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0):
+def box_cells(centre, B, shape):
+    """Index arrays of the B^3 box centred on `centre` (periodic wrap)."""
+    return [(np.arange(B) - B // 2 + c) % n for c, n in zip(centre, shape)]
+
+
+def box_operator(op, centres, B):
+    """The operator restricted to boxes around `centres`, stacked along x:
+    diagonal unchanged, couplings inside a box kept, couplings out of a box
+    (its last layer in each direction) zero."""
+    shape = op[0].shape
+    parts = [[], [], [], []]
+    for c in centres:
+        sel = np.ix_(*box_cells(c, B, shape))
+        parts[0].append(op[0][sel])
+        for d in range(3):
+            cd = op[1 + d][sel].copy()
+            last = [slice(None)] * 3
+            last[d] = B - 1
+            cd[tuple(last)] = 0.0
+            parts[1 + d].append(cd)
+    return tuple(np.concatenate(q, axis=0) for q in parts)
+
+
+def pcg_fixed(op, b, ops, model, k, dtype=np.float64):
+    """k iterations of flexible PCG from zero with the V-cycle on `ops`."""
+    def V(r):
+        return vcycle(r, ops, model, 0, dtype).astype(np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = V(r)
+    p = z.copy()
+    rho = np.sum(r * z)
+    for it in range(1, k + 1):
+        q = apply_schur(p, *op)
+        alpha = rho / np.sum(p * q)
+        x = x + alpha * p
+        r_old = r
+        r = r - alpha * q
+        if it == k:
+            break
+        z = V(r)
+        rho_new = np.sum(z * r)
+        beta = (rho_new - np.sum(z * r_old)) / rho
+        rho = rho_new
+        p = z + beta * p
+    return x
+
+
+def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=None):
     """Flexible PCG on S s = b; stops at ||r||_2 <= max(rtol ||b||_2, atol).
+    With model.box_size > 0 and source `centres` ((i, j, k) cells), the
+    preconditioner follows the V-cycle by the source-subdomain correction: on
+    a box_size^3 box around every source, model.box_inner iterations of
+    flexible PCG from zero for the operator restricted to the boxes, with its
+    own box_levels-level V-cycle, applied to the residual the V-cycle left;
+    the boxes' parts are added box by box.
     Returns (s, iterations, ||r||/||b||)."""
     rtol = model.pcg_rtol if rtol is None else rtol
     maxit = model.pcg_maxit if maxit is None else maxit
     ops = hierarchy(op, model.mg_levels) if precond else None
     dt = np.float32 if model.mg_fp32 else np.float64
+    boxes = (precond and model.box_size > 0 and centres is not None and len(centres) > 0)
+    if boxes:
+        B = model.box_size
+        bop = box_operator(op, centres, B)
+        bops = hierarchy(bop, model.box_levels)
+        sels = [np.ix_(*box_cells(c, B, op[0].shape)) for c in centres]
 
     def V(r):
         if not precond:
             return r.copy()
-        return vcycle(r, ops, model, 0, dt).astype(np.float64)
+        z = vcycle(r, ops, model, 0, dt).astype(np.float64)
+        if boxes:
+            res = r - apply_schur(z, *op)
+            rb = np.concatenate([res[sel] for sel in sels], axis=0)
+            y = pcg_fixed(bop, rb, bops, model, model.box_inner, dt)
+            for s_, sel in enumerate(sels):
+                z[sel] += y[s_ * B:(s_ + 1) * B]
+        return z
 
     x = np.zeros_like(b)
     bn = np.sqrt(np.sum(b * b))

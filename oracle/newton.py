@@ -104,7 +104,8 @@ def newton_step(Un, U0, nH, eh, src_cells, src_Q, dt, cosmo, model,
             # local rows are solved exactly, so ||J S + f||_2 is the Schur
             # residual norm, and ||f||_2 = sqrt(size) times the RMS norm
             atol = model.pcg_forcing * fn * np.sqrt(f.size)
-            sE, its, _ = mg.pcg(op, sch["b"], model, atol=atol)
+            centres = [np.unravel_index(int(c), U.shape[1:]) for c in src_cells]
+            sE, its, _ = mg.pcg(op, sch["b"], model, atol=atol, centres=centres)
         step = jacobian.recover(sE, sch) * scales
         st["cg_its"].append(its)
         lam = 1.0

@@ -36,6 +36,7 @@ class RtParams(ctypes.Structure):
         ("mg_levels", ctypes.c_int32), ("mg_pre", ctypes.c_int32), ("mg_post", ctypes.c_int32),
         ("mg_coarse_sweeps", ctypes.c_int32), ("mg_fp32", ctypes.c_int32),
         ("max_sources", ctypes.c_int32), ("pcg_forcing", ctypes.c_double),
+        ("box_size", ctypes.c_int32), ("box_levels", ctypes.c_int32), ("box_inner", ctypes.c_int32),
     ]
 
 
@@ -67,7 +68,7 @@ class RtNewtonStats(ctypes.Structure):
 
 
 RT_K_NAMES = ["timelevel", "residual", "trial", "schur", "rbgs_fine", "rbgs_coarse",
-              "mg_transfer", "mg_setup", "spmv", "cg_vector", "reduce", "other"]
+              "mg_transfer", "mg_setup", "spmv", "cg_vector", "reduce", "box", "other"]
 
 
 class RtKernelTiming(ctypes.Structure):
@@ -101,6 +102,7 @@ SIGNATURES = {
     "rt_fold_energy": [_P, _P, _P],
     "rt_timing": [_P, _I, ctypes.POINTER(RtKernelTiming)],
     "rt_timing_classes": [_P, ctypes.c_uint32],
+    "rt_use_graphs": [_P, ctypes.c_int32],
     "rt_spectrum_constants": [_I, _D, _P, _P, _P, ctypes.POINTER(_D)],
     "rt_net_workspace_bytes": [_I, _I, _I, _I, ctypes.POINTER(ctypes.c_uint64)],
     "rt_net_create": [_I, _I, _I, _I, _P, ctypes.c_uint64, _P, ctypes.POINTER(_P)],
@@ -189,6 +191,7 @@ def params_from_workload(w, **overrides) -> RtParams:
     p.mg_coarse_sweeps, p.mg_fp32 = w.mg_coarse_sweeps, w.mg_fp32
     p.max_sources = max(64, w.nsources)
     p.pcg_forcing = w.pcg_forcing
+    p.box_size, p.box_levels, p.box_inner = w.box_size, w.box_levels, w.box_inner
     for k, v in overrides.items():
         if k in ("K_gamma", "K_kappa", "K_heat"):
             getattr(p, k)[:] = list(v)
@@ -337,6 +340,10 @@ class RtGrid:
             for c in classes:
                 mask |= 1 << RT_K_NAMES.index(c)
         self._check(lib().rt_timing_classes(self.h, mask), "rt_timing_classes")
+
+    def rt_use_graphs(self, enable):
+        """False: the subdomain correction is issued launch by launch (no graph)."""
+        self._check(lib().rt_use_graphs(self.h, 1 if enable else 0), "rt_use_graphs")
 
     def rt_fold_energy(self, U, eh):
         return self._check(lib().rt_fold_energy(self.h, _ptr(U), _ptr(eh)), "rt_fold_energy")

@@ -49,6 +49,13 @@ struct Workspace {
   std::vector<Level<double>> L64;
   std::vector<Level<float>> L32;
   float* r32;   // FP32 copy of the CG residual fed to the V-cycle
+  // source subdomains: boxes of B^3 cells around the sources, stacked along x
+  int box_cap = 0;                        // boxes the workspace holds (max_sources)
+  double *bd, *bcx, *bcy, *bcz;           // box operator (FP64, level 0 of B64)
+  double *bxv, *br, *bz, *bp, *bq;        // inner PCG vectors
+  double *bparts, *bsc;
+  std::vector<Level<double>> B64;
+  std::vector<Level<float>> B32;
   size_t nparts_cap;
 };
 
@@ -75,7 +82,17 @@ struct rt_grid {
   bool mg_stale = true;     // coarse operators need rebuilding
   bool have_op = false;     // a Schur matrix is present
   double* hpin = nullptr;   // pinned host scalars for asynchronous read-back
+  int nbox = 0;             // active source subdomains (0: V-cycle alone)
+  int tk_override = -1;     // >= 0: time every launch under this class
   hipEvent_t ev_rd = nullptr;
+  // the source-subdomain correction as a captured graph (a few hundred small
+  // launches replayed by one), valid for the (r, z, nbox) it was captured for
+  bool graphs = true;
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t box_exec = nullptr;
+  const double* box_r = nullptr;
+  double* box_z = nullptr;
+  int box_n = 0;
   std::string err;
 };
 
@@ -96,6 +113,7 @@ int fail(rt_grid* g, int code, const char* fmt, ...) {
 // record a start event (returns the slot) / stop event around a launch
 inline long tstart(rt_grid* g, int cls) {
   Timer& t = g->tm;
+  if (g->tk_override >= 0) cls = g->tk_override;
   if (!t.on || !((t.mask >> cls) & 1u)) return -1;
   if (t.used + 2 > t.pool.size()) {
     const size_t grow = t.pool.size() < 1024 ? 1024 : t.pool.size();
@@ -160,6 +178,15 @@ int validate(const rt_params* p, std::string* why) {
   if (p->max_sources < 0) return bad("max_sources < 0");
   if (!(p->pcg_forcing >= 0.0) || !std::isfinite(p->pcg_forcing)) return bad("pcg_forcing must be finite and >= 0");
   if (p->limiter_mode != 0 && p->limiter_mode != 1) return bad("limiter_mode must be 0 or 1");
+  if (p->box_size < 0) return bad("box_size < 0");
+  if (p->box_size > 0) {
+    if (p->box_levels < 1 || p->box_levels > 12 || p->box_inner < 1)
+      return bad("box_levels out of range or box_inner < 1");
+    if (!is_pow2_div(p->box_size, p->box_levels))
+      return bad("box_size must be divisible by 2^(box_levels-1) with an even coarsest size >= 4");
+    if (p->box_size > p->nx || p->box_size > p->ny || p->box_size > p->nz)
+      return bad("box_size larger than the grid");
+  }
   return RT_OK;
 }
 
@@ -227,7 +254,66 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
     }
     nx /= 2; ny /= 2; nz /= 2;
   }
+  w->B64.clear();
+  w->B32.clear();
+  w->box_cap = 0;
+  if (p->box_size > 0 && p->max_sources > 0) {
+    const int B = p->box_size;
+    w->box_cap = p->max_sources;
+    const size_t nb3 = (size_t)w->box_cap * B * B * B;
+    w->bd = c.take<double>(nb3); w->bcx = c.take<double>(nb3);
+    w->bcy = c.take<double>(nb3); w->bcz = c.take<double>(nb3);
+    w->bxv = c.take<double>(nb3); w->br = c.take<double>(nb3);
+    w->bz = c.take<double>(nb3); w->bp = c.take<double>(nb3); w->bq = c.take<double>(nb3);
+    const size_t sb = (size_t)stencil_blocks(w->box_cap * B, B, B);
+    w->bparts = c.take<double>((sb > (size_t)MAX_PARTS ? sb : (size_t)MAX_PARTS) * NCOMP_MAX);
+    w->bsc = c.take<double>(32);
+    // levels sized for every box; rt_set_sources sets the extent in use
+    int bx = w->box_cap * B, by = B, bz = B;
+    for (int l = 0; l < p->box_levels; ++l) {
+      const size_t n = (size_t)bx * by * bz;
+      if (!p->mg_fp32) {
+        Level<double> L{bx, by, bz};
+        if (l == 0) {
+          L.diag = w->bd; L.cx = w->bcx; L.cy = w->bcy; L.cz = w->bcz;
+          L.x = nullptr; L.b = nullptr;          // bound per application
+          L.r = c.take<double>(n);
+        } else {
+          L.diag = c.take<double>(n); L.cx = c.take<double>(n); L.cy = c.take<double>(n);
+          L.cz = c.take<double>(n); L.x = c.take<double>(n); L.b = c.take<double>(n);
+          L.r = c.take<double>(n);
+        }
+        w->B64.push_back(L);
+      } else {
+        Level<float> L{bx, by, bz};
+        L.diag = c.take<float>(n); L.cx = c.take<float>(n); L.cy = c.take<float>(n);
+        L.cz = c.take<float>(n); L.x = c.take<float>(n); L.b = c.take<float>(n);
+        L.r = c.take<float>(n);
+        w->B32.push_back(L);
+      }
+      bx /= 2; by /= 2; bz /= 2;
+    }
+  }
   return c.off + ALIGN;
+}
+
+// extent of the box levels in use for nbox boxes (0: no subdomain correction)
+void drop_box_graph(rt_grid* g) {
+  if (g->box_exec) (void)hipGraphExecDestroy(g->box_exec);   // nothing to report on release
+  g->box_exec = nullptr;
+}
+
+void set_box_extent(rt_grid* g, int nbox) {
+  Workspace& w = g->w;
+  g->nbox = (g->prm.box_size > 0 && nbox > 0 && nbox <= w.box_cap) ? nbox : 0;
+  if (g->nbox != g->box_n) drop_box_graph(g);
+  const int B = g->prm.box_size;
+  for (size_t l = 0; l < w.B64.size(); ++l) {
+    w.B64[l].nx = (g->nbox * B) >> l; w.B64[l].ny = B >> l; w.B64[l].nz = B >> l;
+  }
+  for (size_t l = 0; l < w.B32.size(); ++l) {
+    w.B32[l].nx = (g->nbox * B) >> l; w.B32[l].ny = B >> l; w.B32[l].nz = B >> l;
+  }
 }
 
 Step step_new(double dt, const rt_cosmo* c) { return Step{dt, c->a_new, c->H_new}; }
@@ -295,6 +381,24 @@ int build_hierarchy(rt_grid* g) {
     TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cz, L0.cz, g->st));
     for (size_t l = 1; l < w.L32.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<float>(w.L32[l - 1], w.L32[l], g->st));
   }
+  if (g->nbox > 0) {
+    // the operator restricted to the source boxes, and its hierarchy
+    const int B = g->prm.box_size;
+    const long nb3 = (long)g->nbox * B * B * B;
+    TK(g, RT_K_MG_SETUP, launch_box_extract(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells,
+                                            w.diag, w.cx, w.cy, w.cz, w.bd, w.bcx, w.bcy, w.bcz,
+                                            g->st));
+    if (!g->prm.mg_fp32) {
+      for (size_t l = 1; l < w.B64.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<double>(w.B64[l - 1], w.B64[l], g->st));
+    } else {
+      Level<float>& L0 = w.B32[0];
+      TK(g, RT_K_MG_SETUP, launch_cvt_d2f(nb3, w.bd, L0.diag, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_d2f(nb3, w.bcx, L0.cx, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_d2f(nb3, w.bcy, L0.cy, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_d2f(nb3, w.bcz, L0.cz, g->st));
+      for (size_t l = 1; l < w.B32.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<float>(w.B32[l - 1], w.B32[l], g->st));
+    }
+  }
   g->mg_stale = false;
   HIPCHK(g, hipGetLastError());
   return RT_OK;
@@ -328,6 +432,122 @@ int apply_vcycle(rt_grid* g, const double* r, double* z, bool dots = false) {
   vcycle<float>(g, w.L32, 0);
   TK(g, RT_K_MG_TRANSFER, launch_cvt_f2d(N, L0.x, z, g->st));
   return 0;
+}
+
+// z = V r on the box hierarchy (all boxes at once)
+void box_vcycle(rt_grid* g, const double* r, double* z) {
+  Workspace& w = g->w;
+  if (!g->prm.mg_fp32) {
+    w.B64[0].b = const_cast<double*>(r);
+    w.B64[0].x = z;
+    vcycle<double>(g, w.B64, 0);
+    return;
+  }
+  Level<float>& L0 = w.B32[0];
+  const long n = (long)L0.nx * L0.ny * L0.nz;
+  TK(g, RT_K_BOX, launch_cvt_d2f(n, r, L0.b, g->st));
+  vcycle<float>(g, w.B32, 0);
+  TK(g, RT_K_BOX, launch_cvt_f2d(n, L0.x, z, g->st));
+}
+
+// Source-subdomain correction after the V-cycle: z += the boxes' part of an
+// approximate solution of the box operator with right side r - S z (the
+// residual the V-cycle left) on the boxes, namely box_inner iterations of
+// flexible PCG from zero with the box V-cycle; the iterations run without
+// host read-back, so the whole sequence is fixed and can be captured.
+void box_correct_launches(rt_grid* g, const double* r, double* z) {
+  Workspace& w = g->w;
+  hipStream_t st = g->st;
+  const int B = g->prm.box_size;
+  const int bx = g->nbox * B;
+  const long n = (long)bx * B * B;
+  const int np1 = reduce_blocks(n);
+  const int nst = stencil_blocks(bx, B, B);
+  g->tk_override = RT_K_BOX;
+  TK(g, RT_K_BOX, launch_box_residual(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, w.diag,
+                                      w.cx, w.cy, w.cz, r, z, w.br, st));
+  TK(g, RT_K_BOX, launch_fill<double>(n, w.bxv, 0.0, st));
+  box_vcycle(g, w.br, w.bz);
+  TK(g, RT_K_BOX, launch_dot1(n, w.br, w.bz, w.bparts, st));
+  TK(g, RT_K_BOX, launch_final_reduce(w.bparts, np1, 1, w.bsc + S_RHO, st));
+  TK(g, RT_K_BOX, launch_copy(n, w.bz, w.bp, st));
+  for (int it = 1; it <= g->prm.box_inner; ++it) {
+    TK(g, RT_K_BOX, launch_spmv_dot(bx, B, B, w.bd, w.bcx, w.bcy, w.bcz, w.bp, w.bq, w.bparts, st));
+    TK(g, RT_K_BOX, launch_final_reduce(w.bparts, nst, 1, w.bsc + S_PQ, st));
+    TK(g, RT_K_BOX, launch_cg_alpha(w.bsc, st));
+    TK(g, RT_K_BOX, launch_update_xr(n, w.bxv, w.br, w.bp, w.bq, w.bsc, w.bparts, st));
+    if (it == g->prm.box_inner) break;
+    box_vcycle(g, w.br, w.bz);
+    TK(g, RT_K_BOX, launch_dot2(n, w.bz, w.br, w.bq, w.bparts, st));
+    TK(g, RT_K_BOX, launch_final_reduce(w.bparts, np1, 2, w.bsc + S_ZR, st));
+    TK(g, RT_K_BOX, launch_cg_beta(w.bsc, st));
+    TK(g, RT_K_BOX, launch_update_p(n, w.bp, w.bz, w.bsc, st));
+  }
+  // boxes may overlap: one launch per box, in source order
+  for (int s = 0; s < g->nbox; ++s)
+    TK(g, RT_K_BOX, launch_box_scatter_add(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, s,
+                                           w.bxv, z, st));
+  g->tk_override = -1;
+}
+
+// capture the correction for (r, z) on a private stream (the caller's stream
+// may be the null stream, which cannot be captured); nothing runs meanwhile
+int capture_box(rt_grid* g, const double* r, double* z) {
+  drop_box_graph(g);
+  if (!g->cap_st) HIPCHK(g, hipStreamCreateWithFlags(&g->cap_st, hipStreamNonBlocking));
+  hipStream_t caller = g->st;
+  const bool timing = g->tm.on;
+  g->tm.on = false;   // no event records inside the graph
+  g->st = g->cap_st;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    box_correct_launches(g, r, z);
+    e = hipStreamEndCapture(g->st, &graph);
+  }
+  g->st = caller;
+  g->tm.on = timing;
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->box_exec, graph, nullptr, nullptr, 0);
+  if (graph) {
+    const hipError_t e2 = hipGraphDestroy(graph);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) {
+    drop_box_graph(g);
+    return fail(g, RT_EDEVICE, "capturing the subdomain correction: %s", hipGetErrorString(e));
+  }
+  g->box_r = r;
+  g->box_z = z;
+  g->box_n = g->nbox;
+  return RT_OK;
+}
+
+// one replay of the captured graph (timed as one launch), or with graphs
+// off the launches one by one
+int box_correct(rt_grid* g, const double* r, double* z) {
+  if (!g->graphs) {
+    box_correct_launches(g, r, z);
+    return RT_OK;
+  }
+  if (!g->box_exec || g->box_r != r || g->box_z != z || g->box_n != g->nbox)
+    RTCHK(capture_box(g, r, z));
+  hipError_t e = hipSuccess;
+  TK(g, RT_K_BOX, e = hipGraphLaunch(g->box_exec, g->st));
+  HIPCHK(g, e);
+  return RT_OK;
+}
+
+// the CG preconditioner: the V-cycle, plus the source-subdomain correction
+// when one is configured.  *nd: what apply_vcycle returns for dots (0 with
+// the correction: the dots must follow it)
+int apply_precond(rt_grid* g, const double* r, double* z, bool dots, int* nd) {
+  if (g->nbox == 0) {
+    *nd = apply_vcycle(g, r, z, dots);
+    return RT_OK;
+  }
+  apply_vcycle(g, r, z, false);
+  *nd = 0;
+  return box_correct(g, r, z);
 }
 
 int read_scalars(rt_grid* g, const double* d, double* h, int n) {
@@ -364,7 +584,8 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
     return RT_OK;
   }
   HIPCHK(g, hipMemcpyAsync(w.r, b, N * sizeof(double), hipMemcpyDeviceToDevice, g->st));
-  apply_vcycle(g, w.r, w.z);
+  int nd = 0;
+  RTCHK(apply_precond(g, w.r, w.z, false, &nd));
   ++*vcycles;
   TK(g, RT_K_CG_VECTOR, launch_dot1(N, w.r, w.z, w.parts, g->st));
   finish_reduce(g, nparts, 1, S_RHO);
@@ -375,8 +596,8 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   // back to the host: the device never idles on the read-back.  If that norm
   // turns out converged, the enqueued tail is discarded work and x is final.
   constexpr double LOOKAHEAD = 30.0;
-  auto tail = [&]() {
-    const int nd = apply_vcycle(g, w.r, w.z, true);
+  auto tail = [&]() -> int {
+    RTCHK(apply_precond(g, w.r, w.z, true, &nd));
     ++*vcycles;
     if (nd > 0) {
       finish_reduce(g, nd, 2, S_ZR);
@@ -386,6 +607,7 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
     }
     TK(g, RT_K_REDUCE, launch_cg_beta(w.sc, g->st));
     TK(g, RT_K_CG_VECTOR, launch_update_p(N, w.p, w.z, w.sc, g->st));
+    return RT_OK;
   };
   double rn = bn;
   int k = 0;
@@ -398,13 +620,13 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
     HIPCHK(g, hipMemcpyAsync(g->hpin, w.sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, g->st));
     HIPCHK(g, hipEventRecord(g->ev_rd, g->st));
     const bool ahead = k < maxit && rn > LOOKAHEAD * thr;
-    if (ahead) tail();
+    if (ahead) RTCHK(tail());
     HIPCHK(g, hipEventSynchronize(g->ev_rd));
     rn = std::sqrt(g->hpin[0]);
     if (!std::isfinite(rn)) return fail(g, RT_ENONFINITE, "non-finite CG residual");
     if (rn <= thr) break;
     if (k == maxit) break;
-    if (!ahead) tail();
+    if (!ahead) RTCHK(tail());
   }
   *iters = k > maxit ? maxit : k;
   *relres = rn / bn;
@@ -509,6 +731,8 @@ int rt_destroy_grid(rt_grid* g) {
     for (hipEvent_t e : g->tm.pool) (void)hipEventDestroy(e);
     if (g->ev_rd) (void)hipEventDestroy(g->ev_rd);
     if (g->hpin) (void)hipHostFree(g->hpin);
+    drop_box_graph(g);
+    if (g->cap_st) (void)hipStreamDestroy(g->cap_st);
   }
   delete g;
   return RT_OK;
@@ -541,6 +765,8 @@ int rt_set_sources(rt_grid* g, int32_t n, const int64_t* h_cells, const double* 
     HIPCHK(g, hipStreamSynchronize(g->st));
   }
   g->nsrc = n;
+  set_box_extent(g, n);
+  g->mg_stale = true;
   g->have_tl = false;
   return RT_OK;
 }
@@ -763,6 +989,13 @@ int rt_timing(rt_grid* g, int32_t enable, rt_kernel_timing* out) {
 int rt_timing_classes(rt_grid* g, uint32_t mask) {
   if (!g) return RT_EINVAL;
   g->tm.mask = mask;
+  return RT_OK;
+}
+
+int rt_use_graphs(rt_grid* g, int32_t enable) {
+  if (!g) return RT_EINVAL;
+  g->graphs = enable != 0;
+  if (!g->graphs) drop_box_graph(g);
   return RT_OK;
 }
 

@@ -61,6 +61,8 @@ void launch_dot2(long n, const double* z, const double* r, const double* q, doub
                  hipStream_t st);
 void launch_dot1(long n, const double* a, const double* b, double* parts, hipStream_t st);
 void launch_update_p(long n, double* p, const double* z, const double* sc, hipStream_t st);
+// b = a (a kernel rather than a copy call, so that it can sit in a captured graph)
+void launch_copy(long n, const double* a, double* b, hipStream_t st);
 
 // ---- multigrid (T = double or float) ----
 template <class T>
@@ -92,6 +94,16 @@ template <class T> void launch_prolong_add(const Level<T>& C, const Level<T>& F,
 template <class T> void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st);
 void launch_fold_energy(int N, double* U, double* eh, hipStream_t st);
 void launch_cvt_d2f(long n, const double* a, float* b, hipStream_t st);
+// source subdomains (boxes of B^3 cells around each source, stacked along x)
+void launch_box_extract(int nx, int ny, int nz, int B, int nbox, const long long* cells,
+                        const double* diag, const double* cx, const double* cy, const double* cz,
+                        double* bd, double* bx, double* by, double* bz, hipStream_t st);
+// r - S z on the box cells, into the stacked box vector bv
+void launch_box_residual(int nx, int ny, int nz, int B, int nbox, const long long* cells,
+                         const double* diag, const double* cx, const double* cy, const double* cz,
+                         const double* r, const double* z, double* bv, hipStream_t st);
+void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
+                            const double* y, double* z, hipStream_t st);
 // FP64 natural field -> FP32 field in the layout of level L
 void launch_cvt_d2f_level(const Level<float>& L, const double* a, float* b, hipStream_t st);
 void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st);

@@ -499,6 +499,12 @@ __global__ __launch_bounds__(BLOCK) void k_fill(long n, T* __restrict__ x, T v) 
   if (i < n) x[i] = v;
 }
 
+__global__ __launch_bounds__(BLOCK) void k_copy(long n, const double* __restrict__ a,
+                                                double* __restrict__ b) {
+  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
 __device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Finest-level layout of the FP32 V-cycle.  Natural: cell (i,j,k) at
@@ -837,6 +843,77 @@ __global__ __launch_bounds__(BLOCK) void k_coarsen(Level<T> F, Level<T> C) {
   C.diag[idx] = local + (((cxp + cxm) + (cyp + cym)) + (czp + czm));
 }
 
+// ---------------------------------------------------------------------------
+// source subdomains: a box of B^3 cells centred on each source, the boxes
+// stacked along x into one (nbox*B) x B x B periodic grid.  Box cell
+// (X, j, k), X = s*B + bi, is global cell (c_s + (bi, j, k) - B/2) mod n.
+struct BoxMap {
+  int nx, ny, nz, B, nbox;
+};
+__device__ inline int box_global(const BoxMap& m, long long c, int bi, int bj, int bk) {
+  const int ny = m.ny, nz = m.nz;
+  const int ci = (int)(c / ((long long)ny * nz));
+  const int cj = (int)((c / nz) % ny);
+  const int ck = (int)(c % nz);
+  const int h = m.B >> 1;
+  int i = (ci - h + bi) % m.nx, j = (cj - h + bj) % ny, k = (ck - h + bk) % nz;
+  if (i < 0) i += m.nx;
+  if (j < 0) j += ny;
+  if (k < 0) k += nz;
+  return (i * ny + j) * nz + k;
+}
+// the operator restricted to the boxes: diagonal unchanged, couplings inside
+// a box kept, couplings out of a box (its last layer in each direction, which
+// the periodic storage would join to the next box) zero
+__global__ __launch_bounds__(BLOCK) void k_box_extract(BoxMap m, const long long* __restrict__ cells,
+                                                        const double* __restrict__ diag,
+                                                        const double* __restrict__ cx,
+                                                        const double* __restrict__ cy,
+                                                        const double* __restrict__ cz,
+                                                        double* __restrict__ bd, double* __restrict__ bx,
+                                                        double* __restrict__ by, double* __restrict__ bz) {
+  const C3 c = coord3(m.B, m.B);
+  if (!c.ok) return;
+  const int s = c.i / m.B, bi = c.i - s * m.B;
+  const int g = box_global(m, cells[s], bi, c.j, c.k);
+  const int o = (c.i * m.B + c.j) * m.B + c.k;
+  bd[o] = diag[g];
+  bx[o] = bi == m.B - 1 ? 0.0 : cx[g];
+  by[o] = c.j == m.B - 1 ? 0.0 : cy[g];
+  bz[o] = c.k == m.B - 1 ? 0.0 : cz[g];
+}
+// the residual r - S z left by the V-cycle, on the box cells (S the global
+// operator, z the V-cycle's result)
+__global__ __launch_bounds__(BLOCK) void k_box_residual(BoxMap m, const long long* __restrict__ cells,
+                                                         const double* __restrict__ diag,
+                                                         const double* __restrict__ cx,
+                                                         const double* __restrict__ cy,
+                                                         const double* __restrict__ cz,
+                                                         const double* __restrict__ r,
+                                                         const double* __restrict__ z,
+                                                         double* __restrict__ bv) {
+  const C3 c = coord3(m.B, m.B);
+  if (!c.ok) return;
+  const int s = c.i / m.B;
+  const int g = box_global(m, cells[s], c.i - s * m.B, c.j, c.k);
+  const int k = g % m.nz, j = (g / m.nz) % m.ny, i = g / (m.nz * m.ny);
+  const Nb nb = nbrs(i, j, k, m.nx, m.ny, m.nz);
+  double y = diag[g] * z[g];
+  y = y - cx[g] * z[nb.xp] - cx[nb.xm] * z[nb.xm];
+  y = y - cy[g] * z[nb.yp] - cy[nb.ym] * z[nb.ym];
+  y = y - cz[g] * z[nb.zp] - cz[nb.zm] * z[nb.zm];
+  bv[(c.i * m.B + c.j) * m.B + c.k] = r[g] - y;
+}
+// z += the box's part of y, one box per launch (overlapping boxes add in box order)
+__global__ __launch_bounds__(BLOCK) void k_box_scatter_add(BoxMap m, const long long* __restrict__ cells,
+                                                            int s, const double* __restrict__ y,
+                                                            double* __restrict__ z) {
+  const C3 c = coord3(m.B, m.B);
+  if (!c.ok) return;
+  const int g = box_global(m, cells[s], c.i, c.j, c.k);
+  z[g] += y[((s * m.B + c.i) * m.B + c.j) * m.B + c.k];
+}
+
 // FP64 natural -> FP32 colour-split finest level
 __global__ __launch_bounds__(BLOCK) void k_cvt_d2f_split(int nx, int ny, int nz,
                                                           const double* __restrict__ a,
@@ -975,6 +1052,9 @@ void launch_update_p(long n, double* p, const double* z, const double* sc, hipSt
   hipLaunchKernelGGL(k_update_p, grid_for(n), dim3(BLOCK), 0, st, n, p, z, sc);
 }
 
+void launch_copy(long n, const double* a, double* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, grid_for(n), dim3(BLOCK), 0, st, n, a, b);
+}
 template <class T>
 void launch_fill(long n, T* x, T v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<T>, grid_for(n), dim3(BLOCK), 0, st, n, x, v);
@@ -1029,6 +1109,26 @@ template <class T>
 void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st) {
   const Geo q = geo3(C.nx, C.ny, C.nz);
   RT_LAYOUT(F, k_coarsen, T, q.g, q.b, 0, st, F, C);
+}
+void launch_box_extract(int nx, int ny, int nz, int B, int nbox, const long long* cells,
+                        const double* diag, const double* cx, const double* cy, const double* cz,
+                        double* bd, double* bx, double* by, double* bz, hipStream_t st) {
+  const BoxMap m{nx, ny, nz, B, nbox};
+  const Geo q = geo3(nbox * B, B, B);
+  hipLaunchKernelGGL(k_box_extract, q.g, q.b, 0, st, m, cells, diag, cx, cy, cz, bd, bx, by, bz);
+}
+void launch_box_residual(int nx, int ny, int nz, int B, int nbox, const long long* cells,
+                         const double* diag, const double* cx, const double* cy, const double* cz,
+                         const double* r, const double* z, double* bv, hipStream_t st) {
+  const BoxMap m{nx, ny, nz, B, nbox};
+  const Geo q = geo3(nbox * B, B, B);
+  hipLaunchKernelGGL(k_box_residual, q.g, q.b, 0, st, m, cells, diag, cx, cy, cz, r, z, bv);
+}
+void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
+                            const double* y, double* z, hipStream_t st) {
+  const BoxMap m{nx, ny, nz, B, nbox};
+  const Geo q = geo3(B, B, B);
+  hipLaunchKernelGGL(k_box_scatter_add, q.g, q.b, 0, st, m, cells, s, y, z);
 }
 void launch_cvt_d2f_level(const Level<float>& L, const double* a, float* b, hipStream_t st) {
   if (L.split) {

@@ -82,6 +82,9 @@ class Workload:
     pcg_rtol: float = 1.0e-8
     pcg_maxit: int = 200
     pcg_forcing: float = 0.0   # > 0: CG also stops at ||r|| <= pcg_forcing ||f(U_k)||
+    box_size: int = 0          # > 0: subdomain correction on a box around each source
+    box_levels: int = 3
+    box_inner: int = 6
     mg_levels: int = 3
     mg_pre: int = 2
     mg_post: int = 2

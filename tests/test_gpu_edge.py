@@ -130,11 +130,13 @@ def test_fold_energy():
     assert torch.count_nonzero(sim.Un[0]) == 0
 
 
-@pytest.mark.parametrize("n,levels,steps", [(32, 3, 1), (64, 4, 3)])
-def test_mixed_precision_equal_accuracy(n, levels, steps):
+@pytest.mark.parametrize("n,levels,steps,box", [(32, 3, 1, 0), (64, 4, 3, 0), (64, 4, 3, 16)])
+def test_mixed_precision_equal_accuracy(n, levels, steps, box):
     """FP32 V-cycle: every step still meets the FP64 Newton tolerance; the
     per-field difference to the FP64 oracle stays at the tolerance level."""
     w = synth.CFG_256.replace(n=n, mg_levels=levels) if n == 64 else synth.CFG_SMALL
+    if box:
+        w = w.replace(box_size=box, box_levels=2, box_inner=4)
     s = synth.initial_state(w)
     m = oracle.model_from_workload(w)
     sim = Simulation(w, state={k: (v.copy() if hasattr(v, "copy") else v) for k, v in s.items()},
@@ -158,3 +160,30 @@ def test_mixed_precision_equal_accuracy(n, levels, steps):
         eh = eh + U_o[0]
         U_o[0] = 0.0
         Un = U_o
+
+
+@pytest.mark.parametrize("mg_fp32", [0, 1])
+def test_box_graph_matches_launches(mg_fp32):
+    """The subdomain correction replayed from its captured graph gives the
+    same bits as its launches issued one by one; a new source count
+    re-captures it; a timed replay counts once per V-cycle."""
+    w = synth.CFG_COSMO.replace(n=32, mg_levels=3, box_size=8, box_levels=2, box_inner=3)
+    s = synth.initial_state(w)
+    _, eager = fresh(w, mg_fp32=mg_fp32)
+    _, graph = fresh(w, mg_fp32=mg_fp32)
+    eager.grid.rt_use_graphs(False)
+    graph.grid.rt_timing(True)
+    vcycles = 0
+    for nsrc in (16, 16, 5):
+        if nsrc != 16:
+            for sim in (eager, graph):
+                sim.grid.rt_set_sources(s["src_cells"][:nsrc], s["src_Q"][:nsrc])
+        st_e, st_g = eager.step(), graph.step()
+        assert st_e["status"] == 0 and st_g["status"] == 0
+        assert st_e["cg_its"] == st_g["cg_its"]
+        assert np.array_equal(host(eager.U), host(graph.U))
+        vcycles += st_g["vcycles"]
+        eager.advance()
+        graph.advance()
+    t = graph.grid.rt_timing(False)
+    assert t["box"][0] == vcycles > 0

@@ -209,6 +209,21 @@ def test_newton_steps_256_spacing_forcing():
     newton_parity(w, synth.initial_state(w), steps=3)
 
 
+def test_newton_steps_source_boxes():
+    """The source-subdomain correction on both sides (one 16^3 box, 4 inner
+    PCG iterations on a 2-level box V-cycle): equal counts, fields to 1e-10."""
+    w = synth.CFG_256.replace(n=64, mg_levels=4, box_size=16, box_levels=2, box_inner=4)
+    newton_parity(w, synth.initial_state(w), steps=3)
+
+
+def test_newton_steps_overlapping_boxes():
+    """16 sources in a 32^3 lognormal cut: the 8^3 boxes overlap and their
+    corrections add in source order on both sides."""
+    w = synth.CFG_COSMO.replace(n=32, mg_levels=3, dx=synth.CFG_COSMO.dx, box_size=8,
+                                box_levels=2, box_inner=3)
+    newton_parity(w, synth.initial_state(w), steps=2)
+
+
 def test_newton_steps_expanding_lognormal():
     """Expanding lognormal medium with 16 sources (32^3 cut of the 128^3 workload)."""
     w = synth.CFG_COSMO.replace(n=32, mg_levels=3, dx=synth.CFG_COSMO.dx)
