@@ -45,6 +45,8 @@ HBM_PEAK_GBS = 8000.0
 #              the 3 couplings, write x                                = 6 w
 #              FP32 cycle's last half-sweep: 4 w, write z (FP64, both
 #              colours), read r and q (FP64) for the CG dots           = 4 w + 24 B
+#              (without the dots, when the subdomain correction follows
+#              the V-cycle and changes z                               = 4 w + 8 B)
 # (w = 4 B for the FP32 V-cycle, 8 B for FP64)
 BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0}
 
@@ -52,10 +54,12 @@ BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0
 # HBM traffic per launch of the finest-level FP32 smoother class at 256^3 with
 # V(2,2), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by
 # what the counters read for a plain 2 GiB device copy (FETCH_SIZE x 2.0,
-# WRITE_SIZE x 1.0), averaged over one V-cycle's 7 launches.  It belongs to the
+# WRITE_SIZE x 1.0), averaged over one V-cycle's 7 launches, with the subdomain
+# correction on (the last half-sweep then forms no CG dots).  It belongs to the
 # kernel source it was measured on and is reported as null for any other.
-PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "bytes_per_launch": 4.375e8,
-                             "kernels_sha256": "ff574398d9996a21cec12b41d0fe264d78d775efedefe6bdf6610914bdec351c"}}
+PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "dots": False,
+                             "bytes_per_launch": 4.078e8,
+                             "kernels_sha256": "9b30a86968cd02187ecd3337a893b622f2fab2e00a3bfa9f18ec0017fd36f7d3"}}
 
 
 def kernels_sha256():
@@ -64,15 +68,16 @@ def kernels_sha256():
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def rbgs_fine_per_vcycle(pre, post, w):
+def rbgs_fine_per_vcycle(pre, post, w, dots=True):
     """(launches, algorithmic bytes per cell) of the fine-level smoothing in one
     V-cycle of the CG loop; in the FP32 cycle the last half-sweep writes the
-    FP64 result and forms the CG dots (pre, post > 0 there)."""
+    FP64 result and, unless a subdomain correction follows, forms the CG dots
+    (pre, post > 0 there)."""
     if pre > 0:
         launches = 1 + 2 * (pre - 1) + 2 * post
         b = 6.0 * w + (2 * (pre - 1) + 2 * post) * 5.0 * w
         if w == 4.0 and post > 0:
-            b += (4.0 * w + 24.0) - 5.0 * w
+            b += (4.0 * w + (24.0 if dots else 8.0)) - 5.0 * w
         return launches, b
     return 2 * post, 2 * post * 5.0 * w
 
@@ -181,7 +186,8 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6))
     # roofline of the dominant kernel class
     wbytes = 4.0 if mode.startswith("mixed") else 8.0
     p = sim.grid.params
-    launches_vc, bytes_vc = rbgs_fine_per_vcycle(p.mg_pre, p.mg_post, wbytes)
+    launches_vc, bytes_vc = rbgs_fine_per_vcycle(p.mg_pre, p.mg_post, wbytes,
+                                                 dots=p.box_size == 0)
     cnt, ms = kt[dom]
     if dom == "rbgs_fine":
         total_bytes = cnt / float(launches_vc) * bytes_vc * N
@@ -194,7 +200,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6))
         tr = PMC_TRAFFIC.get(dom)
         traffic = None
         if (tr and tr["w"] == wbytes and tr["n"] == n and tr["pre_post"] == (p.mg_pre, p.mg_post)
-                and kernels_sha256() == tr["kernels_sha256"]):
+                and tr["dots"] == (p.box_size == 0) and kernels_sha256() == tr["kernels_sha256"]):
             traffic = tr["bytes_per_launch"]
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
