@@ -82,7 +82,7 @@ def rbgs_fine_per_vcycle(pre, post, w, dots=True):
     return 2 * post, 2 * post * 5.0 * w
 
 
-def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None, box=(0, 3, 6)):
+def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None, box=(0, 3, 6, 0)):
     """Train the learned-guess network on plain-method trajectories."""
     import numpy as np
     import synth
@@ -91,7 +91,7 @@ def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None, box=(0, 3, 
 
     t0 = time.perf_counter()
     base = synth.CFG_256.replace(n=n_train, mg_levels=4, box_size=box[0], box_levels=box[1],
-                                 box_inner=box[2])
+                                 box_inner=box[2], box_coarse_sweeps=box[3])
     media = [base, base.replace(sigma_ln=1.0, nsources=4, centred=False, seed=100,
                                 logQ_range=(48.0, 48.7))]
     trajs = []
@@ -124,7 +124,7 @@ def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None, box=(0, 3, 
     return theta, info
 
 
-def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6)):
+def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 0)):
     import torch
     import synth
     from paper_0901_1110_amd.binding import RtNet
@@ -132,7 +132,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6))
 
     w = synth.CFG_256.replace(n=n, mg_fp32=1 if mode.startswith("mixed") else 0,
                               pcg_forcing=forcing, box_size=box[0], box_levels=box[1],
-                              box_inner=box[2])
+                              box_inner=box[2], box_coarse_sweeps=box[3])
     if mode.endswith("learned"):
         net = RtNet(1, (n, n, n))
         net.set_params(theta)
@@ -217,7 +217,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6))
     return res
 
 
-def cpu_baseline(n=128, box=(0, 3, 6)):
+def cpu_baseline(n=128, box=(0, 3, 6, 0)):
     """The oracle on a bounded sample: the first implicit step of the same
     256^3-spacing problem on an n^3 periodic box around the source."""
     from threadpoolctl import threadpool_limits
@@ -227,7 +227,7 @@ def cpu_baseline(n=128, box=(0, 3, 6)):
     from oracle import newton
 
     w = synth.CFG_256.replace(n=n, mg_levels=4, box_size=box[0], box_levels=box[1],
-                              box_inner=box[2])
+                              box_inner=box[2], box_coarse_sweeps=box[3])
     m = oracle.model_from_workload(w)
     s = synth.initial_state(w)
     with threadpool_limits(limits=1):
@@ -258,6 +258,8 @@ def main():
                     help="source-subdomain correction: box edge in cells (0: V-cycle alone)")
     ap.add_argument("--box-levels", type=int, default=2)
     ap.add_argument("--box-inner", type=int, default=16)
+    ap.add_argument("--box-coarse-sweeps", type=int, default=4,
+                    help="sweeps of the coarsest box level (0: those of the main hierarchy)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 2 GiB device copy (counter calibration)")
@@ -277,19 +279,20 @@ def main():
               flush=True)
         del a, b
     modes = [m for m in args.modes.split(",") if m]
+    box = (args.box_size, args.box_levels, args.box_inner, args.box_coarse_sweeps)
     results = {}
     theta, train_info = None, None
     if any(m.endswith("learned") for m in modes):
         print("# training the learned guess (untimed)", file=sys.stderr, flush=True)
         theta, train_info = train_guess(steps=args.train_steps, epochs=args.train_epochs,
                                         log=lambda s: print("#   " + s, file=sys.stderr, flush=True),
-                                        box=(args.box_size, args.box_levels, args.box_inner))
+                                        box=box)
         print("# trained: %s" % train_info, file=sys.stderr, flush=True)
     for mode in modes:
         print("# mode %s: %d warm-up + %d timed steps at %d^3" % (mode, args.warmup, args.steps, args.n),
               file=sys.stderr, flush=True)
         results[mode] = run_mode(mode, args.steps, args.warmup, args.n, theta, args.pcg_forcing,
-                                 (args.box_size, args.box_levels, args.box_inner))
+                                 box)
         print("# %s: %.3e cell-updates/s, %.1f ms/step" % (mode, results[mode]["value"],
                                                           results[mode]["ms_per_step"]),
               file=sys.stderr, flush=True)
@@ -325,7 +328,7 @@ def main():
         line["speedup_vs_plain"] = H["value"] / results["plain"]["value"]
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(box=(args.box_size, args.box_levels, args.box_inner))
+        line["cpu_baseline"] = cpu_baseline(box=box)
     print(json.dumps(line), flush=True)
     with open(os.path.join(ROOT, "gpurun_out", "bench_kernels.json") if os.path.isdir(
             os.path.join(ROOT, "gpurun_out")) else os.devnull, "w") as fh:

@@ -91,6 +91,8 @@ typedef struct rt_params {
                             /* box_levels-level V-cycle (0: V-cycle alone)        */
   int32_t box_levels;
   int32_t box_inner;
+  int32_t box_coarse_sweeps; /* coarsest box level: this many (red,black) then     */
+                             /* (black,red) (0: mg_coarse_sweeps)                 */
 } rt_params;
 
 /* Scale factor a and adot/a at t^n (old) and t^{n+1} (new). */

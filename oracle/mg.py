@@ -26,6 +26,8 @@ PCG: flexible (Polak-Ribiere) beta, x0 = 0, stop when ||r||_2 <= rtol ||b||_2
 """
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 
 from .jacobian import apply_schur
@@ -211,6 +213,8 @@ def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=Non
         B = model.box_size
         bop = box_operator(op, centres, B)
         bops = hierarchy(bop, model.box_levels)
+        bmodel = dataclasses.replace(
+            model, mg_coarse_sweeps=model.box_coarse_sweeps or model.mg_coarse_sweeps)
         sels = [np.ix_(*box_cells(c, B, op[0].shape)) for c in centres]
 
     def V(r):
@@ -220,7 +224,7 @@ def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=Non
         if boxes:
             res = r - apply_schur(z, *op)
             rb = np.concatenate([res[sel] for sel in sels], axis=0)
-            y = pcg_fixed(bop, rb, bops, model, model.box_inner, dt)
+            y = pcg_fixed(bop, rb, bops, bmodel, model.box_inner, dt)
             for s_, sel in enumerate(sels):
                 z[sel] += y[s_ * B:(s_ + 1) * B]
         return z

@@ -71,6 +71,7 @@ class Model:
     box_size: int = 0        # source-subdomain correction in the preconditioner, 0: off
     box_levels: int = 3
     box_inner: int = 6
+    box_coarse_sweeps: int = 0   # coarsest box level's sweeps, 0: mg_coarse_sweeps
 
     @property
     def nv(self):
@@ -142,5 +143,6 @@ def model_from_workload(w, **overrides) -> Model:
               pcg_maxit=w.pcg_maxit, mg_levels=w.mg_levels, mg_pre=w.mg_pre,
               mg_post=w.mg_post, mg_coarse_sweeps=w.mg_coarse_sweeps,
               mg_fp32=w.mg_fp32, pcg_forcing=w.pcg_forcing, box_size=w.box_size,
-              box_levels=w.box_levels, box_inner=w.box_inner)
+              box_levels=w.box_levels, box_inner=w.box_inner,
+              box_coarse_sweeps=w.box_coarse_sweeps)
     return dataclasses.replace(m, **overrides) if overrides else m

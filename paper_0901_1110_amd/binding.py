@@ -37,6 +37,7 @@ class RtParams(ctypes.Structure):
         ("mg_coarse_sweeps", ctypes.c_int32), ("mg_fp32", ctypes.c_int32),
         ("max_sources", ctypes.c_int32), ("pcg_forcing", ctypes.c_double),
         ("box_size", ctypes.c_int32), ("box_levels", ctypes.c_int32), ("box_inner", ctypes.c_int32),
+        ("box_coarse_sweeps", ctypes.c_int32),
     ]
 
 
@@ -192,6 +193,7 @@ def params_from_workload(w, **overrides) -> RtParams:
     p.max_sources = max(64, w.nsources)
     p.pcg_forcing = w.pcg_forcing
     p.box_size, p.box_levels, p.box_inner = w.box_size, w.box_levels, w.box_inner
+    p.box_coarse_sweeps = w.box_coarse_sweeps
     for k, v in overrides.items():
         if k in ("K_gamma", "K_kappa", "K_heat"):
             getattr(p, k)[:] = list(v)

@@ -52,7 +52,7 @@ struct Workspace {
   // source subdomains: boxes of B^3 cells around the sources, stacked along x
   int box_cap = 0;                        // boxes the workspace holds (max_sources)
   double *bd, *bcx, *bcy, *bcz;           // box operator (FP64, level 0 of B64)
-  double *bxv, *br, *bz, *bp, *bq;        // inner PCG vectors
+  double *bxv, *br, *bz, *bp, *bq;        // inner PCG vectors (FP32 cycle: float inside)
   double *bparts, *bsc;
   std::vector<Level<double>> B64;
   std::vector<Level<float>> B32;
@@ -180,8 +180,8 @@ int validate(const rt_params* p, std::string* why) {
   if (p->limiter_mode != 0 && p->limiter_mode != 1) return bad("limiter_mode must be 0 or 1");
   if (p->box_size < 0) return bad("box_size < 0");
   if (p->box_size > 0) {
-    if (p->box_levels < 1 || p->box_levels > 12 || p->box_inner < 1)
-      return bad("box_levels out of range or box_inner < 1");
+    if (p->box_levels < 1 || p->box_levels > 12 || p->box_inner < 1 || p->box_coarse_sweeps < 0)
+      return bad("box_levels out of range, box_inner < 1 or box_coarse_sweeps < 0");
     if (!is_pow2_div(p->box_size, p->box_levels))
       return bad("box_size must be divisible by 2^(box_levels-1) with an even coarsest size >= 4");
     if (p->box_size > p->nx || p->box_size > p->ny || p->box_size > p->nz)
@@ -308,11 +308,14 @@ void set_box_extent(rt_grid* g, int nbox) {
   g->nbox = (g->prm.box_size > 0 && nbox > 0 && nbox <= w.box_cap) ? nbox : 0;
   if (g->nbox != g->box_n) drop_box_graph(g);
   const int B = g->prm.box_size;
+  const int blocks = g->nbox > 0 ? g->nbox : 1;   // the boxes are uncoupled
   for (size_t l = 0; l < w.B64.size(); ++l) {
     w.B64[l].nx = (g->nbox * B) >> l; w.B64[l].ny = B >> l; w.B64[l].nz = B >> l;
+    w.B64[l].blocks = blocks;
   }
   for (size_t l = 0; l < w.B32.size(); ++l) {
     w.B32[l].nx = (g->nbox * B) >> l; w.B32[l].ny = B >> l; w.B32[l].nz = B >> l;
+    w.B32[l].blocks = blocks;
   }
 }
 
@@ -320,10 +323,11 @@ Step step_new(double dt, const rt_cosmo* c) { return Step{dt, c->a_new, c->H_new
 
 // ---------------------------------------------------------------------------
 // multigrid
-// out64 (finest level of the FP32 cycle only): the last smoothing launch
-// writes the result widened to this FP64 vector itself
+// cs: sweeps of the coarsest solve.  out64 (finest level of the FP32 cycle
+// only): the last smoothing launch writes the result widened to this FP64
+// vector itself
 template <class T>
-void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, double* out64 = nullptr,
+void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, int cs, double* out64 = nullptr,
             const double* r64 = nullptr, const double* q64 = nullptr, double* parts = nullptr) {
   const rt_params& p = g->prm;
   hipStream_t st = g->st;
@@ -331,16 +335,16 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, double* out64 = nullpt
   const bool coarsest = (l + 1 == (int)Ls.size());
   const int kc = l == 0 ? RT_K_RBGS_FINE : RT_K_RBGS_COARSE;
   const long n = (long)L.nx * L.ny * L.nz;
-  if (coarsest && n <= COARSE_LDS_MAX) {
-    TK(g, kc, launch_coarse_solve_lds<T>(L, p.mg_coarse_sweeps, st));
+  if (coarsest && L.nx % L.blocks == 0 && n / L.blocks <= COARSE_LDS_MAX) {
+    TK(g, kc, launch_coarse_solve_lds<T>(L, cs, st));
     return;
   }
   if (coarsest && n <= COARSE_SOLVE_MAX) {
-    TK(g, kc, launch_coarse_solve<T>(L, p.mg_coarse_sweeps, st));
+    TK(g, kc, launch_coarse_solve<T>(L, cs, st));
     return;
   }
-  const int pre = coarsest ? p.mg_coarse_sweeps : p.mg_pre;
-  const int post = coarsest ? p.mg_coarse_sweeps : p.mg_post;
+  const int pre = coarsest ? cs : p.mg_pre;
+  const int post = coarsest ? cs : p.mg_post;
   if (pre > 0) {
     TK(g, kc, launch_rbgs_first_pair<T>(L, L.x, st));   // (red, black) from x = 0
     for (int s = 1; s < pre; ++s) {
@@ -353,7 +357,7 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, double* out64 = nullpt
   if (!coarsest) {
     TK(g, RT_K_MG_TRANSFER, launch_mg_residual<T>(L, st));
     TK(g, RT_K_MG_TRANSFER, launch_restrict<T>(L, Ls[l + 1], st));
-    vcycle<T>(g, Ls, l + 1);
+    vcycle<T>(g, Ls, l + 1, cs);
     // the post-smoothing starts with black: only red cells need the correction
     TK(g, RT_K_MG_TRANSFER, launch_prolong_add<T>(Ls[l + 1], L, post > 0 ? 0 : -1, st));
   }
@@ -413,7 +417,7 @@ int apply_vcycle(rt_grid* g, const double* r, double* z, bool dots = false) {
   if (!g->prm.mg_fp32) {
     w.L64[0].b = const_cast<double*>(r);
     w.L64[0].x = z;
-    vcycle<double>(g, w.L64, 0);
+    vcycle<double>(g, w.L64, 0, g->prm.mg_coarse_sweeps);
     return 0;
   }
   Level<float>& L0 = w.L32[0];
@@ -422,72 +426,75 @@ int apply_vcycle(rt_grid* g, const double* r, double* z, bool dots = false) {
     // read at seven points by the first pair, FP64 r costs more than it saves
     TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f_level(L0, r, L0.b, g->st));
     if (dots) {
-      vcycle<float>(g, w.L32, 0, z, r, w.q, w.parts);
+      vcycle<float>(g, w.L32, 0, g->prm.mg_coarse_sweeps, z, r, w.q, w.parts);
       return stencil_blocks(L0.nx, L0.ny, L0.nz / 2);
     }
-    vcycle<float>(g, w.L32, 0, z);
+    vcycle<float>(g, w.L32, 0, g->prm.mg_coarse_sweeps, z);
     return 0;
   }
   TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
-  vcycle<float>(g, w.L32, 0);
+  vcycle<float>(g, w.L32, 0, g->prm.mg_coarse_sweeps);
   TK(g, RT_K_MG_TRANSFER, launch_cvt_f2d(N, L0.x, z, g->st));
   return 0;
 }
 
-// z = V r on the box hierarchy (all boxes at once)
-void box_vcycle(rt_grid* g, const double* r, double* z) {
-  Workspace& w = g->w;
-  if (!g->prm.mg_fp32) {
-    w.B64[0].b = const_cast<double*>(r);
-    w.B64[0].x = z;
-    vcycle<double>(g, w.B64, 0);
-    return;
-  }
-  Level<float>& L0 = w.B32[0];
-  const long n = (long)L0.nx * L0.ny * L0.nz;
-  TK(g, RT_K_BOX, launch_cvt_d2f(n, r, L0.b, g->st));
-  vcycle<float>(g, w.B32, 0);
-  TK(g, RT_K_BOX, launch_cvt_f2d(n, L0.x, z, g->st));
+int box_cs(const rt_grid* g) {
+  return g->prm.box_coarse_sweeps > 0 ? g->prm.box_coarse_sweeps : g->prm.mg_coarse_sweeps;
 }
+
+template <class T> std::vector<Level<T>>& box_hier(Workspace& w);
+template <> std::vector<Level<double>>& box_hier<double>(Workspace& w) { return w.B64; }
+template <> std::vector<Level<float>>& box_hier<float>(Workspace& w) { return w.B32; }
 
 // Source-subdomain correction after the V-cycle: z += the boxes' part of an
 // approximate solution of the box operator with right side r - S z (the
 // residual the V-cycle left) on the boxes, namely box_inner iterations of
-// flexible PCG from zero with the box V-cycle; the iterations run without
-// host read-back, so the whole sequence is fixed and can be captured.
-void box_correct_launches(rt_grid* g, const double* r, double* z) {
+// flexible PCG from zero with the box V-cycle, all in T (the V-cycle's
+// type; FP64 dots).  The iterations run without host read-back, so the whole
+// sequence is fixed and can be captured.
+template <class T>
+void box_correct_t(rt_grid* g, const double* r, double* z) {
   Workspace& w = g->w;
   hipStream_t st = g->st;
   const int B = g->prm.box_size;
-  const int bx = g->nbox * B;
-  const long n = (long)bx * B * B;
-  const int np1 = reduce_blocks(n);
-  const int nst = stencil_blocks(bx, B, B);
+  std::vector<Level<T>>& Ls = box_hier<T>(w);
+  Level<T>& L0 = Ls[0];
+  const long n = (long)L0.nx * L0.ny * L0.nz;
+  T* x = reinterpret_cast<T*>(w.bxv);
+  T* br = reinterpret_cast<T*>(w.br);
+  T* bz = reinterpret_cast<T*>(w.bz);
+  T* bp = reinterpret_cast<T*>(w.bp);
+  T* bq = reinterpret_cast<T*>(w.bq);
   g->tk_override = RT_K_BOX;
-  TK(g, RT_K_BOX, launch_box_residual(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, w.diag,
-                                      w.cx, w.cy, w.cz, r, z, w.br, st));
-  TK(g, RT_K_BOX, launch_fill<double>(n, w.bxv, 0.0, st));
-  box_vcycle(g, w.br, w.bz);
-  TK(g, RT_K_BOX, launch_dot1(n, w.br, w.bz, w.bparts, st));
-  TK(g, RT_K_BOX, launch_final_reduce(w.bparts, np1, 1, w.bsc + S_RHO, st));
-  TK(g, RT_K_BOX, launch_copy(n, w.bz, w.bp, st));
+  TK(g, RT_K_BOX, launch_box_residual<T>(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, w.diag,
+                                         w.cx, w.cy, w.cz, r, z, br, st));
+  TK(g, RT_K_BOX, launch_fill<T>(n, x, T(0), st));
+  L0.b = br;   // the box V-cycle maps r -> z in place
+  L0.x = bz;
+  vcycle<T>(g, Ls, 0, box_cs(g));
+  int np = 0;
+  TK(g, RT_K_BOX, np = launch_box_dot1p<T>(n, br, bz, bp, w.bparts, st));
+  TK(g, RT_K_BOX, launch_final_reduce(w.bparts, np, 1, w.bsc + S_RHO, st));
   for (int it = 1; it <= g->prm.box_inner; ++it) {
-    TK(g, RT_K_BOX, launch_spmv_dot(bx, B, B, w.bd, w.bcx, w.bcy, w.bcz, w.bp, w.bq, w.bparts, st));
-    TK(g, RT_K_BOX, launch_final_reduce(w.bparts, nst, 1, w.bsc + S_PQ, st));
-    TK(g, RT_K_BOX, launch_cg_alpha(w.bsc, st));
-    TK(g, RT_K_BOX, launch_update_xr(n, w.bxv, w.br, w.bp, w.bq, w.bsc, w.bparts, st));
+    TK(g, RT_K_BOX, np = launch_box_spmv<T>(L0, bp, bq, w.bparts, st));
+    TK(g, RT_K_BOX, launch_final_reduce_alpha(w.bparts, np, w.bsc, st));
+    TK(g, RT_K_BOX, launch_box_update_xr<T>(n, x, br, bp, bq, w.bsc, st));
     if (it == g->prm.box_inner) break;
-    box_vcycle(g, w.br, w.bz);
-    TK(g, RT_K_BOX, launch_dot2(n, w.bz, w.br, w.bq, w.bparts, st));
-    TK(g, RT_K_BOX, launch_final_reduce(w.bparts, np1, 2, w.bsc + S_ZR, st));
-    TK(g, RT_K_BOX, launch_cg_beta(w.bsc, st));
-    TK(g, RT_K_BOX, launch_update_p(n, w.bp, w.bz, w.bsc, st));
+    vcycle<T>(g, Ls, 0, box_cs(g));
+    TK(g, RT_K_BOX, np = launch_box_dot2<T>(n, bz, br, bq, w.bparts, st));
+    TK(g, RT_K_BOX, launch_final_reduce_beta(w.bparts, np, w.bsc, st));
+    TK(g, RT_K_BOX, launch_box_update_p<T>(n, bp, bz, w.bsc, st));
   }
   // boxes may overlap: one launch per box, in source order
   for (int s = 0; s < g->nbox; ++s)
-    TK(g, RT_K_BOX, launch_box_scatter_add(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, s,
-                                           w.bxv, z, st));
+    TK(g, RT_K_BOX, launch_box_scatter_add<T>(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells,
+                                              s, x, z, st));
   g->tk_override = -1;
+}
+
+void box_correct_launches(rt_grid* g, const double* r, double* z) {
+  if (g->prm.mg_fp32) box_correct_t<float>(g, r, z);
+  else box_correct_t<double>(g, r, z);
 }
 
 // capture the correction for (r, z) on a private stream (the caller's stream
@@ -599,13 +606,8 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   auto tail = [&]() -> int {
     RTCHK(apply_precond(g, w.r, w.z, true, &nd));
     ++*vcycles;
-    if (nd > 0) {
-      finish_reduce(g, nd, 2, S_ZR);
-    } else {
-      TK(g, RT_K_CG_VECTOR, launch_dot2(N, w.z, w.r, w.q, w.parts, g->st));
-      finish_reduce(g, nparts, 2, S_ZR);
-    }
-    TK(g, RT_K_REDUCE, launch_cg_beta(w.sc, g->st));
+    if (nd == 0) TK(g, RT_K_CG_VECTOR, launch_dot2(N, w.z, w.r, w.q, w.parts, g->st));
+    TK(g, RT_K_REDUCE, launch_final_reduce_beta(w.parts, nd > 0 ? nd : nparts, w.sc, g->st));
     TK(g, RT_K_CG_VECTOR, launch_update_p(N, w.p, w.z, w.sc, g->st));
     return RT_OK;
   };
@@ -613,8 +615,8 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   int k = 0;
   for (k = 1; k <= maxit; ++k) {
     TK(g, RT_K_SPMV, launch_spmv_dot(g->P.nx, g->P.ny, g->P.nz, w.diag, w.cx, w.cy, w.cz, w.p, w.q, w.parts, g->st));
-    finish_reduce(g, stencil_blocks(g->P.nx, g->P.ny, g->P.nz), 1, S_PQ);
-    TK(g, RT_K_REDUCE, launch_cg_alpha(w.sc, g->st));
+    TK(g, RT_K_REDUCE, launch_final_reduce_alpha(w.parts, stencil_blocks(g->P.nx, g->P.ny, g->P.nz),
+                                                 w.sc, g->st));
     TK(g, RT_K_CG_VECTOR, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st));
     finish_reduce(g, nparts, 1, S_RR);
     HIPCHK(g, hipMemcpyAsync(g->hpin, w.sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, g->st));

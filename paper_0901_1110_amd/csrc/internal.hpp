@@ -48,8 +48,10 @@ void launch_schur(const DevParams& P, const double* U, const double* f, const do
 // ---- reductions / scalars ----
 void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out,
                          hipStream_t st);
-void launch_cg_alpha(double* sc, hipStream_t st);
-void launch_cg_beta(double* sc, hipStream_t st);
+// the final reduction of p.q followed by alpha, and of (z.r, z.q) followed
+// by beta and rho <- z.r, each in one launch
+void launch_final_reduce_alpha(const double* parts, int nparts, double* sc, hipStream_t st);
+void launch_final_reduce_beta(const double* parts, int nparts, double* sc, hipStream_t st);
 
 // ---- CG vector kernels (FP64) ----
 void launch_spmv_dot(int nx, int ny, int nz, const double* diag, const double* cx,
@@ -61,8 +63,6 @@ void launch_dot2(long n, const double* z, const double* r, const double* q, doub
                  hipStream_t st);
 void launch_dot1(long n, const double* a, const double* b, double* parts, hipStream_t st);
 void launch_update_p(long n, double* p, const double* z, const double* sc, hipStream_t st);
-// b = a (a kernel rather than a copy call, so that it can sit in a captured graph)
-void launch_copy(long n, const double* a, double* b, hipStream_t st);
 
 // ---- multigrid (T = double or float) ----
 template <class T>
@@ -71,6 +71,7 @@ struct Level {
   T *diag, *cx, *cy, *cz;   // operator
   T *x, *b, *r;             // solution, right side, residual scratch
   int split = 0;            // 1: colour-split rows (finest level of the FP32 cycle)
+  int blocks = 1;           // independent x-blocks (zero coupling between them)
 };
 template <class T> void launch_fill(long n, T* x, T v, hipStream_t st);
 template <class T> void launch_rbgs(const Level<T>& L, int colour, hipStream_t st);
@@ -82,7 +83,8 @@ template <class T>
 void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, const double* r64,
                        const double* q64, double* parts, hipStream_t st);
 template <class T> void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st);
-// coarsest solve with the level in registers and LDS (n <= COARSE_LDS_MAX)
+// coarsest solve with each x-block in registers and LDS, one workgroup per
+// block (n / blocks <= COARSE_LDS_MAX, nx divisible by blocks)
 template <class T> void launch_coarse_solve_lds(const Level<T>& L, int sweeps, hipStream_t st);
 constexpr int COARSE_LDS_MAX = 4096;
 int stencil_blocks(int nx, int ny, int nz);   // blocks (= partial sums) of a 3-D stencil launch
@@ -99,11 +101,27 @@ void launch_box_extract(int nx, int ny, int nz, int B, int nbox, const long long
                         const double* diag, const double* cx, const double* cy, const double* cz,
                         double* bd, double* bx, double* by, double* bz, hipStream_t st);
 // r - S z on the box cells, into the stacked box vector bv
+template <class T>
 void launch_box_residual(int nx, int ny, int nz, int B, int nbox, const long long* cells,
                          const double* diag, const double* cx, const double* cy, const double* cz,
-                         const double* r, const double* z, double* bv, hipStream_t st);
+                         const double* r, const double* z, T* bv, hipStream_t st);
+// z += box s's part of the stacked vector y
+template <class T>
 void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
-                            const double* y, double* z, hipStream_t st);
+                            const T* y, double* z, hipStream_t st);
+// inner PCG of the correction on the stacked boxes (level L: the box
+// operator in T); the reduction launches return their partial count
+template <class T>
+int launch_box_dot1p(long n, const T* r, const T* z, T* p, double* parts, hipStream_t st);
+template <class T>
+int launch_box_spmv(const Level<T>& L, const T* p, T* q, double* parts, hipStream_t st);
+template <class T>
+void launch_box_update_xr(long n, T* x, T* r, const T* p, const T* q, const double* sc,
+                          hipStream_t st);
+template <class T>
+int launch_box_dot2(long n, const T* z, const T* r, const T* q, double* parts, hipStream_t st);
+template <class T>
+void launch_box_update_p(long n, T* p, const T* z, const double* sc, hipStream_t st);
 // FP64 natural field -> FP32 field in the layout of level L
 void launch_cvt_d2f_level(const Level<float>& L, const double* a, float* b, hipStream_t st);
 void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st);

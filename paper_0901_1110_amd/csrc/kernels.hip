@@ -381,10 +381,15 @@ __global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __re
 
 // ---------------------------------------------------------------------------
 // reductions and CG scalars
+// post = 1: then alpha = rho / (p.q) (out = sc + S_PQ); post = 2: then the
+// flexible (Polak-Ribiere) beta = (z.r - z.r_old) / rho, with r - r_old =
+// -alpha q, i.e. -alpha (z.q) / rho, and rho <- z.r (out = sc + S_ZR, two
+// components)
 __global__ __launch_bounds__(1024) void k_final_reduce(const double* __restrict__ parts,
                                                        int nparts, int ncomp,
-                                                       double* __restrict__ out) {
+                                                       double* out, double* sc, int post) {
   __shared__ double sh[1024 / 64][NCOMP_MAX];
+  __shared__ double tot[NCOMP_MAX];
   for (int c = 0; c < ncomp; ++c) {
     // eight independent chains (fixed assignment and combine order), so the
     // loads of a thread are in flight together
@@ -405,20 +410,21 @@ __global__ __launch_bounds__(1024) void k_final_reduce(const double* __restrict_
     double s = 0.0;
     for (int w = 0; w < 1024 / 64; ++w) s += sh[w][threadIdx.x];
     out[threadIdx.x] = s;
+    tot[threadIdx.x] = s;
+  }
+  if (post != 0) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (post == 1) {
+        sc[S_ALPHA] = sc[S_RHO] / tot[0];
+      } else {
+        sc[S_BETA] = (-sc[S_ALPHA] * tot[1]) / sc[S_RHO];
+        sc[S_RHO] = tot[0];
+      }
+    }
   }
 }
 
-__global__ void k_cg_alpha(double* sc) {
-  if (threadIdx.x == 0) sc[S_ALPHA] = sc[S_RHO] / sc[S_PQ];
-}
-
-// flexible (Polak-Ribiere) beta = (z.r - z.r_old) / rho with r - r_old = -alpha q
-__global__ void k_cg_beta(double* sc) {
-  if (threadIdx.x == 0) {
-    sc[S_BETA] = (-sc[S_ALPHA] * sc[S_ZQ]) / sc[S_RHO];
-    sc[S_RHO] = sc[S_ZR];
-  }
-}
 
 __global__ __launch_bounds__(BLOCK) void k_spmv_dot(int nx, int ny, int nz,
                                                      const double* __restrict__ diag,
@@ -497,12 +503,6 @@ template <class T>
 __global__ __launch_bounds__(BLOCK) void k_fill(long n, T* __restrict__ x, T v) {
   const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
   if (i < n) x[i] = v;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_copy(long n, const double* __restrict__ a,
-                                                double* __restrict__ b) {
-  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
-  if (i < n) b[i] = a[i];
 }
 
 __device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -659,11 +659,15 @@ __global__ __launch_bounds__(1024) void k_coarse_solve(Level<T> L, int sweeps) {
 // coarsest-level solve in one workgroup with the level held on chip: each
 // thread keeps the right side and the seven coefficients of its cells in
 // registers and x lives in LDS, so the 4*sweeps half-sweeps touch no memory
-constexpr int CS_THREADS = 512, CS_CPT = 4;   // up to 2 * 512 * 4 = 4096 cells
+constexpr int CS_THREADS = 1024, CS_CPT = 2;   // up to 2 * 1024 * 2 = 4096 cells
+// One workgroup per independent x-block of the level (L.blocks of them; the
+// couplings between blocks are zero, as between the boxes of the subdomain
+// hierarchy): the block's coefficients sit in registers, its x in LDS.
 template <class T>
 __global__ __launch_bounds__(CS_THREADS) void k_coarse_solve_lds(Level<T> L, int sweeps) {
   __shared__ T xs[2 * CS_THREADS * CS_CPT];
-  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const int nx = L.nx / L.blocks, ny = L.ny, nz = L.nz;
+  const int base = blockIdx.x * nx * ny * nz;   // first cell of this block
   const int half = nz >> 1;
   const int n2 = nx * ny * half;
   const int tid = threadIdx.x;
@@ -683,14 +687,14 @@ __global__ __launch_bounds__(CS_THREADS) void k_coarse_solve_lds(Level<T> L, int
         const int idx = (i * ny + j) * nz + k;
         const Nb nb = nbrs(i, j, k, nx, ny, nz);
         own[c][m] = idx;
-        cb[c][m] = L.b[idx];
-        cd[c][m] = L.diag[idx];
-        c6[c][m][0] = L.cx[idx];   nb6[c][m][0] = nb.xp;
-        c6[c][m][1] = L.cx[nb.xm]; nb6[c][m][1] = nb.xm;
-        c6[c][m][2] = L.cy[idx];   nb6[c][m][2] = nb.yp;
-        c6[c][m][3] = L.cy[nb.ym]; nb6[c][m][3] = nb.ym;
-        c6[c][m][4] = L.cz[idx];   nb6[c][m][4] = nb.zp;
-        c6[c][m][5] = L.cz[nb.zm]; nb6[c][m][5] = nb.zm;
+        cb[c][m] = L.b[base + idx];
+        cd[c][m] = L.diag[base + idx];
+        c6[c][m][0] = L.cx[base + idx];   nb6[c][m][0] = nb.xp;
+        c6[c][m][1] = L.cx[base + nb.xm]; nb6[c][m][1] = nb.xm;
+        c6[c][m][2] = L.cy[base + idx];   nb6[c][m][2] = nb.yp;
+        c6[c][m][3] = L.cy[base + nb.ym]; nb6[c][m][3] = nb.ym;
+        c6[c][m][4] = L.cz[base + idx];   nb6[c][m][4] = nb.zp;
+        c6[c][m][5] = L.cz[base + nb.zm]; nb6[c][m][5] = nb.zm;
       }
     }
   }
@@ -717,7 +721,7 @@ __global__ __launch_bounds__(CS_THREADS) void k_coarse_solve_lds(Level<T> L, int
       __syncthreads();
     }
   }
-  for (int t = tid; t < 2 * n2; t += CS_THREADS) L.x[t] = xs[t];
+  for (int t = tid; t < 2 * n2; t += CS_THREADS) L.x[base + t] = xs[t];
 }
 
 template <class T, bool SF>
@@ -883,7 +887,8 @@ __global__ __launch_bounds__(BLOCK) void k_box_extract(BoxMap m, const long long
   bz[o] = c.k == m.B - 1 ? 0.0 : cz[g];
 }
 // the residual r - S z left by the V-cycle, on the box cells (S the global
-// operator, z the V-cycle's result)
+// operator, z the V-cycle's result), rounded to the box solve's type
+template <class T>
 __global__ __launch_bounds__(BLOCK) void k_box_residual(BoxMap m, const long long* __restrict__ cells,
                                                          const double* __restrict__ diag,
                                                          const double* __restrict__ cx,
@@ -891,7 +896,7 @@ __global__ __launch_bounds__(BLOCK) void k_box_residual(BoxMap m, const long lon
                                                          const double* __restrict__ cz,
                                                          const double* __restrict__ r,
                                                          const double* __restrict__ z,
-                                                         double* __restrict__ bv) {
+                                                         T* __restrict__ bv) {
   const C3 c = coord3(m.B, m.B);
   if (!c.ok) return;
   const int s = c.i / m.B;
@@ -902,16 +907,89 @@ __global__ __launch_bounds__(BLOCK) void k_box_residual(BoxMap m, const long lon
   y = y - cx[g] * z[nb.xp] - cx[nb.xm] * z[nb.xm];
   y = y - cy[g] * z[nb.yp] - cy[nb.ym] * z[nb.ym];
   y = y - cz[g] * z[nb.zp] - cz[nb.zm] * z[nb.zm];
-  bv[(c.i * m.B + c.j) * m.B + c.k] = r[g] - y;
+  bv[(c.i * m.B + c.j) * m.B + c.k] = (T)(r[g] - y);
 }
 // z += the box's part of y, one box per launch (overlapping boxes add in box order)
+template <class T>
 __global__ __launch_bounds__(BLOCK) void k_box_scatter_add(BoxMap m, const long long* __restrict__ cells,
-                                                            int s, const double* __restrict__ y,
+                                                            int s, const T* __restrict__ y,
                                                             double* __restrict__ z) {
   const C3 c = coord3(m.B, m.B);
   if (!c.ok) return;
   const int g = box_global(m, cells[s], c.i, c.j, c.k);
-  z[g] += y[((s * m.B + c.i) * m.B + c.j) * m.B + c.k];
+  z[g] += (double)y[((s * m.B + c.i) * m.B + c.j) * m.B + c.k];
+}
+
+// ---- inner PCG of the subdomain correction, T the box V-cycle's type (the
+// vectors are kept in it; dot products accumulate in FP64 and leave block
+// partials for the final reduction, which forms the CG scalar).
+// rho = r.z, p = z
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_box_dot1p(long n, const T* __restrict__ r,
+                                                      const T* __restrict__ z, T* __restrict__ p,
+                                                      double* __restrict__ parts) {
+  double acc[1] = {0.0};
+  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (i < n) {
+    const T zv = z[i];
+    p[i] = zv;
+    acc[0] = (double)r[i] * (double)zv;
+  }
+  block_reduce<1>(acc, parts);
+}
+// q = S p (stacked boxes) and the partials of p.q
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_box_spmv(int nx, int ny, int nz, const T* __restrict__ diag,
+                                                     const T* __restrict__ cx, const T* __restrict__ cy,
+                                                     const T* __restrict__ cz, const T* __restrict__ p,
+                                                     T* __restrict__ q, double* __restrict__ parts) {
+  double acc[1] = {0.0};
+  const C3 c = coord3(ny, nz);
+  if (c.ok) {
+    const int idx = (c.i * ny + c.j) * nz + c.k;
+    const Nb nb = nbrs(c.i, c.j, c.k, nx, ny, nz);
+    const T pv = p[idx];
+    T y = diag[idx] * pv;
+    y = y - cx[idx] * p[nb.xp] - cx[nb.xm] * p[nb.xm];
+    y = y - cy[idx] * p[nb.yp] - cy[nb.ym] * p[nb.ym];
+    y = y - cz[idx] * p[nb.zp] - cz[nb.zm] * p[nb.zm];
+    q[idx] = y;
+    acc[0] = (double)pv * (double)y;
+  }
+  block_reduce<1>(acc, parts);
+}
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_box_update_xr(long n, T* __restrict__ x, T* __restrict__ r,
+                                                          const T* __restrict__ p,
+                                                          const T* __restrict__ q,
+                                                          const double* __restrict__ sc) {
+  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const double alpha = sc[S_ALPHA];
+  x[i] = (T)(x[i] + alpha * p[i]);
+  r[i] = (T)(r[i] - alpha * q[i]);
+}
+// the partials of z.r and z.q
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_box_dot2(long n, const T* __restrict__ z,
+                                                     const T* __restrict__ r, const T* __restrict__ q,
+                                                     double* __restrict__ parts) {
+  double acc[2] = {0.0, 0.0};
+  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (i < n) {
+    const double zv = z[i];
+    acc[0] = zv * (double)r[i];
+    acc[1] = zv * (double)q[i];
+  }
+  block_reduce<2>(acc, parts);
+}
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_box_update_p(long n, T* __restrict__ p,
+                                                         const T* __restrict__ z,
+                                                         const double* __restrict__ sc) {
+  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (i >= n) return;
+  p[i] = (T)(z[i] + sc[S_BETA] * p[i]);
 }
 
 // FP64 natural -> FP32 colour-split finest level
@@ -1021,13 +1099,16 @@ void launch_schur(const DevParams& P, const double* U, const double* f, const do
 }
 
 void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(1024), 0, st, parts, nparts, ncomp, out);
+  hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(1024), 0, st, parts, nparts, ncomp, out,
+                     (double*)nullptr, 0);
 }
-void launch_cg_alpha(double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, st, sc);
+void launch_final_reduce_alpha(const double* parts, int nparts, double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(1024), 0, st, parts, nparts, 1, sc + S_PQ,
+                     sc, 1);
 }
-void launch_cg_beta(double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, st, sc);
+void launch_final_reduce_beta(const double* parts, int nparts, double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(1024), 0, st, parts, nparts, 2, sc + S_ZR,
+                     sc, 2);
 }
 
 void launch_spmv_dot(int nx, int ny, int nz, const double* diag, const double* cx,
@@ -1052,9 +1133,6 @@ void launch_update_p(long n, double* p, const double* z, const double* sc, hipSt
   hipLaunchKernelGGL(k_update_p, grid_for(n), dim3(BLOCK), 0, st, n, p, z, sc);
 }
 
-void launch_copy(long n, const double* a, double* b, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy, grid_for(n), dim3(BLOCK), 0, st, n, a, b);
-}
 template <class T>
 void launch_fill(long n, T* x, T v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<T>, grid_for(n), dim3(BLOCK), 0, st, n, x, v);
@@ -1084,7 +1162,7 @@ void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, const doubl
 }
 template <class T>
 void launch_coarse_solve_lds(const Level<T>& L, int sweeps, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarse_solve_lds<T>, dim3(1), dim3(CS_THREADS), 0, st, L, sweeps);
+  hipLaunchKernelGGL(k_coarse_solve_lds<T>, dim3(L.blocks), dim3(CS_THREADS), 0, st, L, sweeps);
 }
 template <class T>
 void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st) {
@@ -1117,19 +1195,62 @@ void launch_box_extract(int nx, int ny, int nz, int B, int nbox, const long long
   const Geo q = geo3(nbox * B, B, B);
   hipLaunchKernelGGL(k_box_extract, q.g, q.b, 0, st, m, cells, diag, cx, cy, cz, bd, bx, by, bz);
 }
+template <class T>
 void launch_box_residual(int nx, int ny, int nz, int B, int nbox, const long long* cells,
                          const double* diag, const double* cx, const double* cy, const double* cz,
-                         const double* r, const double* z, double* bv, hipStream_t st) {
+                         const double* r, const double* z, T* bv, hipStream_t st) {
   const BoxMap m{nx, ny, nz, B, nbox};
   const Geo q = geo3(nbox * B, B, B);
-  hipLaunchKernelGGL(k_box_residual, q.g, q.b, 0, st, m, cells, diag, cx, cy, cz, r, z, bv);
+  hipLaunchKernelGGL(k_box_residual<T>, q.g, q.b, 0, st, m, cells, diag, cx, cy, cz, r, z, bv);
 }
+template <class T>
 void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
-                            const double* y, double* z, hipStream_t st) {
+                            const T* y, double* z, hipStream_t st) {
   const BoxMap m{nx, ny, nz, B, nbox};
   const Geo q = geo3(B, B, B);
-  hipLaunchKernelGGL(k_box_scatter_add, q.g, q.b, 0, st, m, cells, s, y, z);
+  hipLaunchKernelGGL(k_box_scatter_add<T>, q.g, q.b, 0, st, m, cells, s, y, z);
 }
+template <class T>
+int launch_box_dot1p(long n, const T* r, const T* z, T* p, double* parts, hipStream_t st) {
+  hipLaunchKernelGGL(k_box_dot1p<T>, grid_for(n), dim3(BLOCK), 0, st, n, r, z, p, parts);
+  return (int)grid_for(n).x;
+}
+template <class T>
+int launch_box_spmv(const Level<T>& L, const T* p, T* q, double* parts, hipStream_t st) {
+  const Geo g = geo3(L.nx, L.ny, L.nz);
+  hipLaunchKernelGGL(k_box_spmv<T>, g.g, g.b, 0, st, L.nx, L.ny, L.nz, L.diag, L.cx, L.cy, L.cz,
+                     p, q, parts);
+  return (int)(g.g.x * g.g.y * g.g.z);
+}
+template <class T>
+void launch_box_update_xr(long n, T* x, T* r, const T* p, const T* q, const double* sc,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_box_update_xr<T>, grid_for(n), dim3(BLOCK), 0, st, n, x, r, p, q, sc);
+}
+template <class T>
+int launch_box_dot2(long n, const T* z, const T* r, const T* q, double* parts, hipStream_t st) {
+  hipLaunchKernelGGL(k_box_dot2<T>, grid_for(n), dim3(BLOCK), 0, st, n, z, r, q, parts);
+  return (int)grid_for(n).x;
+}
+template <class T>
+void launch_box_update_p(long n, T* p, const T* z, const double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_box_update_p<T>, grid_for(n), dim3(BLOCK), 0, st, n, p, z, sc);
+}
+#define RT_BOX_INST(T)                                                                          \
+  template void launch_box_residual<T>(int, int, int, int, int, const long long*, const double*, \
+                                       const double*, const double*, const double*,            \
+                                       const double*, const double*, T*, hipStream_t);          \
+  template void launch_box_scatter_add<T>(int, int, int, int, int, const long long*, int,       \
+                                          const T*, double*, hipStream_t);                      \
+  template int launch_box_dot1p<T>(long, const T*, const T*, T*, double*, hipStream_t);        \
+  template int launch_box_spmv<T>(const Level<T>&, const T*, T*, double*, hipStream_t);         \
+  template void launch_box_update_xr<T>(long, T*, T*, const T*, const T*, const double*,        \
+                                        hipStream_t);                                           \
+  template int launch_box_dot2<T>(long, const T*, const T*, const T*, double*, hipStream_t);   \
+  template void launch_box_update_p<T>(long, T*, const T*, const double*, hipStream_t);
+RT_BOX_INST(double)
+RT_BOX_INST(float)
+#undef RT_BOX_INST
 void launch_cvt_d2f_level(const Level<float>& L, const double* a, float* b, hipStream_t st) {
   if (L.split) {
     const Geo q = geo3(L.nx, L.ny, L.nz);

@@ -85,6 +85,7 @@ class Workload:
     box_size: int = 0          # > 0: subdomain correction on a box around each source
     box_levels: int = 3
     box_inner: int = 6
+    box_coarse_sweeps: int = 0  # coarsest box level's sweeps (0: mg_coarse_sweeps)
     mg_levels: int = 3
     mg_pre: int = 2
     mg_post: int = 2

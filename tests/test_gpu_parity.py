@@ -211,8 +211,10 @@ def test_newton_steps_256_spacing_forcing():
 
 def test_newton_steps_source_boxes():
     """The source-subdomain correction on both sides (one 16^3 box, 4 inner
-    PCG iterations on a 2-level box V-cycle): equal counts, fields to 1e-10."""
-    w = synth.CFG_256.replace(n=64, mg_levels=4, box_size=16, box_levels=2, box_inner=4)
+    PCG iterations on a 2-level box V-cycle with 3 coarsest sweeps): equal
+    counts, fields to 1e-10."""
+    w = synth.CFG_256.replace(n=64, mg_levels=4, box_size=16, box_levels=2, box_inner=4,
+                              box_coarse_sweeps=3)
     newton_parity(w, synth.initial_state(w), steps=3)
 
 
