@@ -59,7 +59,7 @@ BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0
 # kernel source it was measured on and is reported as null for any other.
 PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "dots": False,
                              "bytes_per_launch": 4.078e8,
-                             "kernels_sha256": "9b30a86968cd02187ecd3337a893b622f2fab2e00a3bfa9f18ec0017fd36f7d3"}}
+                             "kernels_sha256": "0973b5d9f9138534533f24c4d5b6345d84421cbb50ba5d17cd96428c76b232bc"}}
 
 
 def kernels_sha256():
