@@ -45,8 +45,8 @@ HBM_PEAK_GBS = 8000.0
 #              the 3 couplings, write x                                = 6 w
 #              FP32 cycle's last half-sweep: 4 w, write z (FP64, both
 #              colours), read r and q (FP64) for the CG dots           = 4 w + 24 B
-#              (without the dots, when the subdomain correction follows
-#              the V-cycle and changes z                               = 4 w + 8 B)
+#              (the subdomain correction, when on, adds its own part of
+#              the dots over the box cells)
 # (w = 4 B for the FP32 V-cycle, 8 B for FP64)
 BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0}
 
@@ -71,8 +71,7 @@ def kernels_sha256():
 def rbgs_fine_per_vcycle(pre, post, w, dots=True):
     """(launches, algorithmic bytes per cell) of the fine-level smoothing in one
     V-cycle of the CG loop; in the FP32 cycle the last half-sweep writes the
-    FP64 result and, unless a subdomain correction follows, forms the CG dots
-    (pre, post > 0 there)."""
+    FP64 result and forms the CG dots (pre, post > 0 there)."""
     if pre > 0:
         launches = 1 + 2 * (pre - 1) + 2 * post
         b = 6.0 * w + (2 * (pre - 1) + 2 * post) * 5.0 * w
@@ -186,8 +185,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
     # roofline of the dominant kernel class
     wbytes = 4.0 if mode.startswith("mixed") else 8.0
     p = sim.grid.params
-    launches_vc, bytes_vc = rbgs_fine_per_vcycle(p.mg_pre, p.mg_post, wbytes,
-                                                 dots=p.box_size == 0)
+    launches_vc, bytes_vc = rbgs_fine_per_vcycle(p.mg_pre, p.mg_post, wbytes)
     cnt, ms = kt[dom]
     if dom == "rbgs_fine":
         total_bytes = cnt / float(launches_vc) * bytes_vc * N
@@ -200,7 +198,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
         tr = PMC_TRAFFIC.get(dom)
         traffic = None
         if (tr and tr["w"] == wbytes and tr["n"] == n and tr["pre_post"] == (p.mg_pre, p.mg_post)
-                and tr["dots"] == (p.box_size == 0) and kernels_sha256() == tr["kernels_sha256"]):
+                and tr["dots"] and kernels_sha256() == tr["kernels_sha256"]):
             traffic = tr["bytes_per_launch"]
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",

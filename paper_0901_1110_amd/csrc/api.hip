@@ -89,10 +89,12 @@ struct rt_grid {
   // launches replayed by one), valid for the (r, z, nbox) it was captured for
   bool graphs = true;
   hipStream_t cap_st = nullptr;
-  hipGraphExec_t box_exec = nullptr;
-  const double* box_r = nullptr;
-  double* box_z = nullptr;
-  int box_n = 0;
+  struct BoxGraph {
+    hipGraphExec_t exec = nullptr;
+    const double* r = nullptr;
+    double* z = nullptr;
+    int nbox = 0, dots = 0;
+  } box_graph[2];           // without and with the dot partials
   std::string err;
 };
 
@@ -219,7 +221,9 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
   w->p = c.take<double>(N);
   w->q = c.take<double>(N);
   {
-    const size_t sb = (size_t)stencil_blocks(p->nx, p->ny, p->nz);
+    size_t sb = (size_t)stencil_blocks(p->nx, p->ny, p->nz);
+    if (p->box_size > 0)   // the corrections' own dot partials follow the V-cycle's
+      sb += (size_t)p->max_sources * stencil_blocks(p->box_size, p->box_size, p->box_size);
     w->nparts_cap = sb > (size_t)MAX_PARTS ? sb : (size_t)MAX_PARTS;
     w->parts = c.take<double>(w->nparts_cap * NCOMP_MAX);
   }
@@ -299,14 +303,16 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
 
 // extent of the box levels in use for nbox boxes (0: no subdomain correction)
 void drop_box_graph(rt_grid* g) {
-  if (g->box_exec) (void)hipGraphExecDestroy(g->box_exec);   // nothing to report on release
-  g->box_exec = nullptr;
+  for (auto& b : g->box_graph) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);   // nothing to report on release
+    b.exec = nullptr;
+  }
 }
 
 void set_box_extent(rt_grid* g, int nbox) {
   Workspace& w = g->w;
   g->nbox = (g->prm.box_size > 0 && nbox > 0 && nbox <= w.box_cap) ? nbox : 0;
-  if (g->nbox != g->box_n) drop_box_graph(g);
+  drop_box_graph(g);
   const int B = g->prm.box_size;
   const int blocks = g->nbox > 0 ? g->nbox : 1;   // the boxes are uncoupled
   for (size_t l = 0; l < w.B64.size(); ++l) {
@@ -452,8 +458,10 @@ template <> std::vector<Level<float>>& box_hier<float>(Workspace& w) { return w.
 // flexible PCG from zero with the box V-cycle, all in T (the V-cycle's
 // type; FP64 dots).  The iterations run without host read-back, so the whole
 // sequence is fixed and can be captured.
+// dots > 0: the V-cycle left that many partials of z.r and z.q (q = w.q) in
+// w.parts; the scatter appends those of the correction
 template <class T>
-void box_correct_t(rt_grid* g, const double* r, double* z) {
+void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
   Workspace& w = g->w;
   hipStream_t st = g->st;
   const int B = g->prm.box_size;
@@ -486,21 +494,27 @@ void box_correct_t(rt_grid* g, const double* r, double* z) {
     TK(g, RT_K_BOX, launch_box_update_p<T>(n, bp, bz, w.bsc, st));
   }
   // boxes may overlap: one launch per box, in source order
+  const int nbb = stencil_blocks(B, B, B);
   for (int s = 0; s < g->nbox; ++s)
     TK(g, RT_K_BOX, launch_box_scatter_add<T>(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells,
-                                              s, x, z, st));
+                                              s, x, z, r, w.q,
+                                              dots > 0 ? w.parts + (size_t)(dots + s * nbb) * NCOMP_MAX
+                                                       : nullptr,
+                                              st));
   g->tk_override = -1;
 }
 
-void box_correct_launches(rt_grid* g, const double* r, double* z) {
-  if (g->prm.mg_fp32) box_correct_t<float>(g, r, z);
-  else box_correct_t<double>(g, r, z);
+void box_correct_launches(rt_grid* g, const double* r, double* z, int dots) {
+  if (g->prm.mg_fp32) box_correct_t<float>(g, r, z, dots);
+  else box_correct_t<double>(g, r, z, dots);
 }
 
-// capture the correction for (r, z) on a private stream (the caller's stream
-// may be the null stream, which cannot be captured); nothing runs meanwhile
-int capture_box(rt_grid* g, const double* r, double* z) {
-  drop_box_graph(g);
+// capture the correction for (r, z, dots) on a private stream (the caller's
+// stream may be the null stream, which cannot be captured); nothing runs
+// meanwhile
+int capture_box(rt_grid* g, rt_grid::BoxGraph& bg, const double* r, double* z, int dots) {
+  if (bg.exec) (void)hipGraphExecDestroy(bg.exec);   // nothing to report on release
+  bg.exec = nullptr;
   if (!g->cap_st) HIPCHK(g, hipStreamCreateWithFlags(&g->cap_st, hipStreamNonBlocking));
   hipStream_t caller = g->st;
   const bool timing = g->tm.on;
@@ -509,52 +523,57 @@ int capture_box(rt_grid* g, const double* r, double* z) {
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    box_correct_launches(g, r, z);
+    box_correct_launches(g, r, z, dots);
     e = hipStreamEndCapture(g->st, &graph);
   }
   g->st = caller;
   g->tm.on = timing;
-  if (e == hipSuccess) e = hipGraphInstantiate(&g->box_exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphInstantiate(&bg.exec, graph, nullptr, nullptr, 0);
   if (graph) {
     const hipError_t e2 = hipGraphDestroy(graph);
     if (e == hipSuccess) e = e2;
   }
   if (e != hipSuccess) {
-    drop_box_graph(g);
+    if (bg.exec) (void)hipGraphExecDestroy(bg.exec);
+    bg.exec = nullptr;
     return fail(g, RT_EDEVICE, "capturing the subdomain correction: %s", hipGetErrorString(e));
   }
-  g->box_r = r;
-  g->box_z = z;
-  g->box_n = g->nbox;
+  bg.r = r;
+  bg.z = z;
+  bg.nbox = g->nbox;
+  bg.dots = dots;
   return RT_OK;
 }
 
 // one replay of the captured graph (timed as one launch), or with graphs
 // off the launches one by one
-int box_correct(rt_grid* g, const double* r, double* z) {
+int box_correct(rt_grid* g, const double* r, double* z, int dots) {
   if (!g->graphs) {
-    box_correct_launches(g, r, z);
+    box_correct_launches(g, r, z, dots);
     return RT_OK;
   }
-  if (!g->box_exec || g->box_r != r || g->box_z != z || g->box_n != g->nbox)
-    RTCHK(capture_box(g, r, z));
+  rt_grid::BoxGraph& bg = g->box_graph[dots > 0 ? 1 : 0];
+  if (!bg.exec || bg.r != r || bg.z != z || bg.nbox != g->nbox || bg.dots != dots)
+    RTCHK(capture_box(g, bg, r, z, dots));
   hipError_t e = hipSuccess;
-  TK(g, RT_K_BOX, e = hipGraphLaunch(g->box_exec, g->st));
+  TK(g, RT_K_BOX, e = hipGraphLaunch(bg.exec, g->st));
   HIPCHK(g, e);
   return RT_OK;
 }
 
 // the CG preconditioner: the V-cycle, plus the source-subdomain correction
-// when one is configured.  *nd: what apply_vcycle returns for dots (0 with
-// the correction: the dots must follow it)
+// when one is configured.  *nd: the number of partials of z.r and z.q the
+// application left in w.parts (the FP32 cycle forms them when dots is set;
+// the correction then adds its own), else 0
 int apply_precond(rt_grid* g, const double* r, double* z, bool dots, int* nd) {
+  const int nv = apply_vcycle(g, r, z, dots);
   if (g->nbox == 0) {
-    *nd = apply_vcycle(g, r, z, dots);
+    *nd = nv;
     return RT_OK;
   }
-  apply_vcycle(g, r, z, false);
-  *nd = 0;
-  return box_correct(g, r, z);
+  *nd = nv > 0 ? nv + g->nbox * stencil_blocks(g->prm.box_size, g->prm.box_size, g->prm.box_size)
+               : 0;
+  return box_correct(g, r, z, nv);
 }
 
 int read_scalars(rt_grid* g, const double* d, double* h, int n) {

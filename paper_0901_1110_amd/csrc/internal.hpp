@@ -105,10 +105,12 @@ template <class T>
 void launch_box_residual(int nx, int ny, int nz, int B, int nbox, const long long* cells,
                          const double* diag, const double* cx, const double* cy, const double* cz,
                          const double* r, const double* z, T* bv, hipStream_t st);
-// z += box s's part of the stacked vector y
+// z += box s's part of the stacked vector y; parts non-null: also the
+// stencil_blocks(B, B, B) block partials of y.r and y.q over the box
 template <class T>
 void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
-                            const T* y, double* z, hipStream_t st);
+                            const T* y, double* z, const double* r, const double* q,
+                            double* parts, hipStream_t st);
 // inner PCG of the correction on the stacked boxes (level L: the box
 // operator in T); the reduction launches return their partial count
 template <class T>

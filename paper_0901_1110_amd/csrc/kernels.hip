@@ -909,15 +909,28 @@ __global__ __launch_bounds__(BLOCK) void k_box_residual(BoxMap m, const long lon
   y = y - cz[g] * z[nb.zp] - cz[nb.zm] * z[nb.zm];
   bv[(c.i * m.B + c.j) * m.B + c.k] = (T)(r[g] - y);
 }
-// z += the box's part of y, one box per launch (overlapping boxes add in box order)
+// z += the box's part of y, one box per launch (overlapping boxes add in box
+// order); with parts, also the block partials of y.r and y.q over the box,
+// which complete the V-cycle's own partials of z.r and z.q
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_box_scatter_add(BoxMap m, const long long* __restrict__ cells,
                                                             int s, const T* __restrict__ y,
-                                                            double* __restrict__ z) {
+                                                            double* __restrict__ z,
+                                                            const double* __restrict__ r,
+                                                            const double* __restrict__ q,
+                                                            double* __restrict__ parts) {
   const C3 c = coord3(m.B, m.B);
-  if (!c.ok) return;
-  const int g = box_global(m, cells[s], c.i, c.j, c.k);
-  z[g] += (double)y[((s * m.B + c.i) * m.B + c.j) * m.B + c.k];
+  double acc[2] = {0.0, 0.0};
+  if (c.ok) {
+    const int g = box_global(m, cells[s], c.i, c.j, c.k);
+    const double yv = (double)y[((s * m.B + c.i) * m.B + c.j) * m.B + c.k];
+    z[g] += yv;
+    if (parts) {
+      acc[0] = yv * r[g];
+      acc[1] = yv * q[g];
+    }
+  }
+  if (parts) block_reduce<2>(acc, parts);
 }
 
 // ---- inner PCG of the subdomain correction, T the box V-cycle's type (the
@@ -1205,10 +1218,11 @@ void launch_box_residual(int nx, int ny, int nz, int B, int nbox, const long lon
 }
 template <class T>
 void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
-                            const T* y, double* z, hipStream_t st) {
+                            const T* y, double* z, const double* r, const double* q,
+                            double* parts, hipStream_t st) {
   const BoxMap m{nx, ny, nz, B, nbox};
-  const Geo q = geo3(B, B, B);
-  hipLaunchKernelGGL(k_box_scatter_add<T>, q.g, q.b, 0, st, m, cells, s, y, z);
+  const Geo gq = geo3(B, B, B);
+  hipLaunchKernelGGL(k_box_scatter_add<T>, gq.g, gq.b, 0, st, m, cells, s, y, z, r, q, parts);
 }
 template <class T>
 int launch_box_dot1p(long n, const T* r, const T* z, T* p, double* parts, hipStream_t st) {
@@ -1241,7 +1255,8 @@ void launch_box_update_p(long n, T* p, const T* z, const double* sc, hipStream_t
                                        const double*, const double*, const double*,            \
                                        const double*, const double*, T*, hipStream_t);          \
   template void launch_box_scatter_add<T>(int, int, int, int, int, const long long*, int,       \
-                                          const T*, double*, hipStream_t);                      \
+                                          const T*, double*, const double*, const double*,     \
+                                          double*, hipStream_t);                                \
   template int launch_box_dot1p<T>(long, const T*, const T*, T*, double*, hipStream_t);        \
   template int launch_box_spmv<T>(const Level<T>&, const T*, T*, double*, hipStream_t);         \
   template void launch_box_update_xr<T>(long, T*, T*, const T*, const T*, const double*,        \

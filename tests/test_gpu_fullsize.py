@@ -98,13 +98,20 @@ def test_residual_and_schur_sampled_blocks(full, c0):
     assert rel(inner(block(b, c0)), inner(so["b"])) <= 1e-12
 
 
-@pytest.mark.parametrize("mg_fp32", [0, 1])
-def test_full_step_properties(full, mg_fp32):
+# the benchmark's default preconditioner: the 32^3 subdomain correction with
+# a two-level box V-cycle (4 coarsest sweeps) and 16 inner iterations, and
+# the inexact-Newton forcing 1e-6
+BENCH = dict(box_size=32, box_levels=2, box_inner=16, box_coarse_sweeps=4, pcg_forcing=1e-6)
+
+
+@pytest.mark.parametrize("mg_fp32,over", [(0, {}), (1, {}), (0, BENCH), (1, BENCH)])
+def test_full_step_properties(full, mg_fp32, over):
     s, sim0 = full
     # start from the state after one step (shared fixture), run one more step
     st_in = dict(U=host(sim0.Un), nH=s["nH"], eh=host(sim0.eh), src_cells=s["src_cells"],
                  src_Q=s["src_Q"])
-    sim = Simulation(W, state={k: (v.copy() if hasattr(v, "copy") else v) for k, v in st_in.items()},
+    sim = Simulation(W.replace(**over),
+                     state={k: (v.copy() if hasattr(v, "copy") else v) for k, v in st_in.items()},
                      mg_fp32=mg_fp32)
     sim.step_index = 1
     st = sim.step()
