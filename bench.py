@@ -30,6 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Newton-step cell-updates/s at 256^3, mixed+learned vs plain FP64, Newton tol 1e-6"
+METRIC_SG = "Newton-step cell-updates/s, expanding-universe I-front (Sec. 4.6), Newton tol 1e-6"
+WORKLOAD_HII = ("hii_256: %d^3 periodic hydrogen, centred 5e48 photons/s source, 13.2 kpc box, "
+                "dt=1e11 s, theta=1, Newton tol 1e-6, PCG rtol 1e-8%s, 5-level V-cycle RB-GS 2+2%s")
+WORKLOAD_SG = ("sg_q05_z4: %d^3 periodic uniform hydrogen, 0.625 kpc proper cells at z=4, "
+               "centred 5e48 photons/s source, isothermal 1e4 K, Einstein-de Sitter from z=4, "
+               "dt=2e15 s, theta=1, Newton tol 1e-6, PCG rtol 1e-8%s, 4-level V-cycle RB-GS 2+2%s")
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per cell and launch of each kernel class (H-only, FP64
@@ -123,15 +129,16 @@ def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None, box=(0, 3, 
     return theta, info
 
 
-def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 0)):
+def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 0),
+             workload="hii_256"):
     import torch
     import synth
     from paper_0901_1110_amd.binding import RtNet
     from paper_0901_1110_amd.driver import LearnedSimulation, Simulation
 
-    w = synth.CFG_256.replace(n=n, mg_fp32=1 if mode.startswith("mixed") else 0,
-                              pcg_forcing=forcing, box_size=box[0], box_levels=box[1],
-                              box_inner=box[2], box_coarse_sweeps=box[3])
+    w = synth.WORKLOADS[workload].replace(
+        n=n, mg_fp32=1 if mode.startswith("mixed") else 0, pcg_forcing=forcing,
+        box_size=box[0], box_levels=box[1], box_inner=box[2], box_coarse_sweeps=box[3])
     if mode.endswith("learned"):
         net = RtNet(1, (n, n, n))
         net.set_params(theta)
@@ -215,17 +222,17 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
     return res
 
 
-def cpu_baseline(n=128, box=(0, 3, 6, 0)):
+def cpu_baseline(n=128, box=(0, 3, 6, 0), workload="hii_256"):
     """The oracle on a bounded sample: the first implicit step of the same
-    256^3-spacing problem on an n^3 periodic box around the source."""
+    problem (same cell size) on an n^3 periodic box around the source."""
     from threadpoolctl import threadpool_limits
 
     import synth
     import oracle
     from oracle import newton
 
-    w = synth.CFG_256.replace(n=n, mg_levels=4, box_size=box[0], box_levels=box[1],
-                              box_inner=box[2], box_coarse_sweeps=box[3])
+    w = synth.WORKLOADS[workload].replace(n=n, mg_levels=4, box_size=box[0], box_levels=box[1],
+                                          box_inner=box[2], box_coarse_sweeps=box[3])
     m = oracle.model_from_workload(w)
     s = synth.initial_state(w)
     with threadpool_limits(limits=1):
@@ -235,9 +242,9 @@ def cpu_baseline(n=128, box=(0, 3, 6, 0)):
         dt = time.perf_counter() - t0
     return {"value": n ** 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": "first implicit step (status %d, %d Newton its, %d CG its) of the "
-                      "256^3-spacing centred-source problem on a %d^3 periodic box, same "
-                      "preconditioner, NumPy FP64, 1 thread, %.1f s"
-                      % (st["status"], st["newton_its"], sum(st["cg_its"]), n, dt)}
+                      "%s problem (same cell size) on a %d^3 periodic box around the source, "
+                      "same preconditioner, NumPy FP64, 1 thread, %.1f s"
+                      % (st["status"], st["newton_its"], sum(st["cg_its"]), workload, n, dt)}
 
 
 def main():
@@ -245,15 +252,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--modes", default="plain,mixed,learned,mixed+learned")
+    ap.add_argument("--modes", default=None,
+                    help="default plain,mixed,learned,mixed+learned (plain,mixed for sg_q05_z4)")
     ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=200)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--workload", default="hii_256", choices=["hii_256", "sg_q05_z4"],
+                    help="hii_256: the timed 256^3 HII region; sg_q05_z4: the expanding-universe "
+                         "I-front of Sec. 4.6 at 128^3 (cell size fixed, --n sets the box)")
+    ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--pcg-forcing", type=float, default=1e-6,
                     help="inexact-Newton forcing factor delta_k / ||f(U_k)|| (Sec. 3.2.1; "
                          "0: the fixed relative CG tolerance alone)")
-    ap.add_argument("--box-size", type=int, default=32,
-                    help="source-subdomain correction: box edge in cells (0: V-cycle alone)")
+    ap.add_argument("--box-size", type=int, default=None,
+                    help="source-subdomain correction: box edge in cells (0: V-cycle alone; "
+                         "default 32 for hii_256, 0 for sg_q05_z4)")
     ap.add_argument("--box-levels", type=int, default=2)
     ap.add_argument("--box-inner", type=int, default=16)
     ap.add_argument("--box-coarse-sweeps", type=int, default=4,
@@ -276,7 +288,17 @@ def main():
         print("# copy calibration: 3 x %d bytes read + written" % (8 << 28), file=sys.stderr,
               flush=True)
         del a, b
+    if args.n is None:
+        args.n = 256 if args.workload == "hii_256" else 128
+    if args.box_size is None:
+        args.box_size = 32 if args.workload == "hii_256" else 0
+    if args.modes is None:
+        args.modes = "plain,mixed,learned,mixed+learned" if args.workload == "hii_256" \
+            else "plain,mixed"
     modes = [m for m in args.modes.split(",") if m]
+    if args.workload != "hii_256" and any(m.endswith("learned") for m in modes):
+        print("the learned guess is trained for the HII-region workload only", file=sys.stderr)
+        sys.exit(2)
     box = (args.box_size, args.box_levels, args.box_inner, args.box_coarse_sweeps)
     results = {}
     theta, train_info = None, None
@@ -290,21 +312,20 @@ def main():
         print("# mode %s: %d warm-up + %d timed steps at %d^3" % (mode, args.warmup, args.steps, args.n),
               file=sys.stderr, flush=True)
         results[mode] = run_mode(mode, args.steps, args.warmup, args.n, theta, args.pcg_forcing,
-                                 box)
+                                 box, args.workload)
         print("# %s: %.3e cell-updates/s, %.1f ms/step" % (mode, results[mode]["value"],
                                                           results[mode]["ms_per_step"]),
               file=sys.stderr, flush=True)
     head = next((m for m in ("mixed+learned", "mixed", "learned") if m in results), modes[0])
     H = results[head]
     line = {
-        "metric": METRIC, "value": H["value"], "unit": "cell-updates/s", "n_gpus": 1,
+        "metric": METRIC if args.workload == "hii_256" else METRIC_SG,
+        "value": H["value"], "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": H["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32" if head.startswith("mixed") else "f64",
         "data": "synthetic",
-        "config": {"workload": "hii_256: %d^3 periodic hydrogen, centred 5e48 photons/s source, "
-                               "13.2 kpc box, dt=1e11 s, theta=1, Newton tol 1e-6, PCG rtol 1e-8%s, "
-                               "5-level V-cycle RB-GS 2+2%s" % (
+        "config": {"workload": (WORKLOAD_HII if args.workload == "hii_256" else WORKLOAD_SG) % (
                                    args.n, " or ||r|| <= %g ||f(U_k)|| (inexact-Newton forcing)"
                                    % args.pcg_forcing if args.pcg_forcing > 0 else "",
                                    ", then a %d^3 source-subdomain correction (%d inner PCG its, "
@@ -326,7 +347,8 @@ def main():
         line["speedup_vs_plain"] = H["value"] / results["plain"]["value"]
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(box=box)
+        line["cpu_baseline"] = (cpu_baseline(box=box) if args.workload == "hii_256"
+                                else cpu_baseline(64, box, args.workload))
     print(json.dumps(line), flush=True)
     with open(os.path.join(ROOT, "gpurun_out", "bench_kernels.json") if os.path.isdir(
             os.path.join(ROOT, "gpurun_out")) else os.devnull, "w") as fh:

@@ -150,7 +150,22 @@ CFG_HHE = Workload(
     centred=False, x0=(0.9999, 0.9999, 1.0e-4), E0=1.0e-20 * _A0 ** 3,
     u_E=1.0e-20 * _A0 ** 3, a_start=_A0, a_end=_A1, mg_levels=6, mg_fp32=1)
 
-WORKLOADS = {w.name: w for w in (CFG_SMALL, CFG_COSMO, CFG_256, CFG_HHE)}
+# Cosmological I-front of Sec. 4.6, case q0 = 0.5, z_i = 4: uniform hydrogen
+# of proper density 1.175e-28 g/cm^3 at z_i (n_H = rho / m_H), isothermal at
+# 1e4 K, the single 5e48 photons/s source of Sec. 4.5, E = 1e-35 erg/cm^3 and
+# no ionization at the start; Einstein-de Sitter expansion from a = 0.2.  The
+# paper's 80 kpc (proper at z_i) box, periodic with a centred source, 50
+# steps of 2e15 s (to z = 1.08, while the front stays inside the box).
+_A_SG = 0.2
+_M_H_G = 1.6726e-24          # g per hydrogen atom (input conversion only)
+_DT_SG = 2.0e15
+CFG_SG = Workload(
+    name="sg_q05_z4", n=128, dx=80.0 * KPC_CM / _A_SG / 128, dt=_DT_SG, steps=50,
+    nH_mean=1.175e-28 / _M_H_G * _A_SG ** 3, x0=(1.0,), E0=1.0e-35 * _A_SG ** 3,
+    u_E=1.0e-20 * _A_SG ** 3, isothermal=1, T_iso=1.0e4, a_start=_A_SG,
+    a_end=eds_scale_factor(eds_time(_A_SG) + 50 * _DT_SG), mg_levels=4)
+
+WORKLOADS = {w.name: w for w in (CFG_SMALL, CFG_COSMO, CFG_256, CFG_HHE, CFG_SG)}
 
 
 # --- generators ---------------------------------------------------------------
