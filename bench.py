@@ -130,11 +130,11 @@ def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None, box=(0, 3, 
 
 
 def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 0),
-             workload="hii_256"):
+             workload="hii_256", adaptive=0.0):
     import torch
     import synth
     from paper_0901_1110_amd.binding import RtNet
-    from paper_0901_1110_amd.driver import LearnedSimulation, Simulation
+    from paper_0901_1110_amd.driver import AdaptiveSimulation, LearnedSimulation, Simulation
 
     w = synth.WORKLOADS[workload].replace(
         n=n, mg_fp32=1 if mode.startswith("mixed") else 0, pcg_forcing=forcing,
@@ -144,6 +144,9 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
         net.set_params(theta)
         sim = LearnedSimulation(w, net)
         warmup = max(warmup, 2)
+    elif adaptive > 0.0:
+        # adaptive steps (max-norm estimate), at most ten times the fixed step
+        sim = AdaptiveSimulation(w, adaptive, p=0.0, dt_max=10.0 * w.dt)
     else:
         sim = Simulation(w)
     # the warm-up times every kernel class to find the dominant one; the timed
@@ -185,6 +188,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
     res = dict(mode=mode, cells=N, steps=steps, wall_s=wall, event_ms=gpu_ms,
                value=N * steps / wall, ms_per_step=1e3 * wall / steps,
                newton_its=newton, cg_its=cg, vcycles=vc,
+               model_seconds_per_s=sum(st_.get("dt", w.dt) for st_ in stats) / wall,
                cell_newton_its_per_s=N * newton / wall, kernels_warmup=kt_warm,
                network_guess_used=sum(s["used_alt_guess"] for s in stats),
                fnorm0_mean=sum(min(s["fnorm_guess"], s["fnorm_alt"]) if s["fnorm_alt"] >= 0
@@ -270,6 +274,9 @@ def main():
     ap.add_argument("--box-inner", type=int, default=16)
     ap.add_argument("--box-coarse-sweeps", type=int, default=4,
                     help="sweeps of the coarsest box level (0: those of the main hierarchy)")
+    ap.add_argument("--adaptive", type=float, default=0.0,
+                    help="tau_tol > 0: adaptive steps with the explicit predictor as the guess "
+                         "(plain and mixed modes; 0: the fixed step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 2 GiB device copy (counter calibration)")
@@ -296,6 +303,10 @@ def main():
         args.modes = "plain,mixed,learned,mixed+learned" if args.workload == "hii_256" \
             else "plain,mixed"
     modes = [m for m in args.modes.split(",") if m]
+    if args.adaptive > 0.0 and any(m.endswith("learned") for m in modes):
+        print("--adaptive offers the predictor as the guess: plain and mixed modes only",
+              file=sys.stderr)
+        sys.exit(2)
     if args.workload != "hii_256" and any(m.endswith("learned") for m in modes):
         print("the learned guess is trained for the HII-region workload only", file=sys.stderr)
         sys.exit(2)
@@ -312,7 +323,7 @@ def main():
         print("# mode %s: %d warm-up + %d timed steps at %d^3" % (mode, args.warmup, args.steps, args.n),
               file=sys.stderr, flush=True)
         results[mode] = run_mode(mode, args.steps, args.warmup, args.n, theta, args.pcg_forcing,
-                                 box, args.workload)
+                                 box, args.workload, args.adaptive)
         print("# %s: %.3e cell-updates/s, %.1f ms/step" % (mode, results[mode]["value"],
                                                           results[mode]["ms_per_step"]),
               file=sys.stderr, flush=True)
@@ -335,7 +346,7 @@ def main():
                    "mode": head, "grid": args.n, "parallelism": "single GPU"},
         "roofline": H.get("roofline"),
         "modes": {k: {kk: v[kk] for kk in ("value", "ms_per_step", "newton_its", "cg_its",
-                                           "vcycles", "cell_newton_its_per_s",
+                                           "vcycles", "cell_newton_its_per_s", "model_seconds_per_s",
                                            "network_guess_used", "fnorm0_mean")
                       if kk in v} | ({"box_correction": v["box_correction"]}
                                      if "box_correction" in v else {})

@@ -185,6 +185,25 @@ int rt_mg_vcycle(rt_grid* g, const double* d_r, double* d_z);
 int rt_mg_pcg_solve(rt_grid* g, const double* d_b, double* d_sE, double rtol,
                     int32_t maxit, int32_t* h_iters, double* h_relres);
 
+/* Explicit predictor (Sec. 3.2.4, Eq. 44): writes d_Upred [nv][N] =
+ * U^n - dt [L_e; L_n; D_E + L_E](U^n) + dt [0; 0; 4 pi eta], the forward
+ * Euler step of the system (Eq. 44 printed with the tendency's sign such
+ * that it steps backwards; this is the forward step), expansion factors
+ * a_old, H_old and the limiter at U^n, then projected onto the physical
+ * bounds (fractions into [0, 1], the helium pair to a sum <= 1, E >= 0) with
+ * e_c kept at its t^n value where e_h + e_c would not be positive.  Also
+ * stores the lagged face coefficients, as rt_time_level does.  Meant as the
+ * d_Ualt guess of rt_newton_step.  d_Upred must not be d_Un (RT_EINVAL). */
+int rt_predict(rt_grid* g, const double* d_Un, double dt, const rt_cosmo* c, double* d_Upred);
+
+/* Time-error estimate of Sec. 3.2.3 (Eqs. 41-42) between the new state and
+ * the predictor, in the normalized unknowns U_v / u_v: with
+ * w = sqrt(|a b|) + 1 and q = |a - b| / w per cell and unknown,
+ * *h_eps = (sum q^p / (N nv))^(1/p) for p > 0, max q for p <= 0 (the max
+ * norm).  Synchronises the stream.  RT_EINVAL for a non-finite p. */
+int rt_time_error(rt_grid* g, const double* d_Unew, const double* d_Upred, double p,
+                  double* h_eps);
+
 /* One implicit time step (Sec. 3.2): time level from d_Un, Newton from the
  * guess in d_U (in: U_0, out: U^{n+1}).  If d_Ualt is not NULL it is a
  * second candidate guess: the one with the smaller initial residual norm is

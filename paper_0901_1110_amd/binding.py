@@ -103,6 +103,8 @@ SIGNATURES = {
     "rt_fold_energy": [_P, _P, _P],
     "rt_timing": [_P, _I, ctypes.POINTER(RtKernelTiming)],
     "rt_timing_classes": [_P, ctypes.c_uint32],
+    "rt_predict": [_P, _P, _D, ctypes.POINTER(RtCosmo), _P],
+    "rt_time_error": [_P, _P, _P, _D, ctypes.POINTER(ctypes.c_double)],
     "rt_use_graphs": [_P, ctypes.c_int32],
     "rt_spectrum_constants": [_I, _D, _P, _P, _P, ctypes.POINTER(_D)],
     "rt_net_workspace_bytes": [_I, _I, _I, _I, ctypes.POINTER(ctypes.c_uint64)],
@@ -273,6 +275,21 @@ class RtGrid:
         self._check(lib().rt_time_level(self.h, _ptr(Un), float(dt), ctypes.byref(cc), _ptr(gn)),
                     "rt_time_level")
         return gn
+
+    def rt_predict(self, Un, dt, c, Up=None):
+        """Explicit predictor of the step (projected forward Euler update)."""
+        Up = self.new_state() if Up is None else Up
+        cc = cosmo(c)
+        self._check(lib().rt_predict(self.h, _ptr(Un), float(dt), ctypes.byref(cc), _ptr(Up)),
+                    "rt_predict")
+        return Up
+
+    def rt_time_error(self, Unew, Upred, p=0.0):
+        """Time-error estimate between the new state and the predictor (p <= 0: max norm)."""
+        out = ctypes.c_double(0.0)
+        self._check(lib().rt_time_error(self.h, _ptr(Unew), _ptr(Upred), float(p), ctypes.byref(out)),
+                    "rt_time_error")
+        return out.value
 
     def rt_eval_residual(self, U, gn, dt, c, f=None, norm=True):
         f = self.new_state() if f is None else f

@@ -798,6 +798,39 @@ int rt_time_level(rt_grid* g, const double* d_Un, double dt, const rt_cosmo* c, 
   return time_level(g, d_Un, dt, c, d_gn);
 }
 
+int rt_predict(rt_grid* g, const double* d_Un, double dt, const rt_cosmo* c, double* d_Upred) {
+  RTCHK(check_ready(g, false));
+  if (!d_Un || !d_Upred || !c) return fail(g, RT_EINVAL, "null argument");
+  if (d_Upred == d_Un) return fail(g, RT_EINVAL, "d_Upred must not be d_Un");
+  const DevParams& P = g->P;
+  DevParams P0 = P;
+  P0.theta = 0.0;   // the explicit part of a theta = 0 step is the forward Euler update
+  TK(g, RT_K_TIMELEVEL, launch_faces(P, d_Un, g->nH, c->a_old, g->w.D, g->st));
+  TK(g, RT_K_TIMELEVEL, launch_explicit(P0, d_Un, g->nH, g->eh, g->w.D, Step{dt, c->a_old, c->H_old},
+                                        d_Upred, g->st));
+  const double scale = dt * P.hnu / (P.dx * P.dx * P.dx);
+  TK(g, RT_K_TIMELEVEL, launch_sources(g->w.src_cells, g->w.src_Q, g->nsrc, scale,
+                                       d_Upred + (size_t)(P.nv - 1) * P.N, g->st));
+  TK(g, RT_K_TIMELEVEL, launch_predict_project(P, d_Un, g->eh, d_Upred, g->st));
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+int rt_time_error(rt_grid* g, const double* d_Unew, const double* d_Upred, double p, double* h_eps) {
+  if (!g) return RT_EINVAL;
+  if (!d_Unew || !d_Upred || !h_eps) return fail(g, RT_EINVAL, "null argument");
+  if (!std::isfinite(p)) return fail(g, RT_EINVAL, "p must be finite (p <= 0: max norm)");
+  const DevParams& P = g->P;
+  int nb = 0;
+  TK(g, RT_K_REDUCE, nb = launch_time_error(P, d_Unew, d_Upred, p, g->w.parts, g->st));
+  TK(g, RT_K_REDUCE, launch_final_summax(g->w.parts, nb, g->w.sc + S_TSUM, g->st));
+  double h[2];
+  RTCHK(read_scalars(g, g->w.sc + S_TSUM, h, 2));
+  *h_eps = p > 0.0 ? std::pow(h[0] / ((double)P.N * P.nv), 1.0 / p) : h[1];
+  if (!std::isfinite(*h_eps)) return fail(g, RT_ENONFINITE, "non-finite time-error estimate");
+  return RT_OK;
+}
+
 int rt_eval_residual(rt_grid* g, const double* d_U, const double* d_gn, double dt,
                      const rt_cosmo* c, double* d_f, double* h_rms) {
   RTCHK(check_ready(g, true));

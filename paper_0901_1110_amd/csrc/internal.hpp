@@ -20,7 +20,8 @@ inline int reduce_blocks(long n) {
 }
 
 // Indices of the device scalar slots used by CG.
-enum Scalar { S_RHO = 0, S_PQ, S_ALPHA, S_RR, S_ZR, S_ZQ, S_BETA, S_BB, S_FN, S_VIOL, S_COUNT };
+enum Scalar { S_RHO = 0, S_PQ, S_ALPHA, S_RR, S_ZR, S_ZQ, S_BETA, S_BB, S_FN, S_VIOL, S_TSUM, S_TMAX,
+              S_COUNT };
 
 struct Step {     // per-call time-step data
   double dt, a, H;
@@ -36,6 +37,13 @@ void launch_sources(const long long* cells, const double* Q, int n, double scale
 void launch_residual(const DevParams& P, const double* U, const double* g, const double* nH,
                      const double* eh, const double* D, Step s, double* f, double* parts,
                      hipStream_t st);
+// explicit predictor: projection of U^n - dt L(U^n) + sources (already in Up)
+void launch_predict_project(const DevParams& P, const double* Un, const double* eh, double* Up,
+                            hipStream_t st);
+// time-error partials (sum of q^p for p > 0, max q); returns the partial count
+int launch_time_error(const DevParams& P, const double* A, const double* B, double p,
+                      double* parts, hipStream_t st);
+void launch_final_summax(const double* parts, int nparts, double* out, hipStream_t st);
 void launch_trial(const DevParams& P, const double* U, const double* ftM, const double* W,
                   const double* sE, double lambda, double* Ut, hipStream_t st);
 void launch_local_jac(const DevParams& P, const double* U, const double* nH, const double* eh,

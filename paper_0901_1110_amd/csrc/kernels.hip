@@ -230,6 +230,106 @@ __global__ __launch_bounds__(BLOCK) void k_trial(DevParams P, const double* __re
   for (int r = 0; r < NS + 2; ++r) Ut[r * N + idx] = v[r];
 }
 
+// the explicit predictor's projection (Sec. 3.2.4): fractions into [0, 1]
+// (the helium pair rescaled to a sum <= 1), E >= 0, and e_c kept at its
+// value at t^n where e_h + e_c would not be positive
+template <int NS>
+__global__ __launch_bounds__(BLOCK) void k_predict_project(DevParams P, const double* __restrict__ Un,
+                                                          const double* __restrict__ eh,
+                                                          double* __restrict__ Up) {
+  const int N = P.N;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= N) return;
+  double v[NS + 2];
+#pragma unroll
+  for (int r = 0; r < NS + 2; ++r) v[r] = Up[r * N + idx];
+#pragma unroll
+  for (int r = 1; r <= NS; ++r) v[r] = fmin(fmax(v[r], 0.0), 1.0);
+  if constexpr (NS == 3) {
+    const double tot = v[2] + v[3];
+    if (tot > 1.0) {
+      v[2] = v[2] / tot;
+      v[3] = v[3] / tot;
+    }
+  }
+  v[NS + 1] = fmax(v[NS + 1], 0.0);
+  if (!(eh[idx] + v[0] > 0.0)) v[0] = Un[idx];
+#pragma unroll
+  for (int r = 0; r < NS + 2; ++r) Up[r * N + idx] = v[r];
+}
+
+// time-error estimate (Sec. 3.2.3, Eqs. 41-42) in the normalized unknowns:
+// q = |a - b| / (sqrt(|a b|) + 1); block partials of sum q^p (p > 0) and of
+// max q
+template <int NS>
+__global__ __launch_bounds__(BLOCK) void k_time_error(DevParams P, const double* __restrict__ A,
+                                                     const double* __restrict__ B, double p,
+                                                     double* __restrict__ parts) {
+  constexpr int NV = NS + 2;
+  const int N = P.N;
+  double sum = 0.0, mx = 0.0;
+  for (int idx = blockIdx.x * BLOCK + threadIdx.x; idx < N; idx += gridDim.x * BLOCK) {
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const double sc = r == 0 ? P.u_e : (r == NV - 1 ? P.u_E : 1.0);
+      const double a = A[(size_t)r * N + idx] / sc, b = B[(size_t)r * N + idx] / sc;
+      const double q = fabs(a - b) / (sqrt(fabs(a * b)) + 1.0);
+      mx = fmax(mx, q);
+      if (p > 0.0) sum += p == 2.0 ? q * q : (p == 1.0 ? q : pow(q, p));
+    }
+  }
+  __shared__ double sh[BLOCK / 64][2];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sum += __shfl_xor(sum, off, 64);
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6][0] = sum;
+    sh[threadIdx.x >> 6][1] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0, m = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) {
+      s += sh[w][0];
+      m = fmax(m, sh[w][1]);
+    }
+    parts[(size_t)blockIdx.x * NCOMP_MAX] = s;
+    parts[(size_t)blockIdx.x * NCOMP_MAX + 1] = m;
+  }
+}
+// out[0] = sum of the partials' first components (fixed order), out[1] = max
+// of the second
+__global__ __launch_bounds__(1024) void k_final_summax(const double* __restrict__ parts, int nparts,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[1024 / 64][2];
+  double s = 0.0, m = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 1024) {
+    s += parts[(size_t)i * NCOMP_MAX];
+    m = fmax(m, parts[(size_t)i * NCOMP_MAX + 1]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    m = fmax(m, __shfl_xor(m, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6][0] = s;
+    sh[threadIdx.x >> 6][1] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0, u = 0.0;
+    for (int w = 0; w < 1024 / 64; ++w) {
+      t += sh[w][0];
+      u = fmax(u, sh[w][1]);
+    }
+    out[0] = t;
+    out[1] = u;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // local Jacobian blocks by forward-mode differentiation of local_ops
 template <int NS>
@@ -1082,6 +1182,23 @@ void launch_residual(const DevParams& P, const double* U, const double* g, const
   else hipLaunchKernelGGL(k_residual<3>, q.g, q.b, 0, st, P, U, g, nH, eh, D, s, f, parts);
 }
 
+void launch_predict_project(const DevParams& P, const double* Un, const double* eh, double* Up,
+                            hipStream_t st) {
+  if (P.ns == 1)
+    hipLaunchKernelGGL(k_predict_project<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, eh, Up);
+  else
+    hipLaunchKernelGGL(k_predict_project<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, eh, Up);
+}
+int launch_time_error(const DevParams& P, const double* A, const double* B, double p,
+                      double* parts, hipStream_t st) {
+  const int nb = reduce_blocks(P.N);
+  if (P.ns == 1) hipLaunchKernelGGL(k_time_error<1>, dim3(nb), dim3(BLOCK), 0, st, P, A, B, p, parts);
+  else hipLaunchKernelGGL(k_time_error<3>, dim3(nb), dim3(BLOCK), 0, st, P, A, B, p, parts);
+  return nb;
+}
+void launch_final_summax(const double* parts, int nparts, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_final_summax, dim3(1), dim3(1024), 0, st, parts, nparts, out);
+}
 void launch_trial(const DevParams& P, const double* U, const double* ftM, const double* W,
                   const double* sE, double lambda, double* Ut, hipStream_t st) {
   if (P.ns == 1)

@@ -43,6 +43,44 @@ class Simulation:
         self.step_index += 1
 
 
+class AdaptiveSimulation(Simulation):
+    """Steps of adaptive length (Sec. 3.2.3): the explicit predictor is
+    offered as the Newton guess, the time-error estimate between the new
+    state and the predictor sets the next step, dt <- min(tau dt / eps,
+    dt_max); a step whose Newton iteration fails is retried at half length."""
+
+    def __init__(self, w, tau, p=0.0, dt_max=None, device="cuda", state=None, **overrides):
+        super().__init__(w, device=device, state=state, **overrides)
+        self.tau, self.p = float(tau), float(p)
+        self.dt = float(w.dt)
+        self.dt_max = float(dt_max) if dt_max is not None else 1.0e3 * self.dt
+        self.t = 0.0
+        self.Up = self.grid.new_state()
+        self.eps = None
+
+    def step(self, Ualt=None, max_halvings=10):
+        for _ in range(max_halvings + 1):
+            c = self.w.cosmology_at(self.t, self.dt)
+            self.grid.rt_predict(self.Un, self.dt, c, self.Up)
+            self.U.copy_(self.Un)
+            st = self.grid.rt_newton_step(self.Un, self.U, self.dt, c, Ualt=self.Up)
+            st["dt"] = self.dt
+            if st["status"] == 0:
+                self.eps = self.grid.rt_time_error(self.U, self.Up, self.p)
+                st["eps"] = self.eps
+                return st
+            self.dt *= 0.5
+        return st
+
+    def advance(self):
+        self.grid.rt_fold_energy(self.U, self.eh)
+        self.Un, self.U = self.U, self.Un
+        self.step_index += 1
+        self.t += self.dt
+        eps = self.eps
+        self.dt = self.dt_max if not eps > 0.0 else min(self.tau * self.dt / eps, self.dt_max)
+
+
 class LearnedSimulation(Simulation):
     """Simulation whose Newton guess is the better (by initial residual) of
     U^n and the network's proposal from levels n and n-1."""

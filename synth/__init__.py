@@ -113,6 +113,16 @@ class Workload:
         a_n = eds_scale_factor(t0 + (step + 1) * self.dt)
         return (a_o, eds_hubble(a_o), a_n, eds_hubble(a_n))
 
+    def cosmology_at(self, t: float, dt: float):
+        """(a_old, H_old, a_new, H_new) for a step of length dt starting a time
+        t after the first step's start (variable steps)."""
+        if self.a_end is None:
+            return self.cosmology(0)
+        t0 = eds_time(self.a_start)
+        a_o = eds_scale_factor(t0 + t)
+        a_n = eds_scale_factor(t0 + t + dt)
+        return (a_o, eds_hubble(a_o), a_n, eds_hubble(a_n))
+
 
 # --- the five workloads -----------------------------------------------------
 # Periodic 13.2 kpc box (twice the 6.6 kpc octant of Sec. 4.5, so a centred

@@ -1,0 +1,98 @@
+"""Explicit predictor and adaptive time steps (Sec. 3.2.3, Eqs. 41-43;
+Sec. 3.2.4, Eq. 44) through the C ABI, against the oracle.
+
+- rt_predict equals the oracle's predictor on random physical states
+  (hydrogen and hydrogen+helium, a = 1 and a = 0.5, large and small steps,
+  so that the projection and the e_c rule act);
+- rt_time_error equals the oracle's estimate for the max norm and p = 1, 2, 3;
+- an adaptive run (predictor offered as the guess, next step from the
+  estimate) takes the same step lengths, guess choices and Newton counts as
+  the oracle's, on the static HII region and on the expanding medium.
+"""
+import numpy as np
+import pytest
+
+import synth
+import oracle
+from oracle import timestep as ots
+from paper_0901_1110_amd.driver import AdaptiveSimulation
+from tests.gpu_cases import dev, host, pair, random_case, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("ns,a,dt_scale", [(1, 1.0, 1.0), (1, 0.5, 1.0), (3, 0.5, 1.0),
+                                            (1, 1.0, 1e-4), (3, 1.0, 1e-4)])
+def test_predict_parity(ns, a, dt_scale):
+    w, c = random_case(ns, 16, 1.0, a, seed=11 + ns)
+    m, g = pair(w, c)
+    dt = c["dt"] * dt_scale
+    ref = ots.predictor(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], dt, c["cosmo"], m)
+    Up = host(g.rt_predict(dev(c["Un"]), dt, c["cosmo"]))
+    for v in range(m.nv):
+        s = max(float(np.max(np.abs(ref[v]))), float(np.max(np.abs(c["Un"][v]))))
+        assert rel(Up[v], ref[v], s) <= 1e-12, v
+
+
+@pytest.mark.parametrize("p", [0.0, 1.0, 2.0, 3.0])
+def test_time_error_parity(p):
+    w, c = random_case(3, 16, 1.0, 1.0, seed=4)
+    m, g = pair(w, c)
+    A = c["U"].copy()
+    B = c["Un"].copy()
+    ref = ots.time_error(A, B, m, np.inf if p == 0.0 else p)
+    got = g.rt_time_error(dev(A), dev(B), p)
+    assert abs(got / ref - 1.0) <= 1e-12, (got, ref)
+
+
+def oracle_adaptive(w, tau, p, dt_max, steps):
+    m = oracle.model_from_workload(w)
+    s = synth.initial_state(w)
+    U, eh = s["U"].copy(), s["eh"].copy()
+    t, dt = 0.0, w.dt
+    out = []
+    for _ in range(steps):
+        for _ in range(11):   # a failed step is retried at half length, as the driver does
+            c = w.cosmology_at(t, dt)
+            U1, st, _, eps = ots.adaptive_step(U, s["nH"], eh, s["src_cells"], s["src_Q"], dt, c,
+                                               m, np.inf if p == 0.0 else p)
+            if st["status"] == 0:
+                break
+            dt *= 0.5
+        assert st["status"] == 0, st
+        out.append((dt, st["newton_its"], st["cg_its"], st["used_predictor"], eps, U1.copy()))
+        eh = eh + U1[0]
+        U1[0] = 0.0
+        U = U1
+        t += dt
+        dt = ots.next_dt(dt, eps, tau, dt_max)
+    return out
+
+
+@pytest.mark.parametrize("name", ["hii", "cosmo"])
+def test_adaptive_run_parity(name):
+    if name == "hii":
+        w = synth.CFG_SMALL.replace(n=16, dx=synth.CFG_SMALL.dx * 2, dt=1e9)
+        tau, p, dt_max = 0.02, 0.0, 1e12
+    else:
+        w = synth.CFG_COSMO.replace(n=32, mg_levels=3)
+        tau, p, dt_max = 0.05, 2.0, 1e14
+    steps = 6
+    ref = oracle_adaptive(w, tau, p, dt_max, steps)
+    sim = AdaptiveSimulation(w, tau, p=p, dt_max=dt_max)
+    for k in range(steps):
+        st = sim.step()
+        assert st["status"] == 0, st
+        dt_o, its_o, cg_o, used_o, eps_o, U_o = ref[k]
+        assert abs(st["dt"] / dt_o - 1.0) <= 1e-9, (k, st["dt"], dt_o)
+        assert st["newton_its"] == its_o and st["cg_its"] == cg_o, (k, st, its_o, cg_o)
+        assert st["used_alt_guess"] == used_o, k
+        # the estimate compares two states that agree with the oracle's to
+        # ~1e-10, so tiny estimates carry that noise
+        assert abs(st["eps"] - eps_o) <= 1e-6 * eps_o + 1e-9, (k, st["eps"], eps_o)
+        U = host(sim.U)
+        for v in range(U.shape[0]):
+            assert rel(U[v], U_o[v]) <= 1e-8, (k, v)
+        sim.advance()
+    # the controller moved the step
+    assert len({round(r[0], 3) for r in ref}) > 1
