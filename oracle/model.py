@@ -36,6 +36,8 @@ HNU_HEII = 54.4 * EV
 SIGMA_HI = 6.30e-18          # threshold cross sections (cm^2), readings
 SIGMA_HEI = 7.42e-18
 SIGMA_HEII = 1.575e-18
+SIGMA_SB = 5.670374419e-5    # Stefan-Boltzmann constant (erg cm^-2 s^-1 K^-4)
+A_RAD = 4.0 * SIGMA_SB / C_LIGHT   # radiation constant a_r
 KAPPA_FLOOR_CELLS = 1.0e-3   # face opacity floor: 1e-3 per proper cell width
 E_FLOOR = 1.0e-300           # guards E_face in R = |dE| / E
 
@@ -58,6 +60,13 @@ class Model:
     hnu_mean: float          # erg per source photon
     limiter_mode: int = 0    # 0: flux limiter; 1: constant D0 (test mode)
     D0: float = 0.0
+    # LTE coupling (Sec. 2.1, Eq. 9): no species equations (nspecies = 0),
+    # constant proper absorption and Planck-mean coefficients, fixed mean
+    # particle mass mu m_H
+    lte: int = 0
+    kappa_lte: float = 0.0
+    kappaP_lte: float = 0.0
+    mu_lte: float = 0.6
     newton_tol: float = 1e-6
     newton_maxit: int = 20
     pcg_rtol: float = 1e-8
@@ -144,5 +153,6 @@ def model_from_workload(w, **overrides) -> Model:
               mg_post=w.mg_post, mg_coarse_sweeps=w.mg_coarse_sweeps,
               mg_fp32=w.mg_fp32, pcg_forcing=w.pcg_forcing, box_size=w.box_size,
               box_levels=w.box_levels, box_inner=w.box_inner,
-              box_coarse_sweeps=w.box_coarse_sweeps)
+              box_coarse_sweeps=w.box_coarse_sweeps, lte=w.lte, kappa_lte=w.kappa_lte,
+              kappaP_lte=w.kappaP_lte, mu_lte=w.mu_lte)
     return dataclasses.replace(m, **overrides) if overrides else m

@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .model import (ALPHA_B_1E4, ALPHA_HEII_1E4, ALPHA_HEIII_1E4, ALPHA_T_EXP,
+from .model import (A_RAD, ALPHA_B_1E4, ALPHA_HEII_1E4, ALPHA_HEIII_1E4, ALPHA_T_EXP,
                     BETA_COOL, C_LIGHT, GAMMA, K_B, M_H)
 
 
@@ -58,7 +58,10 @@ def recombination_coefficients(T):
 
 
 def opacity(U, nH, a, model):
-    """Proper absorption coefficient kappa (1/cm) from the species fractions."""
+    """Proper absorption coefficient kappa (1/cm) from the species fractions
+    (LTE: the constant coefficient)."""
+    if model.lte:
+        return model.kappa_lte + 0.0 * U[0].real
     xHI, xHeI, xHeII, _ = species_fractions(U, model.nspecies)
     n_p = nH / a ** 3
     K = model.K_kappa
@@ -68,12 +71,31 @@ def opacity(U, nH, a, model):
     return k
 
 
+def local_operators_lte(U, nH, eh, a, H, model):
+    """LTE coupling (Sec. 2.1, Eq. 9): eta = kappa_P sigma_SB T^4 / pi,
+    G = c kappa E / rho, Lambda = 4 pi eta / rho, with T from the ideal gas
+    (Eq. 7) at the fixed mean particle mass mu m_H; U = (e_c, E).  Here
+    4 pi eta = c kappa_P a_r T^4 depends on U and stays in L_E."""
+    ec, E = U[0], U[-1]
+    a3 = a ** 3
+    rho_p = M_H * (nH / a3) * (1.0 + 4.0 * model.y_he)
+    T = (GAMMA - 1.0) * model.mu_lte * M_H * (eh + ec) / K_B
+    emit = C_LIGHT * model.kappaP_lte * A_RAD * T ** 4        # 4 pi eta (proper)
+    absorb = C_LIGHT * model.kappa_lte * E                     # comoving
+    L = np.empty(U.shape, dtype=np.result_type(U, nH, eh, complex if np.iscomplexobj(U) else float))
+    L[0] = 2.0 * H * ec - absorb / a3 / rho_p + emit / rho_p
+    L[-1] = model.m * H * E + absorb - a3 * emit
+    return L
+
+
 def local_operators(U, nH, eh, a, H, model):
     """Return L with rows (L_e, L_x1..L_xNs, L_E_local), same shape as U.
 
     L_E_local excludes the diffusion term and the source emissivity (the
     emissivity does not depend on U; it enters the constant vector g).
     """
+    if model.lte:
+        return local_operators_lte(U, nH, eh, a, H, model)
     ns = model.nspecies
     y = model.y_he
     ec, E = U[0], U[-1]

@@ -86,6 +86,10 @@ class Workload:
     box_levels: int = 3
     box_inner: int = 6
     box_coarse_sweeps: int = 0  # coarsest box level's sweeps (0: mg_coarse_sweeps)
+    lte: int = 0                # 1: LTE coupling, no species (nspecies = 0)
+    kappa_lte: float = 0.0      # LTE absorption coefficient (proper, 1/cm)
+    kappaP_lte: float = 0.0     # LTE Planck-mean coefficient (proper, 1/cm)
+    mu_lte: float = 0.6         # LTE mean particle mass (units of m_H)
     mg_levels: int = 3
     mg_pre: int = 2
     mg_post: int = 2
@@ -167,7 +171,7 @@ CFG_HHE = Workload(
 # paper's 80 kpc (proper at z_i) box, periodic with a centred source, 50
 # steps of 2e15 s (to z = 1.08, while the front stays inside the box).
 _A_SG = 0.2
-_M_H_G = 1.6726e-24          # g per hydrogen atom (input conversion only)
+_M_H_G = 1.6735575e-24       # g per hydrogen atom (input conversion only)
 _DT_SG = 2.0e15
 CFG_SG = Workload(
     name="sg_q05_z4", n=128, dx=80.0 * KPC_CM / _A_SG / 128, dt=_DT_SG, steps=50,
@@ -175,7 +179,20 @@ CFG_SG = Workload(
     u_E=1.0e-20 * _A_SG ** 3, isothermal=1, T_iso=1.0e4, a_start=_A_SG,
     a_end=eds_scale_factor(eds_time(_A_SG) + 50 * _DT_SG), mg_levels=4)
 
-WORKLOADS = {w.name: w for w in (CFG_SMALL, CFG_COSMO, CFG_256, CFG_HHE, CFG_SG)}
+# Matter-radiation equilibration of Sec. 4.2 (LTE coupling, Eq. 9): a uniform
+# medium of one opacity 4e-8 /cm (absorption and Planck mean), density
+# 1e-7 g/cm^3 (n_H = rho / m_H), mean particle mass 0.6 m_H, E = 1e12
+# erg/cm^3, gas energy density 1e10 (hot start) or 1e2 (cold start) erg/cm^3,
+# 4^3 periodic cells, no sources, 250 steps of 1e-9 s to t = 2.5e-7 s.
+_RHO_TS = 1.0e-7
+CFG_TS_HOT = Workload(
+    name="ts_hot", n=4, dx=1.0, nspecies=0, x0=(), lte=1, kappa_lte=4.0e-8, kappaP_lte=4.0e-8,
+    mu_lte=0.6, nH_mean=_RHO_TS / _M_H_G, Q=0.0, E0=1.0e12, u_E=1.0e12,
+    eh0=1.0e10 / _RHO_TS, u_e=1.0e15, dt=1.0e-9, steps=250, mg_levels=1, newton_tol=1e-10)
+CFG_TS_COLD = CFG_TS_HOT.replace(name="ts_cold", eh0=1.0e2 / _RHO_TS)
+
+WORKLOADS = {w.name: w for w in (CFG_SMALL, CFG_COSMO, CFG_256, CFG_HHE, CFG_SG, CFG_TS_HOT,
+                                 CFG_TS_COLD)}
 
 
 # --- generators ---------------------------------------------------------------

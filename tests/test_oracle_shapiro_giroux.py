@@ -24,7 +24,7 @@ from tests.sg_closed_form import front_radius, ionized_radius, stromgren_radius
 HERE = os.path.dirname(__file__)
 SG = json.load(open(os.path.join(HERE, "golden", "shapiro_giroux_q05_z4.json")))
 ILIEV = json.load(open(os.path.join(HERE, "golden", "iliev_test1.json")))
-M_H = 1.6726e-24
+M_H = 1.6735575e-24   # hydrogen atom (g): n_H = rho_b / m_H
 
 
 def sg_constants(w):
