@@ -58,7 +58,7 @@ typedef enum rt_status {
 /* Problem and solver parameters (plain old data; copied at rt_create_grid). */
 typedef struct rt_params {
   int32_t nx, ny, nz;
-  int32_t nspecies;         /* 1: HI; 3: HI, HeI, HeII (Sec. 2, Eq. 4) */
+  int32_t nspecies;         /* 1: HI; 3: HI, HeI, HeII (Sec. 2, Eq. 4); 0: LTE */
   double  dx;               /* comoving cell width (cm) */
   double  theta;            /* theta-scheme weight in (0, 1] (Sec. 3.2) */
   double  u_e, u_E;         /* unit scales of e_c and E (Sec. 3.2.2, Eq. 36) */
@@ -93,6 +93,11 @@ typedef struct rt_params {
   int32_t box_inner;
   int32_t box_coarse_sweeps; /* coarsest box level: this many (red,black) then     */
                              /* (black,red) (0: mg_coarse_sweeps)                 */
+  int32_t lte;              /* 1: LTE coupling (Sec. 2.1, Eq. 9), nspecies = 0,  */
+                            /* U = (e_c, E); 0: the non-LTE rates              */
+  double  kappa_lte;        /* LTE absorption coefficient (proper, 1/cm)        */
+  double  kappaP_lte;       /* LTE Planck-mean coefficient (proper, 1/cm)       */
+  double  mu_lte;           /* LTE mean particle mass (units of m_H)            */
 } rt_params;
 
 /* Scale factor a and adot/a at t^n (old) and t^{n+1} (new). */

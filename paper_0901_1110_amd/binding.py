@@ -38,6 +38,8 @@ class RtParams(ctypes.Structure):
         ("max_sources", ctypes.c_int32), ("pcg_forcing", ctypes.c_double),
         ("box_size", ctypes.c_int32), ("box_levels", ctypes.c_int32), ("box_inner", ctypes.c_int32),
         ("box_coarse_sweeps", ctypes.c_int32),
+        ("lte", ctypes.c_int32), ("kappa_lte", ctypes.c_double), ("kappaP_lte", ctypes.c_double),
+        ("mu_lte", ctypes.c_double),
     ]
 
 
@@ -196,6 +198,7 @@ def params_from_workload(w, **overrides) -> RtParams:
     p.pcg_forcing = w.pcg_forcing
     p.box_size, p.box_levels, p.box_inner = w.box_size, w.box_levels, w.box_inner
     p.box_coarse_sweeps = w.box_coarse_sweeps
+    p.lte, p.kappa_lte, p.kappaP_lte, p.mu_lte = w.lte, w.kappa_lte, w.kappaP_lte, w.mu_lte
     for k, v in overrides.items():
         if k in ("K_gamma", "K_kappa", "K_heat"):
             getattr(p, k)[:] = list(v)

@@ -165,7 +165,13 @@ bool is_pow2_div(int n, int levels) {
 int validate(const rt_params* p, std::string* why) {
   auto bad = [&](const char* m) { *why = m; return RT_EINVAL; };
   if (!p) return bad("null params");
-  if (p->nspecies != 1 && p->nspecies != 3) return bad("nspecies must be 1 or 3");
+  if (p->lte != 0 && p->lte != 1) return bad("lte must be 0 or 1");
+  if (p->lte ? p->nspecies != 0 : (p->nspecies != 1 && p->nspecies != 3))
+    return bad("nspecies must be 1 or 3 (0 exactly with lte)");
+  if (p->lte && (!(p->kappa_lte >= 0.0) || !(p->kappaP_lte >= 0.0) || !(p->mu_lte > 0.0) ||
+                 !std::isfinite(p->kappa_lte) || !std::isfinite(p->kappaP_lte) ||
+                 !std::isfinite(p->mu_lte)))
+    return bad("LTE coefficients must be finite, kappa >= 0 and mu > 0");
   if (p->mg_levels < 1 || p->mg_levels > 12) return bad("mg_levels out of range");
   if (!is_pow2_div(p->nx, p->mg_levels) || !is_pow2_div(p->ny, p->mg_levels) ||
       !is_pow2_div(p->nz, p->mg_levels))
@@ -722,6 +728,7 @@ int rt_create_grid(const rt_params* p, void* d_ws, uint64_t ws_bytes, void* hip_
   DevParams& P = g->P;
   P.nx = p->nx; P.ny = p->ny; P.nz = p->nz;
   P.ns = p->nspecies; P.nv = p->nspecies + 2; P.nb = p->nspecies + 1;
+  P.kap_lte = p->kappa_lte; P.kapP_lte = p->kappaP_lte; P.mu_lte = p->mu_lte;
   P.N = p->nx * p->ny * p->nz;
   P.iso = p->isothermal; P.lim_mode = p->limiter_mode;
   P.dx = p->dx; P.theta = p->theta; P.u_e = p->u_e; P.u_E = p->u_E;

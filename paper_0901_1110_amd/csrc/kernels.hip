@@ -97,7 +97,7 @@ __global__ __launch_bounds__(BLOCK) void k_faces(DevParams P, const double* __re
   const int idx = (c.i * P.ny + c.j) * P.nz + c.k;
   const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
   const double* E = Un + (NS + 1) * N;
-  double x[NS];
+  double x[NS > 0 ? NS : 1];
   const int nbr[3] = {nb.xp, nb.yp, nb.zp};
 #pragma unroll
   for (int s = 0; s < NS; ++s) x[s] = Un[(1 + s) * N + idx];
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(BLOCK) void k_faces(DevParams P, const double* __re
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int q = nbr[d];
-    double xq[NS];
+    double xq[NS > 0 ? NS : 1];
 #pragma unroll
     for (int s = 0; s < NS; ++s) xq[s] = Un[(1 + s) * N + q];
     const double kQ = opacity<NS>(xq, nH[q], a, P);
@@ -1155,18 +1155,23 @@ int stencil_blocks(int nx, int ny, int nz) {
   return (int)(q.g.x * q.g.y * q.g.z);
 }
 
+// launches KERN<NS> for the grid's species count (0: LTE, 1: H, 3: H + He)
+#define RT_NS(P, KERN, ...)                                            \
+  do {                                                                  \
+    if ((P).ns == 0) hipLaunchKernelGGL((KERN<0>), __VA_ARGS__);        \
+    else if ((P).ns == 1) hipLaunchKernelGGL((KERN<1>), __VA_ARGS__);   \
+    else hipLaunchKernelGGL((KERN<3>), __VA_ARGS__);                    \
+  } while (0)
 void launch_faces(const DevParams& P, const double* Un, const double* nH, double a, double* D,
                   hipStream_t st) {
   const Geo q = geo3(P.nx, P.ny, P.nz);
-  if (P.ns == 1) hipLaunchKernelGGL(k_faces<1>, q.g, q.b, 0, st, P, Un, nH, a, D);
-  else hipLaunchKernelGGL(k_faces<3>, q.g, q.b, 0, st, P, Un, nH, a, D);
+  RT_NS(P, k_faces, q.g, q.b, 0, st, P, Un, nH, a, D);
 }
 
 void launch_explicit(const DevParams& P, const double* Un, const double* nH, const double* eh,
                      const double* D, Step s, double* g, hipStream_t st) {
   const Geo q = geo3(P.nx, P.ny, P.nz);
-  if (P.ns == 1) hipLaunchKernelGGL(k_explicit<1>, q.g, q.b, 0, st, P, Un, nH, eh, D, s, g);
-  else hipLaunchKernelGGL(k_explicit<3>, q.g, q.b, 0, st, P, Un, nH, eh, D, s, g);
+  RT_NS(P, k_explicit, q.g, q.b, 0, st, P, Un, nH, eh, D, s, g);
 }
 
 void launch_sources(const long long* cells, const double* Q, int n, double scale, double* gE,
@@ -1178,22 +1183,17 @@ void launch_residual(const DevParams& P, const double* U, const double* g, const
                      const double* eh, const double* D, Step s, double* f, double* parts,
                      hipStream_t st) {
   const Geo q = geo3(P.nx, P.ny, P.nz);
-  if (P.ns == 1) hipLaunchKernelGGL(k_residual<1>, q.g, q.b, 0, st, P, U, g, nH, eh, D, s, f, parts);
-  else hipLaunchKernelGGL(k_residual<3>, q.g, q.b, 0, st, P, U, g, nH, eh, D, s, f, parts);
+  RT_NS(P, k_residual, q.g, q.b, 0, st, P, U, g, nH, eh, D, s, f, parts);
 }
 
 void launch_predict_project(const DevParams& P, const double* Un, const double* eh, double* Up,
                             hipStream_t st) {
-  if (P.ns == 1)
-    hipLaunchKernelGGL(k_predict_project<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, eh, Up);
-  else
-    hipLaunchKernelGGL(k_predict_project<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, eh, Up);
+  RT_NS(P, k_predict_project, grid_for(P.N), dim3(BLOCK), 0, st, P, Un, eh, Up);
 }
 int launch_time_error(const DevParams& P, const double* A, const double* B, double p,
                       double* parts, hipStream_t st) {
   const int nb = reduce_blocks(P.N);
-  if (P.ns == 1) hipLaunchKernelGGL(k_time_error<1>, dim3(nb), dim3(BLOCK), 0, st, P, A, B, p, parts);
-  else hipLaunchKernelGGL(k_time_error<3>, dim3(nb), dim3(BLOCK), 0, st, P, A, B, p, parts);
+  RT_NS(P, k_time_error, dim3(nb), dim3(BLOCK), 0, st, P, A, B, p, parts);
   return nb;
 }
 void launch_final_summax(const double* parts, int nparts, double* out, hipStream_t st) {
@@ -1201,31 +1201,20 @@ void launch_final_summax(const double* parts, int nparts, double* out, hipStream
 }
 void launch_trial(const DevParams& P, const double* U, const double* ftM, const double* W,
                   const double* sE, double lambda, double* Ut, hipStream_t st) {
-  if (P.ns == 1)
-    hipLaunchKernelGGL(k_trial<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, ftM, W, sE, lambda, Ut);
-  else
-    hipLaunchKernelGGL(k_trial<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, ftM, W, sE, lambda, Ut);
+  RT_NS(P, k_trial, grid_for(P.N), dim3(BLOCK), 0, st, P, U, ftM, W, sE, lambda, Ut);
 }
 
 void launch_local_jac(const DevParams& P, const double* U, const double* nH, const double* eh,
                       Step s, double* M, double* Ucol, double* Lrow, double* dloc,
                       hipStream_t st) {
-  if (P.ns == 1)
-    hipLaunchKernelGGL(k_local_jac<1>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, nH, eh, s, M, Ucol,
-                       Lrow, dloc);
-  else
-    hipLaunchKernelGGL(k_local_jac<3>, grid_for(P.N), dim3(BLOCK), 0, st, P, U, nH, eh, s, M, Ucol,
-                       Lrow, dloc);
+  RT_NS(P, k_local_jac, grid_for(P.N), dim3(BLOCK), 0, st, P, U, nH, eh, s, M, Ucol, Lrow, dloc);
 }
 
 void launch_schur(const DevParams& P, const double* U, const double* f, const double* nH,
                   const double* eh, const double* D, Step s, double* ftM, double* W, double* diag,
                   double* cx, double* cy, double* cz, double* b, hipStream_t st) {
   const Geo q = geo3(P.nx, P.ny, P.nz);
-  if (P.ns == 1)
-    hipLaunchKernelGGL(k_schur<1>, q.g, q.b, 0, st, P, U, f, nH, eh, D, s, ftM, W, diag, cx, cy, cz, b);
-  else
-    hipLaunchKernelGGL(k_schur<3>, q.g, q.b, 0, st, P, U, f, nH, eh, D, s, ftM, W, diag, cx, cy, cz, b);
+  RT_NS(P, k_schur, q.g, q.b, 0, st, P, U, f, nH, eh, D, s, ftM, W, diag, cx, cy, cz, b);
 }
 
 void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out, hipStream_t st) {

@@ -14,6 +14,11 @@
 //   L_HeII = x_HeII Gamma_HeII - x_HeI Gamma_HeI + alpha_HeII n_e x_HeII
 //            - alpha_HeIII n_e x_HeIII
 //   L_E,loc = m H E + c kappa E     (emissivity folded into the time level)
+// LTE coupling (Sec. 2.1, Eq. 9; no species, U = (e_c, E)): with T from the
+// ideal gas at the fixed mean particle mass mu m_H and 4 pi eta =
+// c kappa_P a_r T^4 (4 sigma_SB = c a_r),
+//   L_e     = 2 H e_c - c kappa E_p / rho_p + c kappa_P a_r T^4 / rho_p
+//   L_E,loc = m H E + c kappa E - a^3 c kappa_P a_r T^4
 // The functions are templates on the scalar type so that the same text gives
 // values (double) and exact first derivatives (forward-mode dual numbers).
 #pragma once
@@ -28,6 +33,8 @@ constexpr double M_HYD = 1.6735575e-24;
 constexpr double GAMMA_GAS = 5.0 / 3.0;
 constexpr double T_EXP = -0.7;
 constexpr double BETA_COOL = 0.75;
+constexpr double SIGMA_SB = 5.670374419e-5;
+constexpr double A_RAD = 4.0 * SIGMA_SB / C_LIGHT;
 constexpr double KAPPA_FLOOR = 1.0e-3;   // face opacity floor per proper cell width
 constexpr double E_TINY = 1.0e-300;
 
@@ -40,6 +47,7 @@ struct DevParams {
   double Kg[3], Kk[3], Kh[3];
   double hnu;
   double alpha0[3];   // HII, HeII, HeIII at 1e4 K
+  double kap_lte, kapP_lte, mu_lte;   // LTE coupling (ns = 0)
 };
 
 // ---- forward-mode dual numbers ------------------------------------------
@@ -121,6 +129,19 @@ __device__ inline Dual<K> powc(const Dual<K>& x, double p) {
 template <int NS, class S>
 __device__ inline void local_ops(const S* u, double nH, double eh, double a, double H,
                                  const DevParams& P, S* L) {
+  if constexpr (NS == 0) {
+    const S ec = u[0];
+    const S E = u[1];
+    const double a3 = a * a * a;
+    const double rho = M_HYD * (nH / a3) * (1.0 + 4.0 * P.y);
+    const S T = ((GAMMA_GAS - 1.0) * P.mu_lte * M_HYD / K_BOLTZ) * (eh + ec);
+    const S T2 = T * T;
+    const S emit = (C_LIGHT * P.kapP_lte * A_RAD) * (T2 * T2);
+    const S absorb = (C_LIGHT * P.kap_lte) * E;
+    L[0] = (2.0 * H) * ec - absorb / a3 / rho + emit / rho;
+    L[1] = (P.m * H) * E + absorb - a3 * emit;
+    return;
+  } else {
   const S ec = u[0];
   const S E = u[NS + 1];
   const S xHI = u[1];
@@ -168,11 +189,13 @@ __device__ inline void local_ops(const S* u, double nH, double eh, double a, dou
     L[0] = (2.0 * H) * ec - heat + cool;
   }
   L[NS + 1] = (P.m * H) * E + C_LIGHT * kappa * E;
+  }
 }
 
 // Proper opacity of one cell (for the face coefficients).
 template <int NS>
 __device__ inline double opacity(const double* x, double nH, double a, const DevParams& P) {
+  if constexpr (NS == 0) return P.kap_lte;
   const double np = nH / (a * a * a);
   double k = P.Kk[0] * np * x[0];
   if constexpr (NS == 3) k += P.y * np * (P.Kk[1] * x[1] + P.Kk[2] * x[2]);
