@@ -61,11 +61,11 @@ BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0
 # V(2,2), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by
 # what the counters read for a plain 2 GiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0), averaged over one V-cycle's 7 launches, with the subdomain
-# correction on (the last half-sweep then forms no CG dots).  It belongs to the
+# correction on.  It belongs to the
 # kernel source it was measured on and is reported as null for any other.
-PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "dots": False,
-                             "bytes_per_launch": 4.078e8,
-                             "kernels_sha256": "0973b5d9f9138534533f24c4d5b6345d84421cbb50ba5d17cd96428c76b232bc"}}
+PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "dots": True,
+                             "bytes_per_launch": 4.27e8,
+                             "kernels_sha256": "0cfc2545b4b3db35655d3e687fb4ac7effd0b67f4e6727fc20ba04022055c339"}}
 
 
 def kernels_sha256():
