@@ -98,6 +98,8 @@ typedef struct rt_params {
   double  kappa_lte;        /* LTE absorption coefficient (proper, 1/cm)        */
   double  kappaP_lte;       /* LTE Planck-mean coefficient (proper, 1/cm)       */
   double  mu_lte;           /* LTE mean particle mass (units of m_H)            */
+  int32_t boundary;         /* 0: periodic; 1: reflecting walls on all six      */
+                            /* domain faces (zero diffusive flux through them)  */
 } rt_params;
 
 /* Scale factor a and adot/a at t^n (old) and t^{n+1} (new). */

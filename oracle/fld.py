@@ -34,6 +34,14 @@ def face_coefficients(E, kappa, a, model):
         kf = np.maximum(0.5 * (kappa + kq), KAPPA_FLOOR_CELLS / (a * model.dx))
         R = np.abs(Eq - E) / (a * model.dx * np.maximum(Ef, E_FLOOR))
         out.append(limiter(kf, R))
+    if model.boundary == 1:
+        # reflecting walls: the face after the last cell of each row joins
+        # the domain's two ends and carries no flux
+        for d in range(3):
+            idx = [slice(None)] * 3
+            idx[d] = -1
+            out[d] = out[d].copy()
+            out[d][tuple(idx)] = 0.0
     return out
 
 

@@ -67,6 +67,7 @@ class Model:
     kappa_lte: float = 0.0
     kappaP_lte: float = 0.0
     mu_lte: float = 0.6
+    boundary: int = 0        # 0 periodic; 1 reflecting walls (zero flux on the domain faces)
     newton_tol: float = 1e-6
     newton_maxit: int = 20
     pcg_rtol: float = 1e-8
@@ -154,5 +155,5 @@ def model_from_workload(w, **overrides) -> Model:
               mg_fp32=w.mg_fp32, pcg_forcing=w.pcg_forcing, box_size=w.box_size,
               box_levels=w.box_levels, box_inner=w.box_inner,
               box_coarse_sweeps=w.box_coarse_sweeps, lte=w.lte, kappa_lte=w.kappa_lte,
-              kappaP_lte=w.kappaP_lte, mu_lte=w.mu_lte)
+              kappaP_lte=w.kappaP_lte, mu_lte=w.mu_lte, boundary=w.boundary)
     return dataclasses.replace(m, **overrides) if overrides else m

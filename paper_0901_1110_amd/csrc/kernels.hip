@@ -110,7 +110,10 @@ __global__ __launch_bounds__(BLOCK) void k_faces(DevParams P, const double* __re
 #pragma unroll
     for (int s = 0; s < NS; ++s) xq[s] = Un[(1 + s) * N + q];
     const double kQ = opacity<NS>(xq, nH[q], a, P);
-    D[d * N + idx] = face_D(EP, E[q], kP, kQ, a, P);
+    // reflecting walls: no face joins the last cell of a row to the first
+    const bool wall = P.bc == 1 && (d == 0 ? c.i == P.nx - 1 : (d == 1 ? c.j == P.ny - 1
+                                                                       : c.k == P.nz - 1));
+    D[d * N + idx] = wall ? 0.0 : face_D(EP, E[q], kP, kQ, a, P);
   }
 }
 

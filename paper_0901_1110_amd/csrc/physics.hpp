@@ -48,6 +48,7 @@ struct DevParams {
   double hnu;
   double alpha0[3];   // HII, HeII, HeIII at 1e4 K
   double kap_lte, kapP_lte, mu_lte;   // LTE coupling (ns = 0)
+  int bc;                             // 0 periodic, 1 reflecting walls
 };
 
 // ---- forward-mode dual numbers ------------------------------------------

@@ -90,6 +90,8 @@ class Workload:
     kappa_lte: float = 0.0      # LTE absorption coefficient (proper, 1/cm)
     kappaP_lte: float = 0.0     # LTE Planck-mean coefficient (proper, 1/cm)
     mu_lte: float = 0.6         # LTE mean particle mass (units of m_H)
+    boundary: int = 0           # 0: periodic; 1: reflecting walls
+    corner_source: bool = False  # single source in cell (0, 0, 0) instead of the centre
     mg_levels: int = 3
     mg_pre: int = 2
     mg_post: int = 2
@@ -228,6 +230,8 @@ def sources_for(w: Workload, rng: Optional[np.random.Generator] = None):
     density field, with log10 Q uniform in `logQ_range`.
     """
     n = w.n
+    if w.corner_source:
+        return np.array([0], dtype=np.int64), np.array([w.Q], dtype=np.float64)
     if w.centred:
         c = n // 2
         return (np.array([(c * n + c) * n + c], dtype=np.int64),

@@ -163,8 +163,11 @@ def test_pcg_converges_to_direct_solution():
     assert rel(host(s), s_direct) <= 1e-11
 
 
-def newton_parity(w, state, steps=1, tol_fields=1e-10, mg_fp32=0):
-    """Run `steps` steps on both sides from the same state; compare each step."""
+def newton_parity(w, state, steps=1, tol_fields=1e-10, mg_fp32=0, last_cg_slack=0):
+    """Run `steps` steps on both sides from the same state; compare each step.
+    last_cg_slack: the CG count of a step's last Newton iteration may differ by
+    this much when that iteration starts from a residual below 1e-3 (its right
+    side is then the rounding-level structure of the iterate)."""
     m = oracle.model_from_workload(w)
     from paper_0901_1110_amd.driver import Simulation
     sim = Simulation(w, state={k: v.copy() if hasattr(v, "copy") else v
@@ -178,7 +181,11 @@ def newton_parity(w, state, steps=1, tol_fields=1e-10, mg_fp32=0):
         st = sim.step()
         assert st["status"] == 0 and st_o["status"] == 0, (st, st_o)
         assert st["newton_its"] == st_o["newton_its"], (st, st_o)
-        assert st["cg_its"] == st_o["cg_its"], (st, st_o)
+        if last_cg_slack and st_o["fnorms"][-2] < 1e-3:
+            assert st["cg_its"][:-1] == st_o["cg_its"][:-1], (st, st_o)
+            assert abs(st["cg_its"][-1] - st_o["cg_its"][-1]) <= last_cg_slack, (st, st_o)
+        else:
+            assert st["cg_its"] == st_o["cg_its"], (st, st_o)
         assert st["lambdas"] == st_o["lambdas"]
         U = host(sim.U)
         for v in range(m.nv):
@@ -240,3 +247,35 @@ def test_newton_step_hydrogen_helium():
 def test_newton_step_theta_051():
     w = synth.CFG_SMALL.replace(theta=0.51, dt=1e10)
     newton_parity(w, synth.initial_state(w), steps=2)
+
+
+@pytest.mark.parametrize("ns,seed", [(1, 31), (3, 32)])
+def test_time_level_and_residual_reflecting(ns, seed):
+    """Reflecting walls: the wall faces carry no flux (face coefficients 0)."""
+    w, c = random_case(ns, 16, 1.0, 1.0, seed, boundary=1)
+    m, g = pair(w, c)
+    tl = ores.time_level(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], c["dt"], c["cosmo"], m)
+    f_o = ores.residual(c["U"], tl, c["nH"], c["eh"], c["dt"], c["cosmo"][2], c["cosmo"][3], m)
+    gn = g.rt_time_level(dev(c["Un"]), c["dt"], c["cosmo"])
+    f, rms = g.rt_eval_residual(dev(c["U"]), gn, c["dt"], c["cosmo"])
+    f = host(f)
+    for v in range(m.nv):
+        s = scale_of(f_o[v], c["U"][v] / m.scales[v], tl["g"][v] / m.scales[v])
+        assert rel(f[v], f_o[v], s) <= 1e-12, v
+
+
+def test_newton_steps_reflecting_corner():
+    """The paper's Sec. 4.5 geometry: source in the corner cell, reflecting walls."""
+    w = synth.CFG_256.replace(n=32, mg_levels=3, boundary=1, corner_source=True)
+    newton_parity(w, synth.initial_state(w), steps=3)
+
+
+def test_newton_steps_reflecting_lognormal_boxes():
+    """Reflecting walls with the lognormal medium, 16 sources and overlapping
+    8^3 correction boxes that reach across the walls.  The first step's last
+    Newton iteration starts at ||f|| = 4e-5: with the library's own iterate
+    its CG solve needs 2 iterations, with the oracle's 3 (measured with both
+    iterates through the same calls), so that count may differ by one."""
+    w = synth.CFG_COSMO.replace(n=32, mg_levels=3, boundary=1, box_size=8, box_levels=2,
+                                box_inner=3)
+    newton_parity(w, synth.initial_state(w), steps=2, last_cg_slack=1)
