@@ -216,7 +216,7 @@ def lognormal_density(n: int, sigma_ln: float, mean: float,
     k = 2.0 * np.pi * np.sqrt(k2) / n
     with np.errstate(divide="ignore"):
         filt = np.where(k2 > 0, 1.0 / np.where(k2 > 0, k, 1.0), 0.0)
-    g = np.fft.irfftn(W * filt, s=(n, n, n))
+    g = np.fft.irfftn(W * filt, s=(n, n, n), axes=(0, 1, 2))
     g = (g - g.mean()) / g.std() * sigma_ln
     rho = np.exp(g)
     return mean * rho / rho.mean()
