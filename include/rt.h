@@ -99,7 +99,11 @@ typedef struct rt_params {
   double  kappaP_lte;       /* LTE Planck-mean coefficient (proper, 1/cm)       */
   double  mu_lte;           /* LTE mean particle mass (units of m_H)            */
   int32_t boundary;         /* 0: periodic; 1: reflecting walls on all six      */
-                            /* domain faces (zero diffusive flux through them)  */
+                            /* domain faces (zero diffusive flux through them); */
+                            /* 2: the x-left face holds E at E_dirichlet (a     */
+                            /* ghost cell one width outside), the other faces   */
+                            /* reflect                                          */
+  double  E_dirichlet;      /* boundary 2: comoving E of the x-left ghost cell  */
 } rt_params;
 
 /* Scale factor a and adot/a at t^n (old) and t^{n+1} (new). */

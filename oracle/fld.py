@@ -34,22 +34,41 @@ def face_coefficients(E, kappa, a, model):
         kf = np.maximum(0.5 * (kappa + kq), KAPPA_FLOOR_CELLS / (a * model.dx))
         R = np.abs(Eq - E) / (a * model.dx * np.maximum(Ef, E_FLOOR))
         out.append(limiter(kf, R))
-    if model.boundary == 1:
-        # reflecting walls: the face after the last cell of each row joins
-        # the domain's two ends and carries no flux
+    if model.boundary in (1, 2):
+        # non-periodic: the face after the last cell of each row joins the
+        # domain's two ends and carries no flux; with the x-left Dirichlet
+        # face (boundary 2) that x slot holds the face between the ghost cell
+        # (E_dirichlet, the first cell's opacity) and the first cell
         for d in range(3):
             idx = [slice(None)] * 3
             idx[d] = -1
             out[d] = out[d].copy()
             out[d][tuple(idx)] = 0.0
+        if model.boundary == 2:
+            E0, k0 = E[0], kappa[0]
+            if model.limiter_mode == 1:
+                out[0][-1] = model.D0
+            else:
+                Ef = 0.5 * (model.E_dirichlet + E0)
+                kf = np.maximum(k0, KAPPA_FLOOR_CELLS / (a * model.dx))
+                R = np.abs(E0 - model.E_dirichlet) / (a * model.dx * np.maximum(Ef, E_FLOOR))
+                out[0][-1] = limiter(kf, R)
     return out
 
 
-def diffusion_operator(E, Dfaces, a, dx):
-    """D_E = -div(D grad E) in comoving form with the face coefficients Dfaces."""
+def diffusion_operator(E, Dfaces, a, dx, E_dirichlet=None):
+    """D_E = -div(D grad E) in comoving form with the face coefficients Dfaces.
+    E_dirichlet (x-left Dirichlet face): the x slot after the last cell then
+    holds the ghost face of the first cell, whose neighbour value is fixed."""
     acc = np.zeros_like(E)
     for d in range(3):
-        flux_plus = Dfaces[d] * (np.roll(E, -1, axis=d) - E)   # on the + face
+        Dd = Dfaces[d]
+        if d == 0 and E_dirichlet is not None:
+            Dd = Dd.copy()
+            Db = Dd[-1].copy()
+            Dd[-1] = 0.0
+            acc[0] += Db * (E_dirichlet - E[0])
+        flux_plus = Dd * (np.roll(E, -1, axis=d) - E)          # on the + face
         flux_minus = np.roll(flux_plus, 1, axis=d)             # the - face
         acc += flux_plus - flux_minus
     return -acc / (a * a * dx * dx)

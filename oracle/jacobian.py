@@ -72,7 +72,16 @@ def schur_form(U, f, Dfaces, nH, eh, dt, a, H, model):
     ftM = np.moveaxis(sol[:, :, 0], 0, 1).reshape((nb,) + shape)
     W = np.moveaxis(sol[:, :, 1], 0, 1).reshape((nb,) + shape)
     c = face_couplings(Dfaces, dt, a, model)
+    cb = None
+    if model.boundary == 2:
+        # the x-left Dirichlet face couples the first cell to a fixed value:
+        # it enters that cell's diagonal and no coupling
+        c[0] = c[0].copy()
+        cb = c[0][-1].copy()
+        c[0][-1] = 0.0
     csum = sum(cd + np.roll(cd, 1, axis=d) for d, cd in enumerate(c))
+    if cb is not None:
+        csum[0] = csum[0] + cb
     diag = dloc + csum - np.sum(Lrow * W, axis=0)
     b = np.sum(Lrow * ftM, axis=0) - f[-1]
     return dict(ftM=ftM, W=W, diag=diag, cx=c[0], cy=c[1], cz=c[2], b=b)

@@ -67,7 +67,9 @@ class Model:
     kappa_lte: float = 0.0
     kappaP_lte: float = 0.0
     mu_lte: float = 0.6
-    boundary: int = 0        # 0 periodic; 1 reflecting walls (zero flux on the domain faces)
+    boundary: int = 0        # 0 periodic; 1 reflecting walls (zero flux on the domain faces);
+                             # 2 x-left face at E_dirichlet (ghost cell), other faces reflect
+    E_dirichlet: float = 0.0
     newton_tol: float = 1e-6
     newton_maxit: int = 20
     pcg_rtol: float = 1e-8
@@ -155,5 +157,6 @@ def model_from_workload(w, **overrides) -> Model:
               mg_fp32=w.mg_fp32, pcg_forcing=w.pcg_forcing, box_size=w.box_size,
               box_levels=w.box_levels, box_inner=w.box_inner,
               box_coarse_sweeps=w.box_coarse_sweeps, lte=w.lte, kappa_lte=w.kappa_lte,
-              kappaP_lte=w.kappaP_lte, mu_lte=w.mu_lte, boundary=w.boundary)
+              kappaP_lte=w.kappaP_lte, mu_lte=w.mu_lte, boundary=w.boundary,
+              E_dirichlet=w.E_dirichlet)
     return dataclasses.replace(m, **overrides) if overrides else m

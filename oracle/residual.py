@@ -30,7 +30,8 @@ from .physics import local_operators, opacity
 def tendency(U, nH, eh, a, H, Dfaces, model):
     """[L_e; L_n; D_E + L_E_local](U) with diffusion coefficients Dfaces."""
     L = local_operators(U, nH, eh, a, H, model)
-    L[-1] = L[-1] + fld.diffusion_operator(U[-1], Dfaces, a, model.dx)
+    L[-1] = L[-1] + fld.diffusion_operator(
+        U[-1], Dfaces, a, model.dx, model.E_dirichlet if model.boundary == 2 else None)
     return L
 
 

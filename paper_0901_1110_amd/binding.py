@@ -40,6 +40,7 @@ class RtParams(ctypes.Structure):
         ("box_coarse_sweeps", ctypes.c_int32),
         ("lte", ctypes.c_int32), ("kappa_lte", ctypes.c_double), ("kappaP_lte", ctypes.c_double),
         ("mu_lte", ctypes.c_double), ("boundary", ctypes.c_int32),
+        ("E_dirichlet", ctypes.c_double),
     ]
 
 
@@ -199,7 +200,7 @@ def params_from_workload(w, **overrides) -> RtParams:
     p.box_size, p.box_levels, p.box_inner = w.box_size, w.box_levels, w.box_inner
     p.box_coarse_sweeps = w.box_coarse_sweeps
     p.lte, p.kappa_lte, p.kappaP_lte, p.mu_lte = w.lte, w.kappa_lte, w.kappaP_lte, w.mu_lte
-    p.boundary = w.boundary
+    p.boundary, p.E_dirichlet = w.boundary, w.E_dirichlet
     for k, v in overrides.items():
         if k in ("K_gamma", "K_kappa", "K_heat"):
             getattr(p, k)[:] = list(v)

@@ -166,7 +166,9 @@ int validate(const rt_params* p, std::string* why) {
   auto bad = [&](const char* m) { *why = m; return RT_EINVAL; };
   if (!p) return bad("null params");
   if (p->lte != 0 && p->lte != 1) return bad("lte must be 0 or 1");
-  if (p->boundary != 0 && p->boundary != 1) return bad("boundary must be 0 or 1");
+  if (p->boundary < 0 || p->boundary > 2) return bad("boundary must be 0, 1 or 2");
+  if (p->boundary == 2 && (!(p->E_dirichlet >= 0.0) || !std::isfinite(p->E_dirichlet)))
+    return bad("E_dirichlet must be finite and >= 0");
   if (p->lte ? p->nspecies != 0 : (p->nspecies != 1 && p->nspecies != 3))
     return bad("nspecies must be 1 or 3 (0 exactly with lte)");
   if (p->lte && (!(p->kappa_lte >= 0.0) || !(p->kappaP_lte >= 0.0) || !(p->mu_lte > 0.0) ||
@@ -731,6 +733,7 @@ int rt_create_grid(const rt_params* p, void* d_ws, uint64_t ws_bytes, void* hip_
   P.ns = p->nspecies; P.nv = p->nspecies + 2; P.nb = p->nspecies + 1;
   P.kap_lte = p->kappa_lte; P.kapP_lte = p->kappaP_lte; P.mu_lte = p->mu_lte;
   P.bc = p->boundary;
+  P.Eb = p->E_dirichlet;
   P.N = p->nx * p->ny * p->nz;
   P.iso = p->isothermal; P.lim_mode = p->limiter_mode;
   P.dx = p->dx; P.theta = p->theta; P.u_e = p->u_e; P.u_E = p->u_E;

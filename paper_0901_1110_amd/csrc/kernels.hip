@@ -110,18 +110,30 @@ __global__ __launch_bounds__(BLOCK) void k_faces(DevParams P, const double* __re
 #pragma unroll
     for (int s = 0; s < NS; ++s) xq[s] = Un[(1 + s) * N + q];
     const double kQ = opacity<NS>(xq, nH[q], a, P);
-    // reflecting walls: no face joins the last cell of a row to the first
-    const bool wall = P.bc == 1 && (d == 0 ? c.i == P.nx - 1 : (d == 1 ? c.j == P.ny - 1
-                                                                       : c.k == P.nz - 1));
-    D[d * N + idx] = wall ? 0.0 : face_D(EP, E[q], kP, kQ, a, P);
+    // non-periodic: no face joins the last cell of a row to the first; with
+    // the x-left Dirichlet face that x slot holds the face between the ghost
+    // cell (E_dirichlet, the first cell's opacity) and the first cell
+    const bool wrap = d == 0 ? c.i == P.nx - 1 : (d == 1 ? c.j == P.ny - 1 : c.k == P.nz - 1);
+    if (P.bc != 0 && wrap)
+      D[d * N + idx] = (P.bc == 2 && d == 0) ? face_D(P.Eb, E[q], kQ, kQ, a, P) : 0.0;
+    else
+      D[d * N + idx] = face_D(EP, E[q], kP, kQ, a, P);
   }
 }
 
-// sum over the faces of D_f (E_nbr - E_P) with the +/- ordering of the text
+// sum over the faces of D_f (E_nbr - E_P) with the +/- ordering of the text;
+// with the x-left Dirichlet face (bc 2) the first cell's x neighbour is the
+// ghost value and the last cell has no +x face
 __device__ inline double diffusion_sum(const double* __restrict__ E, const double* __restrict__ D,
-                                       int N, int idx, const Nb& nb, double EP) {
+                                       int N, int idx, const Nb& nb, double EP, int i,
+                                       const DevParams& P) {
   double acc = 0.0;
-  acc += D[idx] * (E[nb.xp] - EP) - D[nb.xm] * (EP - E[nb.xm]);
+  double Dxp = D[idx], Exm = E[nb.xm];
+  if (P.bc == 2) {
+    if (i == P.nx - 1) Dxp = 0.0;
+    if (i == 0) Exm = P.Eb;
+  }
+  acc += Dxp * (E[nb.xp] - EP) - D[nb.xm] * (EP - Exm);
   acc += D[N + idx] * (E[nb.yp] - EP) - D[N + nb.ym] * (EP - E[nb.ym]);
   acc += D[2 * N + idx] * (E[nb.zp] - EP) - D[2 * N + nb.zm] * (EP - E[nb.zm]);
   return acc;
@@ -144,7 +156,7 @@ __global__ __launch_bounds__(BLOCK) void k_explicit(DevParams P, const double* _
   for (int v = 0; v < NV; ++v) u[v] = Un[v * N + idx];
   local_ops<NS, double>(u, nH[idx], eh[idx], s.a, s.H, P, L);
   const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
-  const double dif = diffusion_sum(Un + (NS + 1) * N, D, N, idx, nb, u[NS + 1]);
+  const double dif = diffusion_sum(Un + (NS + 1) * N, D, N, idx, nb, u[NS + 1], c.i, P);
   L[NS + 1] += -dif / (s.a * s.a * P.dx * P.dx);
   const double w = s.dt * (P.theta - 1.0);
 #pragma unroll
@@ -184,7 +196,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual(DevParams P, const double* _
     const double ehv = eh[idx];
     local_ops<NS, double>(u, nH[idx], ehv, s.a, s.H, P, L);
     const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
-    const double dif = diffusion_sum(U + (NS + 1) * N, D, N, idx, nb, u[NS + 1]);
+    const double dif = diffusion_sum(U + (NS + 1) * N, D, N, idx, nb, u[NS + 1], c.i, P);
     L[NS + 1] += -dif * inv_a2dx2;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -463,7 +475,9 @@ __global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __re
   gepp2<NB>(M, B);
   const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
   const double cf = s.dt * P.theta / (s.a * s.a * P.dx * P.dx);
-  const double cxp = cf * D[idx], cxm = cf * D[nb.xm];
+  // with the x-left Dirichlet face the last cell has no +x coupling, and the
+  // first cell's -x face (to the fixed ghost value) enters its diagonal only
+  const double cxp = (P.bc == 2 && c.i == P.nx - 1) ? 0.0 : cf * D[idx], cxm = cf * D[nb.xm];
   const double cyp = cf * D[N + idx], cym = cf * D[N + nb.ym];
   const double czp = cf * D[2 * N + idx], czm = cf * D[2 * N + nb.zm];
   const double csum = ((cxp + cxm) + (cyp + cym)) + (czp + czm);

@@ -48,7 +48,8 @@ struct DevParams {
   double hnu;
   double alpha0[3];   // HII, HeII, HeIII at 1e4 K
   double kap_lte, kapP_lte, mu_lte;   // LTE coupling (ns = 0)
-  int bc;                             // 0 periodic, 1 reflecting walls
+  int bc;                             // 0 periodic, 1 reflecting walls, 2 x-left Dirichlet
+  double Eb;                          // bc 2: E of the x-left ghost cell
 };
 
 // ---- forward-mode dual numbers ------------------------------------------

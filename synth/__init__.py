@@ -90,7 +90,8 @@ class Workload:
     kappa_lte: float = 0.0      # LTE absorption coefficient (proper, 1/cm)
     kappaP_lte: float = 0.0     # LTE Planck-mean coefficient (proper, 1/cm)
     mu_lte: float = 0.6         # LTE mean particle mass (units of m_H)
-    boundary: int = 0           # 0: periodic; 1: reflecting walls
+    boundary: int = 0           # 0: periodic; 1: reflecting walls; 2: x-left Dirichlet
+    E_dirichlet: float = 0.0    # boundary 2: comoving E of the x-left ghost cell
     corner_source: bool = False  # single source in cell (0, 0, 0) instead of the centre
     mg_levels: int = 3
     mg_pre: int = 2
@@ -193,8 +194,19 @@ CFG_TS_HOT = Workload(
     eh0=1.0e10 / _RHO_TS, u_e=1.0e15, dt=1.0e-9, steps=250, mg_levels=1, newton_tol=1e-10)
 CFG_TS_COLD = CFG_TS_HOT.replace(name="ts_cold", eh0=1.0e2 / _RHO_TS)
 
+# Free-streaming radiation of Sec. 4.1: a transparent medium (constant
+# opacities 1e-6 /cm; the LTE terms are then negligible), E = 1e-4 erg/cm^3,
+# E = 1 erg/cm^3 held on the x-left face, the other faces reflecting, a 1 cm
+# cube, to t = 8.3391 ps (a quarter of the light-crossing time) in 100 steps.
+# The gas (1e-7 g/cm^3, mu = 0.6, ~1e4 K) only sets the LTE terms.
+CFG_FS = Workload(
+    name="free_stream_128", n=128, dx=1.0 / 128, nspecies=0, x0=(), lte=1, kappa_lte=1.0e-6,
+    kappaP_lte=1.0e-6, mu_lte=0.6, nH_mean=_RHO_TS / _M_H_G, Q=0.0, E0=1.0e-4, u_E=1.0,
+    eh0=2.07e12, u_e=2.07e12, dt=8.3391e-14, steps=100, mg_levels=5, boundary=2,
+    E_dirichlet=1.0)
+
 WORKLOADS = {w.name: w for w in (CFG_SMALL, CFG_COSMO, CFG_256, CFG_HHE, CFG_SG, CFG_TS_HOT,
-                                 CFG_TS_COLD)}
+                                 CFG_TS_COLD, CFG_FS)}
 
 
 # --- generators ---------------------------------------------------------------
