@@ -65,7 +65,7 @@ BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0
 # kernel source it was measured on and is reported as null for any other.
 PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "dots": True,
                              "bytes_per_launch": 4.27e8,
-                             "kernels_sha256": "b48cdd846ce7fb44980d0d155a41c4e6e63352bfa99e503b4fe0919ce1b58108"}}
+                             "kernels_sha256": "82ac13bb2d3a6b0a54cc54999d0c8835a89f73b57cae27dc7a447ea9cb8b9cb9"}}
 
 
 def kernels_sha256():
