@@ -56,12 +56,28 @@ def test_workspace_bytes_and_validation():
     # >= the FP64 fields the step needs (about 30 per cell)
     assert 30 * 8 * N < n.value < 40 * 8 * N
     for field, bad in (("nspecies", 2), ("nx", 250), ("theta", 0.0), ("mg_levels", 8),
-                       ("u_E", -1.0), ("newton_maxit", 99), ("limiter_mode", 5)):
+                       ("u_E", -1.0), ("newton_maxit", 99), ("limiter_mode", 5),
+                       ("nspecies", 0), ("lte", 1), ("lte", 2), ("boundary", 3),
+                       ("boundary", -1), ("pcg_forcing", -1e-6), ("box_size", 20),
+                       ("box_size", 512)):
         q = b.params_from_workload(synth.CFG_256, **{field: bad})
         assert lib.rt_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == b.RT_EINVAL, field
         h = ctypes.c_void_p()
         assert lib.rt_create_grid(ctypes.byref(q), ctypes.c_void_p(256), 1 << 40, None,
                                   ctypes.byref(h)) == b.RT_EINVAL
+    # combinations: LTE needs nspecies = 0 and finite coefficients; a held
+    # face needs a finite, non-negative value
+    for over in (dict(lte=1, nspecies=0, mu_lte=0.0), dict(lte=1, nspecies=0, kappa_lte=-1.0),
+                 dict(lte=1, nspecies=0, kappaP_lte=float("nan")),
+                 dict(boundary=2, E_dirichlet=-1.0), dict(boundary=2, E_dirichlet=float("inf")),
+                 dict(box_size=32, box_levels=2, box_coarse_sweeps=-1),
+                 dict(box_size=32, box_levels=2, box_inner=0)):
+        q = b.params_from_workload(synth.CFG_256, **over)
+        assert lib.rt_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == b.RT_EINVAL, over
+    for over in (dict(lte=1, nspecies=0, kappa_lte=1e-6, kappaP_lte=1e-6, mu_lte=0.6),
+                 dict(boundary=1), dict(boundary=2, E_dirichlet=1.0)):
+        q = b.params_from_workload(synth.CFG_256, **over)
+        assert lib.rt_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == b.RT_OK, over
     # a workspace that is too short is rejected before any device work
     h = ctypes.c_void_p()
     assert lib.rt_create_grid(ctypes.byref(p), ctypes.c_void_p(256), 1024, None,

@@ -95,6 +95,12 @@ def test_invalid_calls():
         g.rt_eval_residual(U, U, w.dt, w.cosmology(0))        # no time level yet
     with pytest.raises(RtError):
         g.rt_mg_vcycle(nH)                                    # no Schur matrix yet
+    with pytest.raises(RtError) as e:
+        g.rt_predict(U, w.dt, w.cosmology(0), Up=U)           # output aliases the input
+    assert e.value.status == RT_EINVAL
+    with pytest.raises(RtError) as e:
+        g.rt_time_error(U, U.clone(), float("nan"))           # p must be finite
+    assert e.value.status == RT_EINVAL
 
 
 def test_no_sources_uniform():
