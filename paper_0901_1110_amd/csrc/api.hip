@@ -84,6 +84,7 @@ struct rt_grid {
   double* hpin = nullptr;   // pinned host scalars for asynchronous read-back
   int nbox = 0;             // active source subdomains (0: V-cycle alone)
   int tk_override = -1;     // >= 0: time every launch under this class
+  double cg_rate1 = 0.0;    // residual reduction of the last solve's first CG step (0: none yet)
   hipEvent_t ev_rd = nullptr;
   // the source-subdomain correction as a captured graph (a few hundred small
   // launches replayed by one), valid for the (r, z, nbox) it was captured for
@@ -626,11 +627,14 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   finish_reduce(g, nparts, 1, S_RHO);
   HIPCHK(g, hipMemcpyAsync(w.p, w.z, N * sizeof(double), hipMemcpyDeviceToDevice, g->st));
   // The tail of an iteration (V-cycle, dots, new direction) writes only z, p
-  // and CG scalars, so while the last residual is still far above the
-  // tolerance it is enqueued before this iteration's residual norm has come
-  // back to the host: the device never idles on the read-back.  If that norm
-  // turns out converged, the enqueued tail is discarded work and x is final.
-  constexpr double LOOKAHEAD = 30.0;
+  // and CG scalars, so it can be enqueued before this iteration's residual
+  // norm has come back to the host: the device then never idles on the
+  // read-back.  If that norm turns out converged, the enqueued tail (a whole
+  // preconditioner application) is discarded work, while waiting for the norm
+  // costs only the read-back latency.  So the tail runs ahead only when the
+  // norm predicted from the last reduction factor (for the first step: the
+  // first step of the previous solve) stays well above the tolerance.
+  constexpr double LOOKAHEAD = 4.0;
   auto tail = [&]() -> int {
     RTCHK(apply_precond(g, w.r, w.z, true, &nd));
     ++*vcycles;
@@ -639,9 +643,10 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
     TK(g, RT_K_CG_VECTOR, launch_update_p(N, w.p, w.z, w.sc, g->st));
     return RT_OK;
   };
-  double rn = bn;
+  double rn = bn, rn_prev = 0.0;
   int k = 0;
   for (k = 1; k <= maxit; ++k) {
+    const double pred = k > 1 ? rn * (rn / rn_prev) : (g->cg_rate1 > 0.0 ? bn * g->cg_rate1 : HUGE_VAL);
     TK(g, RT_K_SPMV, launch_spmv_dot(g->P.nx, g->P.ny, g->P.nz, w.diag, w.cx, w.cy, w.cz, w.p, w.q, w.parts, g->st));
     TK(g, RT_K_REDUCE, launch_final_reduce_alpha(w.parts, stencil_blocks(g->P.nx, g->P.ny, g->P.nz),
                                                  w.sc, g->st));
@@ -649,11 +654,13 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
     finish_reduce(g, nparts, 1, S_RR);
     HIPCHK(g, hipMemcpyAsync(g->hpin, w.sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, g->st));
     HIPCHK(g, hipEventRecord(g->ev_rd, g->st));
-    const bool ahead = k < maxit && rn > LOOKAHEAD * thr;
+    const bool ahead = k < maxit && pred > LOOKAHEAD * thr;
     if (ahead) RTCHK(tail());
     HIPCHK(g, hipEventSynchronize(g->ev_rd));
+    rn_prev = rn;
     rn = std::sqrt(g->hpin[0]);
     if (!std::isfinite(rn)) return fail(g, RT_ENONFINITE, "non-finite CG residual");
+    if (k == 1) g->cg_rate1 = rn / bn;
     if (rn <= thr) break;
     if (k == maxit) break;
     if (!ahead) RTCHK(tail());
