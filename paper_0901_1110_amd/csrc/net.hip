@@ -65,6 +65,10 @@ __device__ inline int off_cell(const Geo& g, int i, int j, int k, int o) {
 // once per plane rather than once per kernel offset, and every lane keeps
 // its 27 weight fragments (MFMA A operands) in registers.  A wave computes
 // 16 (co) x 16 (cells along z) tiles with 27 MFMAs in offset order.
+// In LDS the four 8-byte channel quads of the cell at slot position p are
+// stored in the order q ^ ((p >> 2) & 3): with 32 B per cell the 16 lanes of
+// one quad would otherwise fall on four bank pairs, and any 16 (or 32)
+// consecutive cells of a row now read conflict-free.
 // mode 0: forward, out = act(bias + W * in); act = LeakyReLU if leaky.
 // mode 1: data gradient, out = (sum_o Wt_o g[cell + off_o]) * leaky'(hprev),
 //         Wt_o = W_{26-o}^T (both modes read the source at +off_o).
@@ -104,7 +108,11 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restr
       const int r = cr / RK, c = cr - r * RK;
       const int j = wrapi(j0 - 1 + r, g.ny), k = wrapi(k0 - 1 + c, g.nz);
       const size_t src = ((size_t)(ip * g.ny + j) * g.nz + k) * CH + 8 * h;
-      *reinterpret_cast<uint4*>(s + cr * 32 + 16 * h) = *reinterpret_cast<const uint4*>(in + src);
+      // quads 2h, 2h + 1 land in the 16-byte half h ^ (sw >> 1), swapped if sw is odd
+      const int sw = (cr >> 2) & 3;
+      uint4 v = *reinterpret_cast<const uint4*>(in + src);
+      if (sw & 1) v = make_uint4(v.z, v.w, v.x, v.y);
+      *reinterpret_cast<uint4*>(s + cr * 32 + 16 * (h ^ (sw >> 1))) = v;
     }
   };
   const int cpr = T.TK >> 4;                        // 16-cell chunks per tile row
@@ -122,8 +130,8 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restr
       for (int o = 0; o < NOFF; ++o) {
         const int di = o / 9 - 1, dj = (o / 3) % 3 - 1, dk = o % 3 - 1;
         const char* s = slot(i + di);
-        const v4s b = *reinterpret_cast<const v4s*>(
-            s + ((jj + 1 + dj) * RK + (kc + col + 1 + dk)) * 32 + 8 * q);
+        const int p = (jj + 1 + dj) * RK + (kc + col + 1 + dk);
+        const v4s b = *reinterpret_cast<const v4s*>(s + p * 32 + 8 * (q ^ ((p >> 2) & 3)));
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[o], b, acc, 0, 0, 0);
       }
       const int cell = (i * g.ny + j0 + jj) * g.nz + k0 + kc + col;
