@@ -65,10 +65,12 @@ __device__ inline int off_cell(const Geo& g, int i, int j, int k, int o) {
 // once per plane rather than once per kernel offset, and every lane keeps
 // its 27 weight fragments (MFMA A operands) in registers.  A wave computes
 // 16 (co) x 16 (cells along z) tiles with 27 MFMAs in offset order.
-// In LDS the four 8-byte channel quads of the cell at slot position p are
-// stored in the order q ^ ((p >> 2) & 3): with 32 B per cell the 16 lanes of
-// one quad would otherwise fall on four bank pairs, and any 16 (or 32)
-// consecutive cells of a row now read conflict-free.
+// In LDS the four 8-byte channel quads of a cell at position x of its row
+// are stored in the order q ^ ((x >> 2) & 3): with 32 B per cell the 16
+// lanes that read one quad of 16 consecutive cells would otherwise fall on
+// four bank pairs.  The key depends on x only, so a lane's three z shifts
+// have fixed quad offsets and, with the row length a compile-time constant,
+// all 27 operand reads of a tile are immediate offsets from nine bases.
 // mode 0: forward, out = act(bias + W * in); act = LeakyReLU if leaky.
 // mode 1: data gradient, out = (sum_o Wt_o g[cell + off_o]) * leaky'(hprev),
 //         Wt_o = W_{26-o}^T (both modes read the source at +off_o).
@@ -76,6 +78,7 @@ __device__ inline int off_cell(const Geo& g, int i, int j, int k, int o) {
 struct Tile {
   int TJ, TK, PI, ntj, ntk;
 };
+template <int TK>
 __global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restrict__ in,
                                               const bf16* __restrict__ W,     // [27][16][16]
                                               const float* __restrict__ bias, int mode,
@@ -83,7 +86,9 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restr
                                               bf16* __restrict__ out, float* __restrict__ out32,
                                               int nout) {
   extern __shared__ __align__(16) char lds[];
-  const int RJ = T.TJ + 2, RK = T.TK + 2;
+  constexpr int RK = TK + 2;                        // cells per LDS row (tile + halo)
+  constexpr int CPR = TK / 16;                      // 16-cell chunks per tile row
+  const int RJ = T.TJ + 2;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int q = lane >> 4;                          // channel quad
@@ -93,11 +98,16 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restr
   blk /= T.ntk;
   const int tj = blk % T.ntj;
   const int i0 = (blk / T.ntj) * T.PI;
-  const int j0 = tj * T.TJ, k0 = tk * T.TK;
+  const int j0 = tj * T.TJ, k0 = tk * TK;
   v4s a[NOFF];
 #pragma unroll
   for (int o = 0; o < NOFF; ++o)
     a[o] = *reinterpret_cast<const v4s*>(W + (o * CH + col) * CH + 4 * q);
+  float bq[4] = {0.f, 0.f, 0.f, 0.f};
+  if (mode == 0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) bq[t] = bias[4 * q + t];
+  }
   const int slot_bytes = RJ * RK * 32;
   auto slot = [&](int p) { return lds + ((p % 3 + 3) % 3) * slot_bytes; };
   auto load_plane = [&](int p) {
@@ -109,29 +119,34 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restr
       const int j = wrapi(j0 - 1 + r, g.ny), k = wrapi(k0 - 1 + c, g.nz);
       const size_t src = ((size_t)(ip * g.ny + j) * g.nz + k) * CH + 8 * h;
       // quads 2h, 2h + 1 land in the 16-byte half h ^ (sw >> 1), swapped if sw is odd
-      const int sw = (cr >> 2) & 3;
+      const int sw = (c >> 2) & 3;
       uint4 v = *reinterpret_cast<const uint4*>(in + src);
       if (sw & 1) v = make_uint4(v.z, v.w, v.x, v.y);
       *reinterpret_cast<uint4*>(s + cr * 32 + 16 * (h ^ (sw >> 1))) = v;
     }
   };
-  const int cpr = T.TK >> 4;                        // 16-cell chunks per tile row
-  const int nch = T.TJ * cpr;
+  // byte offset of this lane's quad in the cells at x = kc + col + e (kc is
+  // a multiple of 16, so the key is that of col + e)
+  int qo[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) qo[e] = 8 * (q ^ (((col + e) >> 2) & 3));
+  const int nch = T.TJ * CPR;
   load_plane(i0 - 1);
   load_plane(i0);
   for (int i = i0; i < i0 + T.PI; ++i) {
     load_plane(i + 1);   // the slot of plane i - 2, read last by plane i - 1
     __syncthreads();
+    const char* sp[3] = {slot(i - 1), slot(i), slot(i + 1)};
     for (int ch = wv; ch < nch; ch += 4) {
-      const int jj = ch / cpr;
-      const int kc = (ch - jj * cpr) << 4;
+      const int jj = ch / CPR;
+      const int kc = (ch - jj * CPR) << 4;
+      const int rc = (jj * RK + kc + col) * 32;
       v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int o = 0; o < NOFF; ++o) {
-        const int di = o / 9 - 1, dj = (o / 3) % 3 - 1, dk = o % 3 - 1;
-        const char* s = slot(i + di);
-        const int p = (jj + 1 + dj) * RK + (kc + col + 1 + dk);
-        const v4s b = *reinterpret_cast<const v4s*>(s + p * 32 + 8 * (q ^ ((p >> 2) & 3)));
+        const int di = o / 9, dj = (o / 3) % 3, dk = o % 3;   // shifts + 1
+        const char* bp = sp[di] + rc + qo[dk];
+        const v4s b = *reinterpret_cast<const v4s*>(bp + (dj * RK + dk) * 32);
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[o], b, acc, 0, 0, 0);
       }
       const int cell = (i * g.ny + j0 + jj) * g.nz + k0 + kc + col;
@@ -139,7 +154,7 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restr
       if (mode == 0) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          v[t] += bias[4 * q + t];
+          v[t] += bq[t];
           if (leaky) v[t] = v[t] > 0.f ? v[t] : LEAK * v[t];
         }
       } else if (hprev) {
@@ -552,7 +567,8 @@ void launch_conv(rt_net* n, const bf16* in, int layer, int mode, int leaky, cons
   const Tile t = conv_tile(n->g);
   const unsigned blocks = (unsigned)((long)t.ntj * t.ntk * (n->g.nx / t.PI));
   const size_t lds = (size_t)3 * (t.TJ + 2) * (t.TK + 2) * 32;
-  hipLaunchKernelGGL(k_conv, dim3(blocks), dim3(256), lds, n->st, n->g, t, in, W,
+  auto kern = t.TK == 64 ? k_conv<64> : (t.TK == 32 ? k_conv<32> : k_conv<16>);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, n->st, n->g, t, in, W,
                      n->bias + 16 * layer, mode, leaky, hprev, out, out32, n->nout);
 }
 
