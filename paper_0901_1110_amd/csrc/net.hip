@@ -110,19 +110,43 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restr
   }
   const int slot_bytes = RJ * RK * 32;
   auto slot = [&](int p) { return lds + ((p % 3 + 3) % 3) * slot_bytes; };
-  auto load_plane = [&](int p) {
-    const int ip = wrapi(p, g.nx);
-    char* s = slot(p);
-    for (int t = threadIdx.x; t < RJ * RK * 2; t += 256) {
+  // this thread's share of a plane load (16-byte halves t = tid + 256 u of
+  // the (RJ, RK) tile with halo), the same in every plane but for the plane
+  // offset: source offset within the plane, and LDS offset with bit 0 set
+  // where the two quads are swapped (quads 2h, 2h + 1 land in the half
+  // h ^ (sw >> 1), swapped if sw is odd; -1: no element)
+  constexpr int NU = (6 * RK * 2 + 255) / 256;      // TJ <= 4
+  int goff[NU], loff[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int t = threadIdx.x + 256 * u;
+    loff[u] = -1;
+    goff[u] = 0;
+    if (t < RJ * RK * 2) {
       const int cr = t >> 1, h = t & 1;
       const int r = cr / RK, c = cr - r * RK;
       const int j = wrapi(j0 - 1 + r, g.ny), k = wrapi(k0 - 1 + c, g.nz);
-      const size_t src = ((size_t)(ip * g.ny + j) * g.nz + k) * CH + 8 * h;
-      // quads 2h, 2h + 1 land in the 16-byte half h ^ (sw >> 1), swapped if sw is odd
       const int sw = (c >> 2) & 3;
-      uint4 v = *reinterpret_cast<const uint4*>(in + src);
-      if (sw & 1) v = make_uint4(v.z, v.w, v.x, v.y);
-      *reinterpret_cast<uint4*>(s + cr * 32 + 16 * (h ^ (sw >> 1))) = v;
+      goff[u] = (j * g.nz + k) * CH + 8 * h;
+      loff[u] = cr * 32 + 16 * (h ^ (sw >> 1)) + (sw & 1);
+    }
+  }
+  const size_t pstride = (size_t)g.ny * g.nz * CH;
+  uint4 pre[NU];
+  auto fetch_plane = [&](int p) {
+    const bf16* src = in + (size_t)wrapi(p, g.nx) * pstride;
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+      if (loff[u] >= 0) pre[u] = *reinterpret_cast<const uint4*>(src + goff[u]);
+  };
+  auto store_plane = [&](int p) {
+    char* s = slot(p);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if (loff[u] < 0) continue;
+      uint4 v = pre[u];
+      if (loff[u] & 1) v = make_uint4(v.z, v.w, v.x, v.y);
+      *reinterpret_cast<uint4*>(s + (loff[u] & ~1)) = v;
     }
   };
   // byte offset of this lane's quad in the cells at x = kc + col + e (kc is
@@ -131,11 +155,18 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, Tile T, const bf16* __restr
 #pragma unroll
   for (int e = 0; e < 3; ++e) qo[e] = 8 * (q ^ (((col + e) >> 2) & 3));
   const int nch = T.TJ * CPR;
-  load_plane(i0 - 1);
-  load_plane(i0);
+  // plane i + 1 is fetched into registers while plane i - 1 ... i are in
+  // use and stored into the slot of plane i - 2 after every wave is done
+  // with that plane
+  fetch_plane(i0 - 1);
+  store_plane(i0 - 1);
+  fetch_plane(i0);
+  store_plane(i0);
+  fetch_plane(i0 + 1);
   for (int i = i0; i < i0 + T.PI; ++i) {
-    load_plane(i + 1);   // the slot of plane i - 2, read last by plane i - 1
+    store_plane(i + 1);
     __syncthreads();
+    if (i + 1 < i0 + T.PI) fetch_plane(i + 2);
     const char* sp[3] = {slot(i - 1), slot(i), slot(i + 1)};
     for (int ch = wv; ch < nch; ch += 4) {
       const int jj = ch / CPR;
