@@ -52,8 +52,8 @@ struct Workspace {
   // source subdomains: boxes of B^3 cells around the sources, stacked along x
   int box_cap = 0;                        // boxes the workspace holds (max_sources)
   double *bd, *bcx, *bcy, *bcz;           // box operator (FP64, level 0 of B64)
-  double *bxv, *br, *bz, *bp, *bq;        // inner PCG vectors (FP32 cycle: float inside)
-  double *bparts, *bsc;
+  double *bxv, *br, *bz, *bp, *bp2, *bq;  // inner PCG vectors (FP32 cycle: float inside)
+  double *bparts, *bparts2, *bsc;
   std::vector<Level<double>> B64;
   std::vector<Level<float>> B32;
   size_t nparts_cap;
@@ -279,8 +279,10 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
     w->bcy = c.take<double>(nb3); w->bcz = c.take<double>(nb3);
     w->bxv = c.take<double>(nb3); w->br = c.take<double>(nb3);
     w->bz = c.take<double>(nb3); w->bp = c.take<double>(nb3); w->bq = c.take<double>(nb3);
+    w->bp2 = c.take<double>(nb3);
     const size_t sb = (size_t)stencil_blocks(w->box_cap * B, B, B);
     w->bparts = c.take<double>((sb > (size_t)MAX_PARTS ? sb : (size_t)MAX_PARTS) * NCOMP_MAX);
+    w->bparts2 = c.take<double>((sb > (size_t)MAX_PARTS ? sb : (size_t)MAX_PARTS) * NCOMP_MAX);
     w->bsc = c.take<double>(32);
     // levels sized for every box; rt_set_sources sets the extent in use
     int bx = w->box_cap * B, by = B, bz = B;
@@ -493,15 +495,22 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
   int np = 0;
   TK(g, RT_K_BOX, np = launch_box_dot1p<T>(n, br, bz, bp, w.bparts, st));
   TK(g, RT_K_BOX, launch_final_reduce(w.bparts, np, 1, w.bsc + S_RHO, st));
+  // the CG scalars are formed by the kernels that use them (each block sums
+  // the partials itself), rho alternates between two slots and p between two
+  // buffers, so an iteration is the product, the update, the V-cycle and the
+  // dots: no reduction launches
+  T* pb[2] = {reinterpret_cast<T*>(w.bp2), bp};
+  int nzp = 0;
   for (int it = 1; it <= g->prm.box_inner; ++it) {
-    TK(g, RT_K_BOX, np = launch_box_spmv<T>(L0, bp, bq, w.bparts, st));
-    TK(g, RT_K_BOX, launch_final_reduce_alpha(w.bparts, np, w.bsc, st));
-    TK(g, RT_K_BOX, launch_box_update_xr<T>(n, x, br, bp, bq, w.bsc, st));
+    const int rho = (it & 1) ? S_RHO : S_RHO2, rho_prev = (it & 1) ? S_RHO2 : S_RHO;
+    T* p = pb[it & 1];
+    const T* p_prev = pb[(it + 1) & 1];
+    TK(g, RT_K_BOX, np = launch_box_spmv_p<T>(L0, bz, p_prev, p, bq, w.bparts, nzp, w.bsc, rho_prev,
+                                              rho, it == 1, w.bparts2, st));
+    TK(g, RT_K_BOX, launch_box_update_xr<T>(n, x, br, p, bq, w.bparts2, np, w.bsc, rho, st));
     if (it == g->prm.box_inner) break;
     vcycle<T>(g, Ls, 0, box_cs(g));
-    TK(g, RT_K_BOX, np = launch_box_dot2<T>(n, bz, br, bq, w.bparts, st));
-    TK(g, RT_K_BOX, launch_final_reduce_beta(w.bparts, np, w.bsc, st));
-    TK(g, RT_K_BOX, launch_box_update_p<T>(n, bp, bz, w.bsc, st));
+    TK(g, RT_K_BOX, nzp = launch_box_dot2<T>(n, bz, br, bq, w.bparts, st));
   }
   // boxes may overlap: one launch per box, in source order
   const int nbb = stencil_blocks(B, B, B);

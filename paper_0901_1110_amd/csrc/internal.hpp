@@ -21,7 +21,7 @@ inline int reduce_blocks(long n) {
 
 // Indices of the device scalar slots used by CG.
 enum Scalar { S_RHO = 0, S_PQ, S_ALPHA, S_RR, S_ZR, S_ZQ, S_BETA, S_BB, S_FN, S_VIOL, S_TSUM, S_TMAX,
-              S_COUNT };
+              S_RHO2, S_COUNT };
 
 struct Step {     // per-call time-step data
   double dt, a, H;
@@ -123,15 +123,18 @@ void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long 
 // operator in T); the reduction launches return their partial count
 template <class T>
 int launch_box_dot1p(long n, const T* r, const T* z, T* p, double* parts, hipStream_t st);
+// beta from the partials of z.r, z.q (rho <- z.r into slot rho_out),
+// pout = z + beta pin (first: z), q = S pout, partials of pout.q
 template <class T>
-int launch_box_spmv(const Level<T>& L, const T* p, T* q, double* parts, hipStream_t st);
+int launch_box_spmv_p(const Level<T>& L, const T* z, const T* pin, T* pout, T* q,
+                      const double* zparts, int nz_parts, double* sc, int rho_in, int rho_out,
+                      bool first, double* parts, hipStream_t st);
+// alpha = sc[rho] / (p.q) from its partials (into sc[S_ALPHA]), x += alpha p, r -= alpha q
 template <class T>
-void launch_box_update_xr(long n, T* x, T* r, const T* p, const T* q, const double* sc,
-                          hipStream_t st);
+void launch_box_update_xr(long n, T* x, T* r, const T* p, const T* q, const double* pqparts,
+                          int npq, double* sc, int rho, hipStream_t st);
 template <class T>
 int launch_box_dot2(long n, const T* z, const T* r, const T* q, double* parts, hipStream_t st);
-template <class T>
-void launch_box_update_p(long n, T* p, const T* z, const double* sc, hipStream_t st);
 // FP64 natural field -> FP32 field in the layout of level L
 void launch_cvt_d2f_level(const Level<float>& L, const double* a, float* b, hipStream_t st);
 void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st);

@@ -1067,35 +1067,77 @@ __global__ __launch_bounds__(BLOCK) void k_box_dot1p(long n, const T* __restrict
   }
   block_reduce<1>(acc, parts);
 }
-// q = S p (stacked boxes) and the partials of p.q
+// sum over np block partials of component c in a fixed order, so that every
+// block of a launch obtains the same value; returned to all threads (every
+// thread of the block must call it)
+__device__ inline double block_sum_parts(const double* __restrict__ parts, int np, int c) {
+  __shared__ double sh[BLOCK / 64];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int nthr = blockDim.x * blockDim.y;
+  double s = 0.0;
+  for (int i = tid; i < np; i += nthr) s += parts[(size_t)i * NCOMP_MAX + c];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((tid & 63) == 0) sh[tid >> 6] = s;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (nthr + 63) >> 6; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+// new direction and product in one pass (stacked boxes): beta = -alpha (z.q)
+// / rho from the previous iteration's partials of z.r and z.q (rho <- z.r
+// into the other slot, by one thread), p' = z + beta p formed at the cell and
+// its six neighbours (p' goes to its own buffer: the old p is still read by
+// other blocks), q = S p', and the partials of p'.q.  first: p' = z.
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_box_spmv(int nx, int ny, int nz, const T* __restrict__ diag,
-                                                     const T* __restrict__ cx, const T* __restrict__ cy,
-                                                     const T* __restrict__ cz, const T* __restrict__ p,
-                                                     T* __restrict__ q, double* __restrict__ parts) {
+__global__ __launch_bounds__(BLOCK) void k_box_spmv_p(int nx, int ny, int nz,
+                                                       const T* __restrict__ diag,
+                                                       const T* __restrict__ cx,
+                                                       const T* __restrict__ cy,
+                                                       const T* __restrict__ cz,
+                                                       const T* __restrict__ z,
+                                                       const T* __restrict__ pin,
+                                                       T* __restrict__ pout, T* __restrict__ q,
+                                                       const double* __restrict__ zparts, int nz_parts,
+                                                       double* sc, int rho_in, int rho_out,
+                                                       int first, double* __restrict__ parts) {
+  double beta = 0.0;
+  if (!first) {
+    const double zr = block_sum_parts(zparts, nz_parts, 0);
+    const double zq = block_sum_parts(zparts, nz_parts, 1);
+    beta = (-sc[S_ALPHA] * zq) / sc[rho_in];
+    if (block_linear() == 0 && threadIdx.x == 0 && threadIdx.y == 0) sc[rho_out] = zr;
+  }
+  auto pn = [&](int i) -> T { return first ? z[i] : (T)(z[i] + beta * pin[i]); };
   double acc[1] = {0.0};
   const C3 c = coord3(ny, nz);
   if (c.ok) {
     const int idx = (c.i * ny + c.j) * nz + c.k;
     const Nb nb = nbrs(c.i, c.j, c.k, nx, ny, nz);
-    const T pv = p[idx];
+    const T pv = pn(idx);
     T y = diag[idx] * pv;
-    y = y - cx[idx] * p[nb.xp] - cx[nb.xm] * p[nb.xm];
-    y = y - cy[idx] * p[nb.yp] - cy[nb.ym] * p[nb.ym];
-    y = y - cz[idx] * p[nb.zp] - cz[nb.zm] * p[nb.zm];
+    y = y - cx[idx] * pn(nb.xp) - cx[nb.xm] * pn(nb.xm);
+    y = y - cy[idx] * pn(nb.yp) - cy[nb.ym] * pn(nb.ym);
+    y = y - cz[idx] * pn(nb.zp) - cz[nb.zm] * pn(nb.zm);
+    pout[idx] = pv;
     q[idx] = y;
     acc[0] = (double)pv * (double)y;
   }
   block_reduce<1>(acc, parts);
 }
+// alpha = rho / (p.q) from the product's partials (stored by one thread),
+// x += alpha p, r -= alpha q
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_box_update_xr(long n, T* __restrict__ x, T* __restrict__ r,
                                                           const T* __restrict__ p,
                                                           const T* __restrict__ q,
-                                                          const double* __restrict__ sc) {
+                                                          const double* __restrict__ pqparts,
+                                                          int npq, double* sc, int rho) {
+  const double alpha = sc[rho] / block_sum_parts(pqparts, npq, 0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[S_ALPHA] = alpha;
   const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
   if (i >= n) return;
-  const double alpha = sc[S_ALPHA];
   x[i] = (T)(x[i] + alpha * p[i]);
   r[i] = (T)(r[i] - alpha * q[i]);
 }
@@ -1112,14 +1154,6 @@ __global__ __launch_bounds__(BLOCK) void k_box_dot2(long n, const T* __restrict_
     acc[1] = zv * (double)q[i];
   }
   block_reduce<2>(acc, parts);
-}
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_box_update_p(long n, T* __restrict__ p,
-                                                         const T* __restrict__ z,
-                                                         const double* __restrict__ sc) {
-  const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
-  if (i >= n) return;
-  p[i] = (T)(z[i] + sc[S_BETA] * p[i]);
 }
 
 // FP64 natural -> FP32 colour-split finest level
@@ -1353,25 +1387,24 @@ int launch_box_dot1p(long n, const T* r, const T* z, T* p, double* parts, hipStr
   return (int)grid_for(n).x;
 }
 template <class T>
-int launch_box_spmv(const Level<T>& L, const T* p, T* q, double* parts, hipStream_t st) {
+int launch_box_spmv_p(const Level<T>& L, const T* z, const T* pin, T* pout, T* q,
+                      const double* zparts, int nz_parts, double* sc, int rho_in, int rho_out,
+                      bool first, double* parts, hipStream_t st) {
   const Geo g = geo3(L.nx, L.ny, L.nz);
-  hipLaunchKernelGGL(k_box_spmv<T>, g.g, g.b, 0, st, L.nx, L.ny, L.nz, L.diag, L.cx, L.cy, L.cz,
-                     p, q, parts);
+  hipLaunchKernelGGL(k_box_spmv_p<T>, g.g, g.b, 0, st, L.nx, L.ny, L.nz, L.diag, L.cx, L.cy, L.cz,
+                     z, pin, pout, q, zparts, nz_parts, sc, rho_in, rho_out, first ? 1 : 0, parts);
   return (int)(g.g.x * g.g.y * g.g.z);
 }
 template <class T>
-void launch_box_update_xr(long n, T* x, T* r, const T* p, const T* q, const double* sc,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_box_update_xr<T>, grid_for(n), dim3(BLOCK), 0, st, n, x, r, p, q, sc);
+void launch_box_update_xr(long n, T* x, T* r, const T* p, const T* q, const double* pqparts,
+                          int npq, double* sc, int rho, hipStream_t st) {
+  hipLaunchKernelGGL(k_box_update_xr<T>, grid_for(n), dim3(BLOCK), 0, st, n, x, r, p, q, pqparts,
+                     npq, sc, rho);
 }
 template <class T>
 int launch_box_dot2(long n, const T* z, const T* r, const T* q, double* parts, hipStream_t st) {
   hipLaunchKernelGGL(k_box_dot2<T>, grid_for(n), dim3(BLOCK), 0, st, n, z, r, q, parts);
   return (int)grid_for(n).x;
-}
-template <class T>
-void launch_box_update_p(long n, T* p, const T* z, const double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_box_update_p<T>, grid_for(n), dim3(BLOCK), 0, st, n, p, z, sc);
 }
 #define RT_BOX_INST(T)                                                                          \
   template void launch_box_residual<T>(int, int, int, int, int, const long long*, const double*, \
@@ -1381,11 +1414,11 @@ void launch_box_update_p(long n, T* p, const T* z, const double* sc, hipStream_t
                                           const T*, double*, const double*, const double*,     \
                                           double*, hipStream_t);                                \
   template int launch_box_dot1p<T>(long, const T*, const T*, T*, double*, hipStream_t);        \
-  template int launch_box_spmv<T>(const Level<T>&, const T*, T*, double*, hipStream_t);         \
-  template void launch_box_update_xr<T>(long, T*, T*, const T*, const T*, const double*,        \
-                                        hipStream_t);                                           \
-  template int launch_box_dot2<T>(long, const T*, const T*, const T*, double*, hipStream_t);   \
-  template void launch_box_update_p<T>(long, T*, const T*, const double*, hipStream_t);
+  template int launch_box_spmv_p<T>(const Level<T>&, const T*, const T*, T*, T*, const double*,  \
+                                    int, double*, int, int, bool, double*, hipStream_t);        \
+  template void launch_box_update_xr<T>(long, T*, T*, const T*, const T*, const double*, int,   \
+                                        double*, int, hipStream_t);                             \
+  template int launch_box_dot2<T>(long, const T*, const T*, const T*, double*, hipStream_t);
 RT_BOX_INST(double)
 RT_BOX_INST(float)
 #undef RT_BOX_INST
