@@ -81,6 +81,7 @@ struct rt_grid {
   bool have_tl = false;     // time-level face coefficients present
   bool mg_stale = true;     // coarse operators need rebuilding
   bool have_op = false;     // a Schur matrix is present
+  bool l0_fp32 = false;     // the FP32 finest-level operator copy matches the FP64 one
   double* hpin = nullptr;   // pinned host scalars for asynchronous read-back
   int nbox = 0;             // active source subdomains (0: V-cycle alone)
   int tk_override = -1;     // >= 0: time every launch under this class
@@ -397,10 +398,13 @@ int build_hierarchy(rt_grid* g) {
     for (size_t l = 1; l < w.L64.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<double>(w.L64[l - 1], w.L64[l], g->st));
   } else {
     Level<float>& L0 = w.L32[0];
-    TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.diag, L0.diag, g->st));
-    TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cx, L0.cx, g->st));
-    TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cy, L0.cy, g->st));
-    TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cz, L0.cz, g->st));
+    if (!g->l0_fp32) {
+      TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.diag, L0.diag, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cx, L0.cx, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cy, L0.cy, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cz, L0.cz, g->st));
+      g->l0_fp32 = true;
+    }
     for (size_t l = 1; l < w.L32.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<float>(w.L32[l - 1], w.L32[l], g->st));
   }
   if (g->nbox > 0) {
@@ -716,6 +720,20 @@ int check_ready(rt_grid* g, bool need_tl) {
   return RT_OK;
 }
 
+// Schur assembly into the workspace operator; with the colour-split FP32
+// finest level the kernel also writes that level's operator copy
+void schur_into_workspace(rt_grid* g, const double* U, const double* f, Step s, double* b) {
+  Workspace& w = g->w;
+  const bool f32 = g->prm.mg_fp32 && !w.L32.empty() && w.L32[0].split;
+  Level<float>* L0 = f32 ? &w.L32[0] : nullptr;
+  launch_schur(g->P, U, f, g->nH, g->eh, w.D, s, w.ftM, w.W, w.diag, w.cx, w.cy, w.cz, b,
+               f32 ? L0->diag : nullptr, f32 ? L0->cx : nullptr, f32 ? L0->cy : nullptr,
+               f32 ? L0->cz : nullptr, g->st);
+  g->l0_fp32 = f32;
+  g->mg_stale = true;
+  g->have_op = true;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -887,11 +905,7 @@ int rt_schur_form(rt_grid* g, const double* d_U, const double* d_f, double dt, c
                   double* d_b) {
   RTCHK(check_ready(g, true));
   if (!d_U || !d_f || !d_b || !c) return fail(g, RT_EINVAL, "null argument");
-  Workspace& w = g->w;
-  launch_schur(g->P, d_U, d_f, g->nH, g->eh, w.D, step_new(dt, c), w.ftM, w.W, w.diag, w.cx, w.cy,
-               w.cz, d_b, g->st);
-  g->mg_stale = true;
-  g->have_op = true;
+  schur_into_workspace(g, d_U, d_f, step_new(dt, c), d_b);
   HIPCHK(g, hipGetLastError());
   return RT_OK;
 }
@@ -926,6 +940,7 @@ int rt_set_operator(rt_grid* g, const double* d_diag, const double* d_cx, const 
   HIPCHK(g, hipMemcpyAsync(w.cy, d_cy, N * 8, hipMemcpyDeviceToDevice, g->st));
   HIPCHK(g, hipMemcpyAsync(w.cz, d_cz, N * 8, hipMemcpyDeviceToDevice, g->st));
   g->mg_stale = true;
+  g->l0_fp32 = false;
   g->have_op = true;
   return RT_OK;
 }
@@ -991,10 +1006,7 @@ int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_
   int k = 0;
   int status = RT_OK;
   while (fn >= g->prm.newton_tol && k < g->prm.newton_maxit) {
-    TK(g, RT_K_SCHUR, launch_schur(P, cur, w.f, g->nH, g->eh, w.D, s, w.ftM, w.W, w.diag, w.cx,
-                                   w.cy, w.cz, w.b, g->st));
-    g->mg_stale = true;
-    g->have_op = true;
+    TK(g, RT_K_SCHUR, schur_into_workspace(g, cur, w.f, s, w.b));
     int its = 0, vc = 0;
     double rr = 0;
     // ||J S + f||_2 equals the Schur residual norm (the local rows are solved

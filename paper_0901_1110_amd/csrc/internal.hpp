@@ -51,7 +51,8 @@ void launch_local_jac(const DevParams& P, const double* U, const double* nH, con
                       hipStream_t st);
 void launch_schur(const DevParams& P, const double* U, const double* f, const double* nH,
                   const double* eh, const double* D, Step s, double* ftM, double* W,
-                  double* diag, double* cx, double* cy, double* cz, double* b, hipStream_t st);
+                  double* diag, double* cx, double* cy, double* cz, double* b, float* d32,
+                  float* cx32, float* cy32, float* cz32, hipStream_t st);
 
 // ---- reductions / scalars ----
 void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out,

@@ -455,7 +455,11 @@ __global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __re
                                                   double* __restrict__ cx,
                                                   double* __restrict__ cy,
                                                   double* __restrict__ cz,
-                                                  double* __restrict__ b) {
+                                                  double* __restrict__ b,
+                                                  float* __restrict__ d32,
+                                                  float* __restrict__ cx32,
+                                                  float* __restrict__ cy32,
+                                                  float* __restrict__ cz32) {
   constexpr int NB = NS + 1;
   const int N = P.N;
   const C3 c = coord3(P.ny, P.nz);
@@ -489,11 +493,22 @@ __global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __re
     ftM[i * N + idx] = B[i][0];
     Wo[i * N + idx] = B[i][1];
   }
-  diag[idx] = (dloc + csum) - lw;
+  const double dg = (dloc + csum) - lw;
+  diag[idx] = dg;
   cx[idx] = cxp;
   cy[idx] = cyp;
   cz[idx] = czp;
   b[idx] = lf - f[NB * N + idx];
+  if (d32) {
+    // FP32 copy for the finest V-cycle level, colour-split: the cells of one
+    // colour of a row first, k = 2m + ((k + i + j) & 1) at place
+    // ((k + i + j) & 1) nz/2 + m
+    const int sidx = (c.i * P.ny + c.j) * P.nz + ((c.k + c.i + c.j) & 1) * (P.nz >> 1) + (c.k >> 1);
+    d32[sidx] = (float)dg;
+    cx32[sidx] = (float)cxp;
+    cy32[sidx] = (float)cyp;
+    cz32[sidx] = (float)czp;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1263,9 +1278,11 @@ void launch_local_jac(const DevParams& P, const double* U, const double* nH, con
 
 void launch_schur(const DevParams& P, const double* U, const double* f, const double* nH,
                   const double* eh, const double* D, Step s, double* ftM, double* W, double* diag,
-                  double* cx, double* cy, double* cz, double* b, hipStream_t st) {
+                  double* cx, double* cy, double* cz, double* b, float* d32, float* cx32,
+                  float* cy32, float* cz32, hipStream_t st) {
   const Geo q = geo3(P.nx, P.ny, P.nz);
-  RT_NS(P, k_schur, q.g, q.b, 0, st, P, U, f, nH, eh, D, s, ftM, W, diag, cx, cy, cz, b);
+  RT_NS(P, k_schur, q.g, q.b, 0, st, P, U, f, nH, eh, D, s, ftM, W, diag, cx, cy, cz, b, d32, cx32,
+        cy32, cz32);
 }
 
 void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out, hipStream_t st) {
