@@ -345,9 +345,12 @@ Step step_new(double dt, const rt_cosmo* c) { return Step{dt, c->a_new, c->H_new
 // cs: sweeps of the coarsest solve.  out64 (finest level of the FP32 cycle
 // only): the last smoothing launch writes the result widened to this FP64
 // vector itself
+// rd, qd, pd (a level in natural layout): the last smoothing launch also
+// leaves the block partials of x.rd and x.qd in pd
 template <class T>
 void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, int cs, double* out64 = nullptr,
-            const double* r64 = nullptr, const double* q64 = nullptr, double* parts = nullptr) {
+            const double* r64 = nullptr, const double* q64 = nullptr, double* parts = nullptr,
+            const T* rd = nullptr, const T* qd = nullptr, double* pd = nullptr) {
   const rt_params& p = g->prm;
   hipStream_t st = g->st;
   Level<T>& L = Ls[l];
@@ -384,6 +387,8 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, int cs, double* out64 
     TK(g, kc, launch_rbgs<T>(L, 1, st));
     if (out64 && s + 1 == post) {
       TK(g, kc, launch_rbgs_out64<T>(L, 0, out64, r64, q64, parts, st));
+    } else if (pd && s + 1 == post) {
+      TK(g, kc, launch_rbgs_dots<T>(L, 0, rd, qd, pd, st));
     } else {
       TK(g, kc, launch_rbgs<T>(L, 0, st));
     }
@@ -501,9 +506,12 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
   TK(g, RT_K_BOX, launch_final_reduce(w.bparts, np, 1, w.bsc + S_RHO, st));
   // the CG scalars are formed by the kernels that use them (each block sums
   // the partials itself), rho alternates between two slots and p between two
-  // buffers, so an iteration is the product, the update, the V-cycle and the
-  // dots: no reduction launches
+  // buffers, so an iteration is the product, the update and the V-cycle,
+  // whose last half-sweep forms the dots: no reduction launches
   T* pb[2] = {reinterpret_cast<T*>(w.bp2), bp};
+  // the box V-cycle's last half-sweep forms z.r and z.q (it exists when the
+  // box level is not the coarsest and post-smooths)
+  const bool fuse_dots = Ls.size() > 1 && g->prm.mg_post > 0;
   int nzp = 0;
   for (int it = 1; it <= g->prm.box_inner; ++it) {
     const int rho = (it & 1) ? S_RHO : S_RHO2, rho_prev = (it & 1) ? S_RHO2 : S_RHO;
@@ -513,8 +521,13 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
                                               rho, it == 1, w.bparts2, st));
     TK(g, RT_K_BOX, launch_box_update_xr<T>(n, x, br, p, bq, w.bparts2, np, w.bsc, rho, st));
     if (it == g->prm.box_inner) break;
-    vcycle<T>(g, Ls, 0, box_cs(g));
-    TK(g, RT_K_BOX, nzp = launch_box_dot2<T>(n, bz, br, bq, w.bparts, st));
+    if (fuse_dots) {
+      vcycle<T>(g, Ls, 0, box_cs(g), nullptr, nullptr, nullptr, nullptr, br, bq, w.bparts);
+      nzp = stencil_blocks(L0.nx, L0.ny, L0.nz / 2);
+    } else {
+      vcycle<T>(g, Ls, 0, box_cs(g));
+      TK(g, RT_K_BOX, nzp = launch_box_dot2<T>(n, bz, br, bq, w.bparts, st));
+    }
   }
   // boxes may overlap: one launch per box, in source order
   const int nbb = stencil_blocks(B, B, B);

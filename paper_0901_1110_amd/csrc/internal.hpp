@@ -91,6 +91,11 @@ template <class T> void launch_rbgs_first_pair(const Level<T>& L, T* xo, hipStre
 template <class T>
 void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, const double* r64,
                        const double* q64, double* parts, hipStream_t st);
+// half-sweep in place that also leaves the block partials of x.r and x.q
+// (all cells); returns their count
+template <class T>
+int launch_rbgs_dots(const Level<T>& L, int colour, const T* r, const T* q, double* parts,
+                     hipStream_t st);
 template <class T> void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st);
 // coarsest solve with each x-block in registers and LDS, one workgroup per
 // block (n / blocks <= COARSE_LDS_MAX, nx divisible by blocks)

@@ -739,6 +739,35 @@ __global__ __launch_bounds__(BLOCK) void k_rbgs_out64(Level<T> L, int colour,
   if (parts) block_reduce<2>(acc, parts);
 }
 
+// the last half-sweep of a V-cycle with the two dots that follow it: x is
+// updated in place, and the thread of cell k also reads its pair partner
+// k ^ 1 (the other colour, final already) to form the block partials of x.r
+// and x.q over both cells (r, q in the level's type, FP64 products and sums)
+template <class T, bool SF>
+__global__ __launch_bounds__(BLOCK) void k_rbgs_dots(Level<T> L, int colour,
+                                                     const T* __restrict__ r,
+                                                     const T* __restrict__ q,
+                                                     double* __restrict__ parts) {
+  double acc[2] = {0.0, 0.0};
+  const C3 c = coord3(L.ny, L.nz >> 1);
+  if (c.ok) {
+    const int k = 2 * c.k + ((c.i + c.j + colour) & 1);
+    const Nb7 nb = nbrs7<SF>(c.i, c.j, k, L.nx, L.ny, L.nz);
+    const T* x = L.x;
+    T s = L.b[nb.c];
+    s = s + L.cx[nb.c] * x[nb.xp] + L.cx[nb.xm] * x[nb.xm];
+    s = s + L.cy[nb.c] * x[nb.yp] + L.cy[nb.ym] * x[nb.ym];
+    s = s + L.cz[nb.c] * x[nb.zp] + L.cz[nb.zm] * x[nb.zm];
+    const T z0 = s / L.diag[nb.c];
+    const int pc = lidx<SF>(c.i, c.j, k ^ 1, L.ny, L.nz);
+    const T z1 = x[pc];
+    L.x[nb.c] = z0;
+    acc[0] = (double)z0 * (double)r[nb.c] + (double)z1 * (double)r[pc];
+    acc[1] = (double)z0 * (double)q[nb.c] + (double)z1 * (double)q[pc];
+  }
+  block_reduce<2>(acc, parts);
+}
+
 // the first (red, black) pair from x = 0 in one pass: red cells take b/diag,
 // black cells use their red neighbours' b/diag (the values the red half-sweep
 // would have produced)
@@ -1348,6 +1377,13 @@ void launch_rbgs_out64(const Level<T>& L, int colour, double* out64, const doubl
   RT_LAYOUT(L, k_rbgs_out64, T, q.g, q.b, 0, st, L, colour, out64, r64, q64, parts);
 }
 template <class T>
+int launch_rbgs_dots(const Level<T>& L, int colour, const T* r, const T* q, double* parts,
+                     hipStream_t st) {
+  const Geo g = geo3(L.nx, L.ny, L.nz / 2);
+  RT_LAYOUT(L, k_rbgs_dots, T, g.g, g.b, 0, st, L, colour, r, q, parts);
+  return (int)(g.g.x * g.g.y * g.g.z);
+}
+template <class T>
 void launch_coarse_solve_lds(const Level<T>& L, int sweeps, hipStream_t st) {
   hipLaunchKernelGGL(k_coarse_solve_lds<T>, dim3(L.blocks), dim3(CS_THREADS), 0, st, L, sweeps);
 }
@@ -1463,6 +1499,7 @@ void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st) {
   template void launch_rbgs<T>(const Level<T>&, int, hipStream_t);                   \
   template void launch_rbgs_first_pair<T>(const Level<T>&, T*, hipStream_t);         \
   template void launch_rbgs_out64<T>(const Level<T>&, int, double*, const double*, const double*, double*, hipStream_t); \
+  template int launch_rbgs_dots<T>(const Level<T>&, int, const T*, const T*, double*, hipStream_t); \
   template void launch_coarse_solve<T>(const Level<T>&, int, hipStream_t);           \
   template void launch_coarse_solve_lds<T>(const Level<T>&, int, hipStream_t); \
   template void launch_mg_residual<T>(const Level<T>&, hipStream_t);                 \
