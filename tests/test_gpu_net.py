@@ -82,6 +82,33 @@ def test_forward_and_decode_parity(ns):
         assert np.max(np.abs(Ug[v] - U_o[v])) <= 1e-9 * scale, v
 
 
+@pytest.mark.parametrize("shape", [(8, 64, 64), (32, 64, 128), (12, 6, 32), (10, 7, 48)])
+def test_forward_parity_tile_shapes(shape):
+    """Every tile of the plane-marching convolution against the oracle
+    network: 64, 32 and 16 cells along z, 4, 2 and 1 rows along y, one plane
+    per block and (32 x 64 x 128: two planes per block) the march that
+    fetches the next plane while computing the current one."""
+    ns = 1
+    rng = np.random.default_rng(sum(shape))
+    m = max(shape)
+    cut = (slice(0, shape[0]), slice(0, shape[1]), slice(0, shape[2]))
+    Un, nH, eh = synth.random_physical_state(m, ns, rng)
+    Unm1, _, ehm1 = synth.random_physical_state(m, ns, rng)
+    Un, Unm1 = Un[(slice(None),) + cut].copy(), Unm1[(slice(None),) + cut].copy()
+    nH, eh, ehm1 = nH[cut].copy(), eh[cut].copy(), ehm1[cut].copy()
+    u_e, u_E = synth.E_GAS_1E4K_X09999, 1e-20
+    net = RtNet(ns, shape)
+    theta = C.init_params(net.nin, net.nout, seed=7, last_scale=0.5).astype(np.float32)
+    net.set_params(theta)
+    Ug = torch.empty((ns + 2,) + shape, dtype=torch.float64, device="cuda")
+    net.forward(dev(Un), dev(Unm1), dev(eh), dev(ehm1), dev(nH), float(nH.mean()), u_e, u_E,
+                dev(eh), Ug)
+    out, feat = [host(t).astype(np.float64) for t in net.get_output()]
+    out_o, _ = C.forward(weights_bf16(theta, net.nin, net.nout), feat[:net.nin], net.nin, net.nout)
+    err = np.linalg.norm(out - out_o) / np.linalg.norm(out_o)
+    assert err <= 2e-2, err
+
+
 @pytest.mark.parametrize("ns", [1, 3])
 def test_gradient_parity(ns):
     n = 16

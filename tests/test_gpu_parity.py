@@ -225,6 +225,15 @@ def test_newton_steps_source_boxes():
     newton_parity(w, synth.initial_state(w), steps=3)
 
 
+@pytest.mark.parametrize("levels,post", [(1, 2), (2, 0)])
+def test_newton_steps_source_box_unfused_dots(levels, post):
+    """Box V-cycles whose last launch cannot form the inner dots (a single
+    box level, solved on chip; no post-smoothing): the separate dots launch."""
+    w = synth.CFG_256.replace(n=32, mg_levels=3, box_size=16, box_levels=levels, box_inner=4,
+                              box_coarse_sweeps=3, mg_post=post, mg_pre=2)
+    newton_parity(w, synth.initial_state(w), steps=2)
+
+
 def test_newton_steps_overlapping_boxes():
     """16 sources in a 32^3 lognormal cut: the 8^3 boxes overlap and their
     corrections add in source order on both sides."""
