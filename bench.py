@@ -275,7 +275,7 @@ def main():
                     help="source-subdomain correction: box edge in cells (0: V-cycle alone; "
                          "default 32 for hii_256, 0 for sg_q05_z4)")
     ap.add_argument("--box-levels", type=int, default=2)
-    ap.add_argument("--box-inner", type=int, default=16)
+    ap.add_argument("--box-inner", type=int, default=20)
     ap.add_argument("--box-coarse-sweeps", type=int, default=4,
                     help="sweeps of the coarsest box level (0: those of the main hierarchy)")
     ap.add_argument("--adaptive", type=float, default=0.0,

@@ -181,7 +181,10 @@ def pcg_fixed(op, b, ops, model, k, dtype=np.float64):
     rho = np.sum(r * z)
     for it in range(1, k + 1):
         q = apply_schur(p, *op)
-        alpha = rho / np.sum(p * q)
+        # the count is fixed: once the residual has vanished (p = 0, rho = 0)
+        # the iterate stays where it is
+        pq = np.sum(p * q)
+        alpha = rho / pq if pq > 0.0 else 0.0
         x = x + alpha * p
         r_old = r
         r = r - alpha * q
@@ -189,7 +192,7 @@ def pcg_fixed(op, b, ops, model, k, dtype=np.float64):
             break
         z = V(r)
         rho_new = np.sum(z * r)
-        beta = (rho_new - np.sum(z * r_old)) / rho
+        beta = (rho_new - np.sum(z * r_old)) / rho if rho != 0.0 else 0.0
         rho = rho_new
         p = z + beta * p
     return x

@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(BLOCK) void k_box_scatter_add(BoxMap m, const long 
 
 // ---- inner PCG of the subdomain correction, T the box V-cycle's type (the
 // vectors are kept in it; dot products accumulate in FP64 and leave block
-// partials for the final reduction, which forms the CG scalar).
+// partials, which the kernel that needs a CG scalar sums itself).
 // rho = r.z, p = z
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_box_dot1p(long n, const T* __restrict__ r,
@@ -1150,7 +1150,10 @@ __global__ __launch_bounds__(BLOCK) void k_box_spmv_p(int nx, int ny, int nz,
   if (!first) {
     const double zr = block_sum_parts(zparts, nz_parts, 0);
     const double zq = block_sum_parts(zparts, nz_parts, 1);
-    beta = (-sc[S_ALPHA] * zq) / sc[rho_in];
+    // a fixed number of iterations runs whatever the convergence: once the
+    // box residual has vanished (rho = 0) the direction is z itself
+    const double rho_prev = sc[rho_in];
+    beta = rho_prev != 0.0 ? (-sc[S_ALPHA] * zq) / rho_prev : 0.0;
     if (block_linear() == 0 && threadIdx.x == 0 && threadIdx.y == 0) sc[rho_out] = zr;
   }
   auto pn = [&](int i) -> T { return first ? z[i] : (T)(z[i] + beta * pin[i]); };
@@ -1178,7 +1181,10 @@ __global__ __launch_bounds__(BLOCK) void k_box_update_xr(long n, T* __restrict__
                                                           const T* __restrict__ q,
                                                           const double* __restrict__ pqparts,
                                                           int npq, double* sc, int rho) {
-  const double alpha = sc[rho] / block_sum_parts(pqparts, npq, 0);
+  // p.q > 0 for any p != 0 (S is positive definite); p = 0 once the box
+  // residual has vanished, and then x and r stay as they are
+  const double pq = block_sum_parts(pqparts, npq, 0);
+  const double alpha = pq > 0.0 ? sc[rho] / pq : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[S_ALPHA] = alpha;
   const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
   if (i >= n) return;

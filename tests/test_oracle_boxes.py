@@ -65,3 +65,24 @@ def test_pcg_with_boxes_reaches_the_dense_solution():
     for x in (x0, x1):
         assert np.max(np.abs(x - x_ref)) <= 1e-9 * np.max(np.abs(x_ref))
     assert it1 <= it0
+
+
+def test_fixed_count_pcg_stops_moving_once_converged():
+    """The inner PCG of the correction runs a fixed number of iterations: a
+    zero right side stays zero (no 0/0), and on a box small enough for the
+    V-cycle to be an exact solve, iterations beyond convergence leave the
+    solution of the dense system unchanged."""
+    n = 8
+    op = random_op(n, 5)
+    w = synth.CFG_SMALL.replace(n=n, mg_levels=1)
+    m = oracle.model_from_workload(w)
+    m = dataclasses.replace(m, mg_coarse_sweeps=200)
+    ops = mg.hierarchy(op, 1)
+    x = mg.pcg_fixed(op, np.zeros((n,) * 3), ops, m, 6)
+    assert np.all(x == 0.0)
+    b = np.random.default_rng(6).standard_normal((n,) * 3)
+    x_ref = np.linalg.solve(dense(op, (n,) * 3), b.ravel()).reshape((n,) * 3)
+    for k in (2, 8):
+        x = mg.pcg_fixed(op, b, ops, m, k)
+        assert np.all(np.isfinite(x))
+        assert np.max(np.abs(x - x_ref)) <= 1e-10 * np.max(np.abs(x_ref)), k
