@@ -632,7 +632,7 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   const int nparts = reduce_blocks(N);
   RTCHK(build_hierarchy(g));
   double h[2];
-  TK(g, RT_K_CG_VECTOR, launch_dot1(N, b, b, w.parts, g->st));
+  TK(g, RT_K_CG_VECTOR, launch_dot1(N, b, b, w.parts, g->st, w.r));   // and r = b
   finish_reduce(g, nparts, 1, S_BB);
   RTCHK(read_scalars(g, w.sc + S_BB, h, 1));
   const double bn = std::sqrt(h[0]);
@@ -645,13 +645,11 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
     HIPCHK(g, hipGetLastError());
     return RT_OK;
   }
-  HIPCHK(g, hipMemcpyAsync(w.r, b, N * sizeof(double), hipMemcpyDeviceToDevice, g->st));
   int nd = 0;
   RTCHK(apply_precond(g, w.r, w.z, false, &nd));
   ++*vcycles;
-  TK(g, RT_K_CG_VECTOR, launch_dot1(N, w.r, w.z, w.parts, g->st));
+  TK(g, RT_K_CG_VECTOR, launch_dot1(N, w.r, w.z, w.parts, g->st, w.p));   // and p = z
   finish_reduce(g, nparts, 1, S_RHO);
-  HIPCHK(g, hipMemcpyAsync(w.p, w.z, N * sizeof(double), hipMemcpyDeviceToDevice, g->st));
   // The tail of an iteration (V-cycle, dots, new direction) writes only z, p
   // and CG scalars, so it can be enqueued before this iteration's residual
   // norm has come back to the host: the device then never idles on the
@@ -1001,12 +999,13 @@ int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_
   double fn, viol;
   RTCHK(residual_norm(g, d_U, w.g, s, w.f, &fn, &viol));
   st.fnorm_guess = fn;
+  bool use_alt = false;
   if (d_Ualt) {
     double fa, va;
     RTCHK(residual_norm(g, d_Ualt, w.g, s, w.ft, &fa, &va));
     st.fnorm_alt = fa;
     if (std::isfinite(fa) && va == 0.0 && fa < fn) {
-      HIPCHK(g, hipMemcpyAsync(d_U, d_Ualt, bytesU, hipMemcpyDeviceToDevice, g->st));
+      use_alt = true;
       std::swap(w.f, w.ft);
       fn = fa;
       st.used_alt_guess = 1;
@@ -1014,7 +1013,9 @@ int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_
   }
   st.fnorm[0] = fn;
   if (!std::isfinite(fn)) return finish(fail(g, RT_ENONFINITE, "non-finite initial residual"));
-  double* cur = d_U;       // current iterate: the caller's buffer or w.Ut
+  // current iterate: the caller's buffer, w.Ut or (read only, until the first
+  // accepted trial) the alternative guess, which is therefore not copied
+  const double* cur = use_alt ? d_Ualt : d_U;
   double* spare = w.Ut;
   int k = 0;
   int status = RT_OK;
@@ -1049,7 +1050,13 @@ int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_
       status = fail(g, RT_ELINESEARCH, "line search failed at Newton iteration %d", k);
       break;
     }
-    std::swap(cur, spare);
+    {
+      // the accepted trial becomes the iterate; the next trial goes to the
+      // other writable buffer (never the alternative guess)
+      double* accepted = spare;
+      spare = cur == d_Ualt ? (accepted == w.Ut ? d_U : w.Ut) : const_cast<double*>(cur);
+      cur = accepted;
+    }
     std::swap(w.f, w.ft);
     fn = ftn;
     st.lambda[k] = lam;

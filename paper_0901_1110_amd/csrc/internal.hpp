@@ -70,7 +70,8 @@ void launch_update_xr(long n, double* x, double* r, const double* p, const doubl
                       const double* sc, double* parts, hipStream_t st);
 void launch_dot2(long n, const double* z, const double* r, const double* q, double* parts,
                  hipStream_t st);
-void launch_dot1(long n, const double* a, const double* b, double* parts, hipStream_t st);
+void launch_dot1(long n, const double* a, const double* b, double* parts, hipStream_t st,
+                 double* copy_b = nullptr);
 void launch_update_p(long n, double* p, const double* z, const double* sc, hipStream_t st);
 
 // ---- multigrid (T = double or float) ----

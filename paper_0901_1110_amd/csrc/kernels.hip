@@ -612,12 +612,17 @@ __global__ __launch_bounds__(BLOCK) void k_dot2(long n, const double* __restrict
   block_reduce<2>(acc, parts);
 }
 
+// partials of a.b; copy_b non-null: also copy_b = b (the copy rides on the read)
 __global__ __launch_bounds__(BLOCK) void k_dot1(long n, const double* __restrict__ a,
                                                  const double* __restrict__ b,
-                                                 double* __restrict__ parts) {
+                                                 double* __restrict__ parts,
+                                                 double* __restrict__ copy_b) {
   double acc[1] = {0.0};
-  for (long i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK)
-    acc[0] += a[i] * b[i];
+  for (long i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK) {
+    const double bv = b[i];
+    acc[0] += a[i] * bv;
+    if (copy_b) copy_b[i] = bv;
+  }
   block_reduce<1>(acc, parts);
 }
 
@@ -1348,8 +1353,9 @@ void launch_dot2(long n, const double* z, const double* r, const double* q, doub
                  hipStream_t st) {
   hipLaunchKernelGGL(k_dot2, dim3(reduce_blocks(n)), dim3(BLOCK), 0, st, n, z, r, q, parts);
 }
-void launch_dot1(long n, const double* a, const double* b, double* parts, hipStream_t st) {
-  hipLaunchKernelGGL(k_dot1, dim3(reduce_blocks(n)), dim3(BLOCK), 0, st, n, a, b, parts);
+void launch_dot1(long n, const double* a, const double* b, double* parts, hipStream_t st,
+                 double* copy_b) {
+  hipLaunchKernelGGL(k_dot1, dim3(reduce_blocks(n)), dim3(BLOCK), 0, st, n, a, b, parts, copy_b);
 }
 void launch_update_p(long n, double* p, const double* z, const double* sc, hipStream_t st) {
   hipLaunchKernelGGL(k_update_p, grid_for(n), dim3(BLOCK), 0, st, n, p, z, sc);

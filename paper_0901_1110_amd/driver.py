@@ -106,9 +106,13 @@ class LearnedSimulation(Simulation):
         if self.Unm1 is None:
             self.Unm1 = torch.empty_like(self.Un)
             self.ehm1 = torch.empty_like(self.eh)
-        self.Unm1.copy_(self.Un)
+        # level n becomes level n - 1 by rotating the three state buffers (U
+        # is overwritten by the next step's guess anyway); e_h is updated in
+        # place, so its old value is copied
         self.ehm1.copy_(self.eh)
-        super().advance()
+        self.grid.rt_fold_energy(self.U, self.eh)
+        self.Unm1, self.Un, self.U = self.Un, self.U, self.Unm1
+        self.step_index += 1
 
 
 def generate_trajectory(w, steps, device="cuda", state=None, **overrides):
