@@ -65,7 +65,7 @@ BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0
 # kernel source it was measured on and is reported as null for any other.
 PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "dots": True,
                              "bytes_per_launch": 4.198e8,
-                             "kernels_sha256": "362da2f45caab4aac6c208d7c22d57384aea7af4b2e4aa8ec698857624ca3d86"}}
+                             "kernels_sha256": "8ddfac089fa5146e05eb323430df8a34f4ded86afa42479a66f9182dced07689"}}
 
 
 def kernels_sha256():
