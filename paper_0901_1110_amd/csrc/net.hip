@@ -308,21 +308,25 @@ __device__ inline void transform(const double* U, const double* e, int c, int N,
   for (int s = 0; s < S.ns; ++s) t[2 + s] = logit_s(U[(size_t)(1 + s) * N + c]);
 }
 
+// base non-null: also the FP64 extrapolation 2 t^n - t^(n-1) that the
+// decode adds the network's correction to ([nt][N])
 __global__ void k_features(int N, Scales S, const double* __restrict__ Un,
                            const double* __restrict__ Unm1, const double* __restrict__ en,
                            const double* __restrict__ enm1, const double* __restrict__ nH,
-                           bf16* __restrict__ feat) {
+                           bf16* __restrict__ feat, double* __restrict__ base) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
-  double t[5];
+  double t[5], tm[5];
   float f[CH];
 #pragma unroll
   for (int q = 0; q < CH; ++q) f[q] = 0.f;
   const int nt = S.ns + 2;
   transform(Un, en, c, N, S, t);
   for (int q = 0; q < nt; ++q) f[q] = (float)t[q];
-  transform(Unm1, enm1, c, N, S, t);
-  for (int q = 0; q < nt; ++q) f[nt + q] = (float)t[q];
+  transform(Unm1, enm1, c, N, S, tm);
+  for (int q = 0; q < nt; ++q) f[nt + q] = (float)tm[q];
+  if (base)
+    for (int q = 0; q < nt; ++q) base[(size_t)q * N + c] = 2.0 * t[q] - tm[q];
   f[2 * nt] = (float)log10(nH[c] / S.nH_mean);
   v4s* out = reinterpret_cast<v4s*>(feat + (size_t)c * CH);
 #pragma unroll
@@ -352,17 +356,15 @@ __global__ void k_target(int N, Scales S, const double* __restrict__ Un,
 }
 
 // guess = inverse transform of (linear extrapolation + network correction)
-__global__ void k_decode(int N, Scales S, const double* __restrict__ Un,
-                         const double* __restrict__ en, const double* __restrict__ Unm1,
-                         const double* __restrict__ enm1, const double* __restrict__ eh,
-                         const float* __restrict__ d, double* __restrict__ Ug) {
+// base: the extrapolation the features pass stored
+__global__ void k_decode(int N, Scales S, const double* __restrict__ base,
+                         const double* __restrict__ eh, const float* __restrict__ d,
+                         double* __restrict__ Ug) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
-  double t[5], tm[5];
-  transform(Un, en, c, N, S, t);
-  transform(Unm1, enm1, c, N, S, tm);
+  double t[5];
   const int ns = S.ns;
-  for (int q = 0; q < ns + 2; ++q) t[q] = (2.0 * t[q] - tm[q]) + (double)d[(size_t)q * N + c];
+  for (int q = 0; q < ns + 2; ++q) t[q] = base[(size_t)q * N + c] + (double)d[(size_t)q * N + c];
   Ug[(size_t)(ns + 1) * N + c] = S.u_E * pow(10.0, t[0]);
   Ug[c] = S.u_e * t[1] - eh[c];
   double x[3];
@@ -495,6 +497,7 @@ struct rt_net {
   float *out, *tgt, *part, *grad, *th, *m, *v, *bias;
   bf16 *Wf, *Wt;
   double *lpart, *lsum, *wE, *wsum;
+  double* base;   // FP64 extrapolation 2 t(U^n) - t(U^(n-1)) of the last features pass
   int nblk_loss;
   int step = 0;
   std::string err;
@@ -536,6 +539,7 @@ size_t carve_net(int ns, int nx, int ny, int nz, char* base, rt_net* n) {
   t->lsum = (double*)take(64);
   t->wE = (double*)take(N * 8);
   t->wsum = (double*)take(64);
+  t->base = (double*)take(N * nout * 8);
   if (n) {
     n->ns = ns; n->nin = nin; n->nout = nout; n->P = P;
     int o = 0;
@@ -685,10 +689,10 @@ int rt_net_forward(rt_net* n, const double* d_Un, const double* d_Unm1, const do
   const Scales S = scales(n, u_e, u_E, nH_mean);
   const int N = n->g.N;
   hipLaunchKernelGGL(k_features, dim3(nb(N, 256)), dim3(256), 0, n->st, N, S, d_Un, d_Unm1, d_en,
-                     d_enm1, d_nH, n->feat);
+                     d_enm1, d_nH, n->feat, n->base);
   forward(n);
-  hipLaunchKernelGGL(k_decode, dim3(nb(N, 256)), dim3(256), 0, n->st, N, S, d_Un, d_en, d_Unm1,
-                     d_enm1, d_eh, n->out, d_Uguess);
+  hipLaunchKernelGGL(k_decode, dim3(nb(N, 256)), dim3(256), 0, n->st, N, S, n->base, d_eh, n->out,
+                     d_Uguess);
   NCHK(n, hipGetLastError());
   return RT_OK;
 }
@@ -716,7 +720,7 @@ int rt_net_train_step(rt_net* n, const double* d_Un, const double* d_Unm1, const
   const Scales S = scales(n, u_e, u_E, nH_mean);
   const int N = n->g.N;
   hipLaunchKernelGGL(k_features, dim3(nb(N, 256)), dim3(256), 0, n->st, N, S, d_Un, d_Unm1, d_en,
-                     d_enm1, d_nH, n->feat);
+                     d_enm1, d_nH, n->feat, nullptr);
   hipLaunchKernelGGL(k_target, dim3(nb(N, 256)), dim3(256), 0, n->st, N, S, d_Un, d_en, d_Unm1,
                      d_enm1, d_Unp1, d_enp1, n->tgt, n->wE);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, n->st, n->wE, N, n->wsum);
