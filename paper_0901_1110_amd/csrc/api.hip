@@ -52,7 +52,7 @@ struct Workspace {
   // source subdomains: boxes of B^3 cells around the sources, stacked along x
   int box_cap = 0;                        // boxes the workspace holds (max_sources)
   double *bd, *bcx, *bcy, *bcz;           // box operator (FP64, level 0 of B64)
-  double *bxv, *br, *bz, *bp, *bp2, *bq;  // inner PCG vectors (FP32 cycle: float inside)
+  double *bxv, *br, *br2, *bz, *bp, *bp2, *bq;  // inner PCG vectors (FP32 cycle: float inside)
   double *bparts, *bparts2, *bsc;
   std::vector<Level<double>> B64;
   std::vector<Level<float>> B32;
@@ -280,7 +280,7 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
     w->bcy = c.take<double>(nb3); w->bcz = c.take<double>(nb3);
     w->bxv = c.take<double>(nb3); w->br = c.take<double>(nb3);
     w->bz = c.take<double>(nb3); w->bp = c.take<double>(nb3); w->bq = c.take<double>(nb3);
-    w->bp2 = c.take<double>(nb3);
+    w->bp2 = c.take<double>(nb3); w->br2 = c.take<double>(nb3);
     const size_t sb = (size_t)stencil_blocks(w->box_cap * B, B, B);
     w->bparts = c.take<double>((sb > (size_t)MAX_PARTS ? sb : (size_t)MAX_PARTS) * NCOMP_MAX);
     w->bparts2 = c.take<double>((sb > (size_t)MAX_PARTS ? sb : (size_t)MAX_PARTS) * NCOMP_MAX);
@@ -350,7 +350,8 @@ Step step_new(double dt, const rt_cosmo* c) { return Step{dt, c->a_new, c->H_new
 template <class T>
 void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, int cs, double* out64 = nullptr,
             const double* r64 = nullptr, const double* q64 = nullptr, double* parts = nullptr,
-            const T* rd = nullptr, const T* qd = nullptr, double* pd = nullptr) {
+            const T* rd = nullptr, const T* qd = nullptr, double* pd = nullptr,
+            bool first_done = false) {
   const rt_params& p = g->prm;
   hipStream_t st = g->st;
   Level<T>& L = Ls[l];
@@ -368,7 +369,8 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, int cs, double* out64 
   const int pre = coarsest ? cs : p.mg_pre;
   const int post = coarsest ? cs : p.mg_post;
   if (pre > 0) {
-    TK(g, kc, launch_rbgs_first_pair<T>(L, L.x, st));   // (red, black) from x = 0
+    // (red, black) from x = 0, unless a fused launch has already done it
+    if (!first_done) TK(g, kc, launch_rbgs_first_pair<T>(L, L.x, st));
     for (int s = 1; s < pre; ++s) {
       TK(g, kc, launch_rbgs<T>(L, 0, st));
       TK(g, kc, launch_rbgs<T>(L, 1, st));
@@ -513,22 +515,39 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
   // box level is not the coarsest and post-smooths)
   const bool fuse_dots = Ls.size() > 1 && g->prm.mg_post > 0;
   int nzp = 0;
+  // the update before each box V-cycle runs inside its first (red, black)
+  // pair (when the cycle pre-smooths and is not a coarsest solve); r then
+  // alternates between two buffers
+  const bool fuse_first = Ls.size() > 1 && g->prm.mg_pre > 0;
+  T* rb[2] = {br, reinterpret_cast<T*>(w.br2)};
+  int ri = 0;
   for (int it = 1; it <= g->prm.box_inner; ++it) {
     const int rho = (it & 1) ? S_RHO : S_RHO2, rho_prev = (it & 1) ? S_RHO2 : S_RHO;
     T* p = pb[it & 1];
     const T* p_prev = pb[(it + 1) & 1];
     TK(g, RT_K_BOX, np = launch_box_spmv_p<T>(L0, bz, p_prev, p, bq, w.bparts, nzp, w.bsc, rho_prev,
                                               rho, it == 1, w.bparts2, st));
-    TK(g, RT_K_BOX, launch_box_update_xr<T>(n, x, br, p, bq, w.bparts2, np, w.bsc, rho, st));
-    if (it == g->prm.box_inner) break;
+    const bool last = it == g->prm.box_inner;
+    if (last || !fuse_first) {
+      TK(g, RT_K_BOX, launch_box_update_xr<T>(n, x, rb[ri], p, bq, w.bparts2, np, w.bsc, rho, st));
+      if (last) break;
+    } else {
+      TK(g, RT_K_BOX, launch_box_update_first_pair<T>(L0, x, rb[ri], rb[ri ^ 1], p, bq, w.bparts2,
+                                                      np, w.bsc, rho, st));
+      ri ^= 1;
+    }
+    T* r = rb[ri];
+    L0.b = r;
     if (fuse_dots) {
-      vcycle<T>(g, Ls, 0, box_cs(g), nullptr, nullptr, nullptr, nullptr, br, bq, w.bparts);
+      vcycle<T>(g, Ls, 0, box_cs(g), nullptr, nullptr, nullptr, nullptr, r, bq, w.bparts, fuse_first);
       nzp = stencil_blocks(L0.nx, L0.ny, L0.nz / 2);
     } else {
-      vcycle<T>(g, Ls, 0, box_cs(g));
-      TK(g, RT_K_BOX, nzp = launch_box_dot2<T>(n, bz, br, bq, w.bparts, st));
+      vcycle<T>(g, Ls, 0, box_cs(g), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                fuse_first);
+      TK(g, RT_K_BOX, nzp = launch_box_dot2<T>(n, bz, r, bq, w.bparts, st));
     }
   }
+  L0.b = br;
   // boxes may overlap: one launch per box, in source order
   const int nbb = stencil_blocks(B, B, B);
   for (int s = 0; s < g->nbox; ++s)

@@ -140,6 +140,12 @@ int launch_box_spmv_p(const Level<T>& L, const T* z, const T* pin, T* pout, T* q
 template <class T>
 void launch_box_update_xr(long n, T* x, T* r, const T* p, const T* q, const double* pqparts,
                           int npq, double* sc, int rho, hipStream_t st);
+// the update above fused with the first (red, black) pair of the box V-cycle
+// (level L, right side rn = ro - alpha q, written to rn; L.x receives the pair)
+template <class T>
+void launch_box_update_first_pair(const Level<T>& L, T* x, const T* ro, T* rn, const T* p,
+                                  const T* q, const double* pqparts, int npq, double* sc, int rho,
+                                  hipStream_t st);
 template <class T>
 int launch_box_dot2(long n, const T* z, const T* r, const T* q, double* parts, hipStream_t st);
 // FP64 natural field -> FP32 field in the layout of level L

@@ -1196,6 +1196,41 @@ __global__ __launch_bounds__(BLOCK) void k_box_update_xr(long n, T* __restrict__
   x[i] = (T)(x[i] + alpha * p[i]);
   r[i] = (T)(r[i] - alpha * q[i]);
 }
+// the box V-cycle's first (red, black) pair from z = 0 fused with the CG
+// update before it: alpha as in k_box_update_xr, x += alpha p and
+// rn = ro - alpha q at the thread's cell (rn in its own buffer: other blocks
+// still read ro), then the pair with right side rn, whose values at the six
+// neighbours the black cells form themselves from ro and q (natural layout)
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_box_update_first_pair(Level<T> L, T* __restrict__ x,
+                                                                  const T* __restrict__ ro,
+                                                                  T* __restrict__ rn,
+                                                                  const T* __restrict__ p,
+                                                                  const T* __restrict__ q,
+                                                                  const double* __restrict__ pqparts,
+                                                                  int npq, double* sc, int rho) {
+  const double pq = block_sum_parts(pqparts, npq, 0);
+  const double alpha = pq > 0.0 ? sc[rho] / pq : 0.0;
+  if (block_linear() == 0 && threadIdx.x == 0 && threadIdx.y == 0) sc[S_ALPHA] = alpha;
+  const C3 c = coord3(L.ny, L.nz);
+  if (!c.ok) return;
+  const int idx = (c.i * L.ny + c.j) * L.nz + c.k;
+  auto rnew = [&](int i) -> T { return (T)(ro[i] - alpha * q[i]); };
+  x[idx] = (T)(x[idx] + alpha * p[idx]);
+  const T bc = rnew(idx);
+  rn[idx] = bc;
+  const T* d = L.diag;
+  if (((c.i + c.j + c.k) & 1) == 0) {
+    L.x[idx] = bc / d[idx];
+    return;
+  }
+  const Nb nb = nbrs(c.i, c.j, c.k, L.nx, L.ny, L.nz);
+  T s = bc;
+  s = s + L.cx[idx] * (rnew(nb.xp) / d[nb.xp]) + L.cx[nb.xm] * (rnew(nb.xm) / d[nb.xm]);
+  s = s + L.cy[idx] * (rnew(nb.yp) / d[nb.yp]) + L.cy[nb.ym] * (rnew(nb.ym) / d[nb.ym]);
+  s = s + L.cz[idx] * (rnew(nb.zp) / d[nb.zp]) + L.cz[nb.zm] * (rnew(nb.zm) / d[nb.zm]);
+  L.x[idx] = s / d[idx];
+}
 // the partials of z.r and z.q
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_box_dot2(long n, const T* __restrict__ z,
@@ -1467,6 +1502,14 @@ void launch_box_update_xr(long n, T* x, T* r, const T* p, const T* q, const doub
                      npq, sc, rho);
 }
 template <class T>
+void launch_box_update_first_pair(const Level<T>& L, T* x, const T* ro, T* rn, const T* p,
+                                  const T* q, const double* pqparts, int npq, double* sc, int rho,
+                                  hipStream_t st) {
+  const Geo g = geo3(L.nx, L.ny, L.nz);
+  hipLaunchKernelGGL(k_box_update_first_pair<T>, g.g, g.b, 0, st, L, x, ro, rn, p, q, pqparts, npq,
+                     sc, rho);
+}
+template <class T>
 int launch_box_dot2(long n, const T* z, const T* r, const T* q, double* parts, hipStream_t st) {
   hipLaunchKernelGGL(k_box_dot2<T>, grid_for(n), dim3(BLOCK), 0, st, n, z, r, q, parts);
   return (int)grid_for(n).x;
@@ -1483,6 +1526,9 @@ int launch_box_dot2(long n, const T* z, const T* r, const T* q, double* parts, h
                                     int, double*, int, int, bool, double*, hipStream_t);        \
   template void launch_box_update_xr<T>(long, T*, T*, const T*, const T*, const double*, int,   \
                                         double*, int, hipStream_t);                             \
+  template void launch_box_update_first_pair<T>(const Level<T>&, T*, const T*, T*, const T*,      \
+                                                const T*, const double*, int, double*, int,     \
+                                                hipStream_t);                                   \
   template int launch_box_dot2<T>(long, const T*, const T*, const T*, double*, hipStream_t);
 RT_BOX_INST(double)
 RT_BOX_INST(float)
