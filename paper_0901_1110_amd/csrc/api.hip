@@ -82,6 +82,7 @@ struct rt_grid {
   bool mg_stale = true;     // coarse operators need rebuilding
   bool have_op = false;     // a Schur matrix is present
   bool l0_fp32 = false;     // the FP32 finest-level operator copy matches the FP64 one
+  const double* r32_of = nullptr;   // the CG residual whose FP32 copy is the finest right side
   double* hpin = nullptr;   // pinned host scalars for asynchronous read-back
   int nbox = 0;             // active source subdomains (0: V-cycle alone)
   int tk_override = -1;     // >= 0: time every launch under this class
@@ -452,8 +453,10 @@ int apply_vcycle(rt_grid* g, const double* r, double* z, bool dots = false) {
   Level<float>& L0 = w.L32[0];
   if (fp32_fused(&g->prm)) {
     // r is converted (into the colour-split layout) by a pass of its own:
-    // read at seven points by the first pair, FP64 r costs more than it saves
-    TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f_level(L0, r, L0.b, g->st));
+    // read at seven points by the first pair, FP64 r costs more than it saves.
+    // The CG's own residual arrives converted by its update.
+    if (g->r32_of != r) TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f_level(L0, r, L0.b, g->st));
+    g->r32_of = r == w.r ? r : nullptr;
     if (dots) {
       vcycle<float>(g, w.L32, 0, g->prm.mg_coarse_sweeps, z, r, w.q, w.parts);
       return stencil_blocks(L0.nx, L0.ny, L0.nz / 2);
@@ -652,6 +655,7 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   RTCHK(build_hierarchy(g));
   double h[2];
   TK(g, RT_K_CG_VECTOR, launch_dot1(N, b, b, w.parts, g->st, w.r));   // and r = b
+  g->r32_of = nullptr;
   finish_reduce(g, nparts, 1, S_BB);
   RTCHK(read_scalars(g, w.sc + S_BB, h, 1));
   const double bn = std::sqrt(h[0]);
@@ -693,7 +697,13 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
     TK(g, RT_K_SPMV, launch_spmv_dot(g->P.nx, g->P.ny, g->P.nz, w.diag, w.cx, w.cy, w.cz, w.p, w.q, w.parts, g->st));
     TK(g, RT_K_REDUCE, launch_final_reduce_alpha(w.parts, stencil_blocks(g->P.nx, g->P.ny, g->P.nz),
                                                  w.sc, g->st));
-    TK(g, RT_K_CG_VECTOR, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st));
+    if (fp32_fused(&g->prm)) {
+      TK(g, RT_K_CG_VECTOR, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st,
+                                             w.L32[0].b, g->P.ny, g->P.nz));
+      g->r32_of = w.r;
+    } else {
+      TK(g, RT_K_CG_VECTOR, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st));
+    }
     finish_reduce(g, nparts, 1, S_RR);
     HIPCHK(g, hipMemcpyAsync(g->hpin, w.sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, g->st));
     HIPCHK(g, hipEventRecord(g->ev_rd, g->st));

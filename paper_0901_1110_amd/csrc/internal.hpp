@@ -67,7 +67,8 @@ void launch_spmv_dot(int nx, int ny, int nz, const double* diag, const double* c
                      const double* cy, const double* cz, const double* p, double* q,
                      double* parts, hipStream_t st);
 void launch_update_xr(long n, double* x, double* r, const double* p, const double* q,
-                      const double* sc, double* parts, hipStream_t st);
+                      const double* sc, double* parts, hipStream_t st,
+                      float* r32 = nullptr, int ny = 0, int nz = 0);
 void launch_dot2(long n, const double* z, const double* r, const double* q, double* parts,
                  hipStream_t st);
 void launch_dot1(long n, const double* a, const double* b, double* parts, hipStream_t st,

@@ -582,12 +582,16 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_dot(int nx, int ny, int nz,
   block_reduce<1>(acc, parts);
 }
 
+// r32 non-null: also the FP32 copy of the new r in the colour-split layout of
+// the FP32 cycle's finest level (ny, nz its extents), so that the V-cycle
+// that follows needs no conversion pass
 __global__ __launch_bounds__(BLOCK) void k_update_xr(long n, double* __restrict__ x,
                                                       double* __restrict__ r,
                                                       const double* __restrict__ p,
                                                       const double* __restrict__ q,
                                                       const double* __restrict__ sc,
-                                                      double* __restrict__ parts) {
+                                                      double* __restrict__ parts,
+                                                      float* __restrict__ r32, int ny, int nz) {
   const double alpha = sc[S_ALPHA];
   double acc[1] = {0.0};
   for (long i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long)gridDim.x * BLOCK) {
@@ -595,6 +599,12 @@ __global__ __launch_bounds__(BLOCK) void k_update_xr(long n, double* __restrict_
     const double rv = r[i] - alpha * q[i];
     r[i] = rv;
     acc[0] += rv * rv;
+    if (r32) {
+      const long row = i / nz;
+      const int k = (int)(i - row * nz);
+      const int j = (int)(row % ny), ii = (int)(row / ny);
+      r32[row * nz + ((k + ii + j) & 1) * (nz >> 1) + (k >> 1)] = (float)rv;
+    }
   }
   block_reduce<1>(acc, parts);
 }
@@ -1380,9 +1390,10 @@ void launch_spmv_dot(int nx, int ny, int nz, const double* diag, const double* c
   hipLaunchKernelGGL(k_spmv_dot, g.g, g.b, 0, st, nx, ny, nz, diag, cx, cy, cz, p, q, parts);
 }
 void launch_update_xr(long n, double* x, double* r, const double* p, const double* q,
-                      const double* sc, double* parts, hipStream_t st) {
+                      const double* sc, double* parts, hipStream_t st, float* r32, int ny,
+                      int nz) {
   hipLaunchKernelGGL(k_update_xr, dim3(reduce_blocks(n)), dim3(BLOCK), 0, st, n, x, r, p, q, sc,
-                     parts);
+                     parts, r32, ny, nz);
 }
 void launch_dot2(long n, const double* z, const double* r, const double* q, double* parts,
                  hipStream_t st) {
