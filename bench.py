@@ -65,7 +65,7 @@ BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0
 # kernel source it was measured on and is reported as null for any other.
 PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "dots": True,
                              "bytes_per_launch": 4.198e8,
-                             "kernels_sha256": "5b81d38c4d93808ba44e4385609f7438d383b25de5d1390aebc1d18e64cfc98e"}}
+                             "kernels_sha256": "30d3d56a17f7a2c42448280a75d4a956f54a4660e32b1f764829694b9c264f47"}}
 
 
 def kernels_sha256():
