@@ -55,6 +55,15 @@ HBM_PEAK_GBS = 8000.0
 #              the dots over the box cells)
 # (w = 4 B for the FP32 V-cycle, 8 B for FP64)
 BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0}
+# with the FP32 cycle the Schur assembly also writes the four FP32 operator
+# arrays of the finest level
+SCHUR_FP32_EXTRA = 16.0
+
+
+def class_bytes_per_cell(dom, wbytes):
+    """Algorithmic bytes per cell of one launch of a modelled Newton-level class."""
+    b = BYTES_PER_CELL[dom]
+    return b + (SCHUR_FP32_EXTRA if dom == "schur" and wbytes == 4.0 else 0.0)
 
 
 # HBM traffic per launch of the finest-level FP32 smoother class at 256^3 with
@@ -204,7 +213,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
     if dom == "rbgs_fine":
         total_bytes = cnt / float(launches_vc) * bytes_vc * N
     elif dom in BYTES_PER_CELL:
-        total_bytes = cnt * BYTES_PER_CELL[dom] * N
+        total_bytes = cnt * class_bytes_per_cell(dom, wbytes) * N
     else:
         total_bytes = None
     if total_bytes is not None and ms > 0:
