@@ -198,20 +198,20 @@ def pcg_fixed(op, b, ops, model, k, dtype=np.float64):
     return x
 
 
-def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=None):
-    """Flexible PCG on S s = b; stops at ||r||_2 <= max(rtol ||b||_2, atol).
-    With model.box_size > 0 and source `centres` ((i, j, k) cells), the
-    preconditioner follows the V-cycle by the source-subdomain correction: on
-    a box_size^3 box around every source, model.box_inner iterations of
+def preconditioner(op, model, centres=None, precond=True):
+    """z = P r for the symmetric 7-point operator op = (diag, cx, cy, cz):
+    the V-cycle on its hierarchy, followed (model.box_size > 0 with source
+    `centres`, (i, j, k) cells) by the source-subdomain correction: on a
+    box_size^3 box around every source, model.box_inner iterations of
     flexible PCG from zero for the operator restricted to the boxes, with its
     own box_levels-level V-cycle, applied to the residual the V-cycle left;
-    the boxes' parts are added box by box.
-    Returns (s, iterations, ||r||/||b||)."""
-    rtol = model.pcg_rtol if rtol is None else rtol
-    maxit = model.pcg_maxit if maxit is None else maxit
-    ops = hierarchy(op, model.mg_levels) if precond else None
+    the boxes' parts are added box by box."""
+    op = tuple(op[:4])
+    if not precond:
+        return lambda r: r.copy()
+    ops = hierarchy(op, model.mg_levels)
     dt = np.float32 if model.mg_fp32 else np.float64
-    boxes = (precond and model.box_size > 0 and centres is not None and len(centres) > 0)
+    boxes = model.box_size > 0 and centres is not None and len(centres) > 0
     if boxes:
         B = model.box_size
         bop = box_operator(op, centres, B)
@@ -221,8 +221,6 @@ def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=Non
         sels = [np.ix_(*box_cells(c, B, op[0].shape)) for c in centres]
 
     def V(r):
-        if not precond:
-            return r.copy()
         z = vcycle(r, ops, model, 0, dt).astype(np.float64)
         if boxes:
             res = r - apply_schur(z, *op)
@@ -231,7 +229,16 @@ def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=Non
             for s_, sel in enumerate(sels):
                 z[sel] += y[s_ * B:(s_ + 1) * B]
         return z
+    return V
 
+
+def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=None):
+    """Flexible PCG on S s = b for a symmetric operator op = (diag, cx, cy,
+    cz); stops at ||r||_2 <= max(rtol ||b||_2, atol).  The preconditioner is
+    preconditioner(op, ...).  Returns (s, iterations, ||r||/||b||)."""
+    rtol = model.pcg_rtol if rtol is None else rtol
+    maxit = model.pcg_maxit if maxit is None else maxit
+    V = preconditioner(op, model, centres, precond)
     x = np.zeros_like(b)
     bn = np.sqrt(np.sum(b * b))
     if bn == 0.0:
@@ -256,3 +263,103 @@ def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=Non
         rho = rho_new
         p = z + beta * p
     return x, maxit, rn / bn
+
+
+REORTH = 0.7071067811865476     # second Gram-Schmidt pass below this ratio
+
+
+def fgmres(op, pop, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=None,
+           restart=None):
+    """Flexible GMRES (right preconditioning, restarted every `restart`
+    iterations) on S s = b for the 7-point operator op = (diag, fx, fy, fz,
+    bx, by, bz), which need not be symmetric; the preconditioner is
+    preconditioner(pop, ...) for a symmetric operator pop = (diag, cx, cy,
+    cz) (the V-cycle, plus the subdomain correction).  Stops once the least-squares
+    residual ||b - S s||_2 <= max(rtol ||b||_2, atol), or after maxit
+    iterations (rtol = atol = 0: exactly maxit).
+
+    Arnoldi with classical Gram-Schmidt and one conditional second pass:
+    v_0 = r / ||r||, z_j = P v_j, w = S z_j, h_ij = w . v_i (i <= j),
+    w' = w - sum_i h_ij v_i; if ||w'|| < ||w|| / sqrt(2) (cancellation: the
+    criterion of Daniel, Gragg, Kaufman and Stewart) the projection is
+    repeated on w' and its coefficients added to h; h_{j+1,j} = ||w'||,
+    v_{j+1} = w' / h_{j+1,j}.  The Hessenberg columns are reduced by Givens
+    rotations, whose last sine gives the residual norm, and the update is
+    s += sum_j y_j z_j.  Returns (s, iterations, estimate / ||b||)."""
+    rtol = model.pcg_rtol if rtol is None else rtol
+    maxit = model.pcg_maxit if maxit is None else maxit
+    m = model.krylov_restart if restart is None else restart
+    P = preconditioner(pop, model, centres, precond)
+    x = np.zeros_like(b)
+    bn = np.sqrt(np.sum(b * b))
+    if bn == 0.0:
+        return x, 0, 0.0
+    tol = max(rtol * bn, atol)
+    its = 0
+    r = b.copy()
+    est = bn
+    while True:
+        beta = np.sqrt(np.sum(r * r))
+        if beta == 0.0:
+            return x, its, 0.0
+        V = [r / beta]
+        Z = []
+        Hc = []                       # rotated Hessenberg columns
+        cs, sn = [], []
+        g = [beta]
+        done = False
+        for j in range(m):
+            Z.append(P(V[j]))
+            w = apply_schur(Z[j], *op)
+            wn = np.sqrt(np.sum(w * w))
+            h = [float(np.sum(w * V[i])) for i in range(j + 1)]
+            for i in range(j + 1):
+                w = w - h[i] * V[i]
+            hn = np.sqrt(np.sum(w * w))
+            if hn < REORTH * wn:
+                h2 = [float(np.sum(w * V[i])) for i in range(j + 1)]
+                for i in range(j + 1):
+                    w = w - h2[i] * V[i]
+                    h[i] += h2[i]
+                hn = np.sqrt(np.sum(w * w))
+            h.append(hn)
+            V.append(w / hn if hn > 0.0 else w)
+            for i in range(j):
+                t = cs[i] * h[i] + sn[i] * h[i + 1]
+                h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1]
+                h[i] = t
+            den = np.sqrt(h[j] * h[j] + h[j + 1] * h[j + 1])
+            c_, s_ = (h[j] / den, h[j + 1] / den) if den > 0.0 else (1.0, 0.0)
+            cs.append(c_)
+            sn.append(s_)
+            h[j] = den
+            g.append(-s_ * g[j])
+            g[j] = c_ * g[j]
+            Hc.append(h[:j + 1])
+            its += 1
+            est = abs(g[j + 1])
+            if est <= tol or its >= maxit or hn == 0.0:
+                done = True
+                break
+        k = len(Hc)
+        y = [0.0] * k
+        for i in range(k - 1, -1, -1):
+            t = g[i]
+            for l in range(i + 1, k):
+                t -= Hc[l][i] * y[l]
+            y[i] = t / Hc[i][i] if Hc[i][i] != 0.0 else 0.0
+        for i in range(k):
+            x = x + y[i] * Z[i]
+        if done:
+            return x, its, est / bn
+        r = b - apply_schur(x, *op)
+
+
+def krylov(op, pop, b, model, **kw):
+    """The Schur solve of a Newton iteration: FGMRES (model.krylov_restart
+    > 0) on the operator op preconditioned through pop, or flexible PCG (0)
+    on pop itself, which is the whole operator only when the limiter does not
+    depend on E (constant D) and there are no species-opacity terms."""
+    if model.krylov_restart > 0:
+        return fgmres(op, pop, b, model, **kw)
+    return pcg(pop, b, model, **kw)

@@ -80,6 +80,7 @@ class Model:
     mg_coarse_sweeps: int = 8
     mg_fp32: int = 0
     pcg_forcing: float = 0.0 # inexact-Newton forcing factor (Sec. 3.2.1), 0: off
+    krylov_restart: int = 30 # Schur solve: FGMRES restart length; 0: flexible PCG
     box_size: int = 0        # source-subdomain correction in the preconditioner, 0: off
     box_levels: int = 3
     box_inner: int = 6
@@ -154,7 +155,8 @@ def model_from_workload(w, **overrides) -> Model:
               newton_maxit=w.newton_maxit, pcg_rtol=w.pcg_rtol,
               pcg_maxit=w.pcg_maxit, mg_levels=w.mg_levels, mg_pre=w.mg_pre,
               mg_post=w.mg_post, mg_coarse_sweeps=w.mg_coarse_sweeps,
-              mg_fp32=w.mg_fp32, pcg_forcing=w.pcg_forcing, box_size=w.box_size,
+              mg_fp32=w.mg_fp32, pcg_forcing=w.pcg_forcing,
+              krylov_restart=w.krylov_restart, box_size=w.box_size,
               box_levels=w.box_levels, box_inner=w.box_inner,
               box_coarse_sweeps=w.box_coarse_sweeps, lte=w.lte, kappa_lte=w.kappa_lte,
               kappaP_lte=w.kappaP_lte, mu_lte=w.mu_lte, boundary=w.boundary,

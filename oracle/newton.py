@@ -14,8 +14,16 @@ lambda = 1 and halve while the trial point leaves the physical bounds
 fails the sufficient-decrease test ||f(U_t)|| <= (1 - 1e-4 lambda) ||f(U_k)||;
 below lambda_min = 2^-10 the step fails.
 
-Two linear-solve modes: 'mgpcg' (the algorithm) and 'direct' (a sparse
+Two linear-solve modes: 'mgpcg' (the algorithm: MG-preconditioned FGMRES on
+the Schur system, or flexible PCG for a symmetric one) and 'direct' (a sparse
 direct solve of the Schur system: the definition of the Newton correction).
+
+Replay mode (replay=dict(its=[...], lambdas=[...])) executes a recorded
+schedule instead of taking the decisions: Newton iteration k runs exactly
+its[k] Krylov iterations and steps with lambda = lambdas[k], and the step
+takes len(its) Newton iterations.  A run of another implementation, whose
+stop tests may fall within rounding of their thresholds, can so be compared
+iterate for iterate.
 """
 from __future__ import annotations
 
@@ -57,17 +65,20 @@ def bounds_ok(U, eh, model):
 
 
 def schur_matrix(op):
-    """Sparse matrix of the 7-point periodic Schur operator."""
-    diag, cx, cy, cz = op
+    """Sparse matrix of the 7-point periodic operator (diag, fx, fy, fz
+    [, bx, by, bz]): row P couples to P + e_d with -f_d[P] and row P + e_d to
+    P with -b_d[P] (b omitted: b = f, symmetric)."""
+    diag, fs = op[0], op[1:4]
+    bs = op[4:7] if len(op) == 7 else fs
     shape = diag.shape
     N = diag.size
     cell = np.arange(N).reshape(shape)
     rows, cols, vals = [cell.ravel()], [cell.ravel()], [diag.ravel()]
-    for d, c in enumerate((cx, cy, cz)):
+    for d, (fw, bw) in enumerate(zip(fs, bs)):
         nbr = np.roll(cell, -1, axis=d).ravel()
         rows += [cell.ravel(), nbr]
         cols += [nbr, cell.ravel()]
-        vals += [-c.ravel(), -c.ravel()]
+        vals += [-fw.ravel(), -bw.ravel()]
     return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                          shape=(N, N))
 
@@ -78,43 +89,60 @@ def direct_solve(op, b):
 
 
 def newton_step(Un, U0, nH, eh, src_cells, src_Q, dt, cosmo, model,
-                linear="mgpcg", tol=None, tl=None):
-    """One implicit time step.  Returns (U^{n+1}, stats dict)."""
+                linear="mgpcg", tol=None, tl=None, replay=None, D=None):
+    """One implicit time step.  Returns (U^{n+1}, stats dict).  D: face
+    coefficients held fixed (a test device, see residual.residual)."""
     tol = model.newton_tol if tol is None else tol
     a, H = cosmo[2], cosmo[3]
     if tl is None:
         tl = residual.time_level(Un, nH, eh, src_cells, src_Q, dt, cosmo, model)
     scales = model.scales.reshape((-1, 1, 1, 1))
     U = U0.copy()
-    f = residual.residual(U, tl, nH, eh, dt, a, H, model)
+    f = residual.residual(U, tl, nH, eh, dt, a, H, model, D)
     fn = residual.rms(f)
     st = dict(status=OK, newton_its=0, cg_its=[], lambdas=[], fnorms=[fn])
     if not np.isfinite(fn):
         st["status"] = ENONFINITE
         return U, st
     k = 0
-    while fn >= tol and k < model.newton_maxit:
-        sch = jacobian.schur_form(U, f, tl["D"], nH, eh, dt, a, H, model)
-        op = (sch["diag"], sch["cx"], sch["cy"], sch["cz"])
+    nits = model.newton_maxit if replay is None else len(replay["its"])
+    while (fn >= tol or replay is not None) and k < nits:
+        sch = jacobian.schur_form(U, f, nH, eh, dt, a, H, model, D)
+        op = jacobian.operator(sch)
+        pop = jacobian.preconditioner_operator(sch)
+        centres = [np.unravel_index(int(c), U.shape[1:]) for c in src_cells]
         if linear == "direct":
             sE, its = direct_solve(op, sch["b"]), 0
+        elif replay is not None:
+            sE, its, _ = mg.krylov(op, pop, sch["b"], model, rtol=0.0,
+                                   maxit=int(replay["its"][k]), centres=centres)
         else:
             # inexact Newton (Sec. 3.2.1): with a forcing factor the linear
             # solve may also stop at ||J S + f|| <= forcing ||f(U_k)||; the
             # local rows are solved exactly, so ||J S + f||_2 is the Schur
             # residual norm, and ||f||_2 = sqrt(size) times the RMS norm
             atol = model.pcg_forcing * fn * np.sqrt(f.size)
-            centres = [np.unravel_index(int(c), U.shape[1:]) for c in src_cells]
-            sE, its, _ = mg.pcg(op, sch["b"], model, atol=atol, centres=centres)
+            sE, its, _ = mg.krylov(op, pop, sch["b"], model, atol=atol, centres=centres)
         step = jacobian.recover(sE, sch) * scales
         st["cg_its"].append(its)
+        if replay is not None:
+            lam = float(replay["lambdas"][k])
+            Ut = U + lam * step
+            if PROJECT:
+                Ut = project(Ut, eh, model)
+            ft = residual.residual(Ut, tl, nH, eh, dt, a, H, model, D)
+            U, f, fn = Ut, ft, residual.rms(ft)
+            st["lambdas"].append(lam)
+            st["fnorms"].append(fn)
+            k += 1
+            continue
         lam = 1.0
         while True:
             Ut = U + lam * step
             if PROJECT:
                 Ut = project(Ut, eh, model)
             if bounds_ok(Ut, eh, model):
-                ft = residual.residual(Ut, tl, nH, eh, dt, a, H, model)
+                ft = residual.residual(Ut, tl, nH, eh, dt, a, H, model, D)
                 ftn = residual.rms(ft)
                 if ftn <= (1.0 - ARMIJO * lam) * fn:
                     break

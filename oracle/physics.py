@@ -71,6 +71,18 @@ def opacity(U, nH, a, model):
     return k
 
 
+def opacity_derivatives(U, nH, a, model):
+    """d kappa / d x_s for every species fraction s (list, empty for LTE)."""
+    if model.lte:
+        return []
+    n_p = nH / a ** 3
+    K = model.K_kappa
+    out = [K[0] * n_p]
+    if model.nspecies == 3:
+        out += [model.y_he * n_p * K[1], model.y_he * n_p * K[2]]
+    return out
+
+
 def local_operators_lte(U, nH, eh, a, H, model):
     """LTE coupling (Sec. 2.1, Eq. 9): eta = kappa_P sigma_SB T^4 / pi,
     G = c kappa E / rho, Lambda = 4 pi eta / rho, with T from the ideal gas

@@ -3,13 +3,11 @@
   f(U) = U + dt theta [L_e; L_n; D_E + L_E](U) - g^n                (Eq. 29)
   g^n  = U^n + dt (theta - 1) [L_e; L_n; D_E + L_E](U^n)            (Eqs. 22-24)
 
-Flux limiter timing (a reading): the face diffusion coefficients D_f of
-Eq. 12 are evaluated once per time step from U^n (the limiter is lagged to
-the previous time level) and held fixed through the Newton iteration.  The
-paper lags the species dependence of D_E inside the Newton matrix (Sec.
-3.2.1); lagging the whole limiter makes the diffusion operator linear within
-the step, the Newton matrix exact, and its E-E block symmetric, as conjugate
-gradients require.
+D_E(U) is the flux-limited diffusion of Eq. 25 with the limiter of Eq. 12
+evaluated at the state it acts on: the face coefficients of f(U) come from
+E and the opacity (species fractions) of U itself, those of the explicit
+part of g^n from U^n.  (Only the Newton matrix approximates anything; the
+residual is the paper's.)
 
 The point-source emissivity 4 pi eta = Q <h nu> / dx^3 in the source cell
 (comoving) does not depend on U, so both theta-weighted copies of it are
@@ -35,9 +33,9 @@ def tendency(U, nH, eh, a, H, Dfaces, model):
     return L
 
 
-def lagged_limiter(Un, nH, a_old, model):
-    """Face coefficients D_f at time level n (held for the whole step)."""
-    return fld.face_coefficients(Un[-1], opacity(Un, nH, a_old, model), a_old, model)
+def limiter_at(U, nH, a, model):
+    """Face coefficients D_f of Eq. 12 evaluated at the state U."""
+    return fld.face_coefficients(U[-1], opacity(U, nH, a, model), a, model)
 
 
 def source_field(shape, src_cells, src_Q, model):
@@ -49,22 +47,26 @@ def source_field(shape, src_cells, src_Q, model):
 
 
 def time_level(Un, nH, eh, src_cells, src_Q, dt, cosmo, model):
-    """Time-level data of a step: dict(g=g^n incl. sources, D=lagged D_f).
+    """Time-level data of a step: dict(g=g^n incl. sources).
 
     cosmo = (a_old, H_old, a_new, H_new): the explicit part uses t^n values.
     """
     a_old, H_old = cosmo[0], cosmo[1]
-    D = lagged_limiter(Un, nH, a_old, model)
     g = Un.copy()
     if model.theta != 1.0:
+        D = limiter_at(Un, nH, a_old, model)
         g = g + dt * (model.theta - 1.0) * tendency(Un, nH, eh, a_old, H_old, D, model)
     g[-1] = g[-1] + dt * source_field(Un.shape[1:], src_cells, src_Q, model)
-    return dict(g=g, D=D)
+    return dict(g=g)
 
 
-def residual(U, tl, nH, eh, dt, a, H, model):
-    """Scaled residual f~ (same shape as U); tl from time_level()."""
-    f = U + dt * model.theta * tendency(U, nH, eh, a, H, tl["D"], model) - tl["g"]
+def residual(U, tl, nH, eh, dt, a, H, model, D=None):
+    """Scaled residual f~ (same shape as U); tl from time_level().  D: face
+    coefficients to hold fixed instead of the limiter at U (a test device:
+    with them the diffusion term is linear in E)."""
+    if D is None:
+        D = limiter_at(U, nH, a, model)
+    f = U + dt * model.theta * tendency(U, nH, eh, a, H, D, model) - tl["g"]
     return f / model.scales.reshape((-1, 1, 1, 1))
 
 

@@ -4,8 +4,8 @@ Eqs. 41-43; Sec. 3.2.4, Eq. 44).  Test infrastructure: plain NumPy FP64.
 Predictor (Eq. 44): the explicit Euler update of the coupled system from
 U^n, with the sign of the tendency read so that it is the forward Euler step
 of dU/dt = -[L_e; L_n; D_E + L_E](U) + [0; 0; 4 pi eta] (the paper's printed
-"+ dt L" would step backwards in time), the expansion factors and the lagged
-limiter at t^n as in the time level.  It is then projected onto the physical
+"+ dt L" would step backwards in time), the expansion factors and the
+limiter at t^n as in the explicit part of the time level.  It is then projected onto the physical
 bounds like a line-search trial point, and where the predicted gas energy
 e_h + e_c would not be positive e_c keeps its value at t^n (a reading).
 
@@ -26,7 +26,7 @@ from . import newton, residual
 def predictor(Un, nH, eh, src_cells, src_Q, dt, cosmo, model):
     """U^pred of Eq. 44 (projected); cosmo = (a_old, H_old, a_new, H_new)."""
     a_old, H_old = cosmo[0], cosmo[1]
-    D = residual.lagged_limiter(Un, nH, a_old, model)
+    D = residual.limiter_at(Un, nH, a_old, model)
     U = Un - dt * residual.tendency(Un, nH, eh, a_old, H_old, D, model)
     U[-1] = U[-1] + dt * residual.source_field(Un.shape[1:], src_cells, src_Q, model)
     U = newton.project(U, eh, model)

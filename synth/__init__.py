@@ -81,7 +81,8 @@ class Workload:
     newton_maxit: int = 20
     pcg_rtol: float = 1.0e-8
     pcg_maxit: int = 200
-    pcg_forcing: float = 0.0   # > 0: CG also stops at ||r|| <= pcg_forcing ||f(U_k)||
+    pcg_forcing: float = 0.0   # > 0: the Krylov solve also stops at ||r|| <= pcg_forcing ||f(U_k)||
+    krylov_restart: int = 30   # Schur solve: FGMRES restart length; 0: flexible PCG
     box_size: int = 0          # > 0: subdomain correction on a box around each source
     box_levels: int = 3
     box_inner: int = 6

@@ -18,16 +18,17 @@ from oracle import jacobian, mg, newton, residual
 from tests.test_oracle_dense_lu import CASES, case
 
 
-@pytest.mark.parametrize("ns,theta,a,seed", CASES[:3] + CASES[3:4])
+@pytest.mark.parametrize("ns,theta,a,seed", CASES[:2] + CASES[3:])
 def test_full_linear_residual_is_the_schur_residual(ns, theta, a, seed):
     m, U, nH, eh, tl, dt, a, H = case(ns, theta, a, seed)
     f = residual.residual(U, tl, nH, eh, dt, a, H, m)
-    J = jacobian.dense_jacobian(U, tl["D"], nH, eh, dt, a, H, m)
-    sch = jacobian.schur_form(U, f, tl["D"], nH, eh, dt, a, H, m)
-    op = (sch["diag"], sch["cx"], sch["cy"], sch["cz"])
+    J = jacobian.dense_jacobian(U, nH, eh, dt, a, H, m)
+    sch = jacobian.schur_form(U, f, nH, eh, dt, a, H, m)
+    op = jacobian.operator(sch)
     fnorm2 = np.linalg.norm(f)
     for forcing in (1e-2, 1e-4):
-        sE, its, _ = mg.pcg(op, sch["b"], m, rtol=0.0, maxit=200, atol=forcing * fnorm2)
+        sE, its, _ = mg.fgmres(op, jacobian.preconditioner_operator(sch), sch["b"], m,
+                               rtol=0.0, maxit=200, atol=forcing * fnorm2)
         S = jacobian.recover(sE, sch)
         full = J @ S.reshape(-1) + f.reshape(-1)
         schur_r = sch["b"] - jacobian.apply_schur(sE, *op)

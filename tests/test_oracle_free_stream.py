@@ -5,10 +5,13 @@ A transparent medium (opacity 1e-6 /cm) starts at E = 1e-4 erg/cm^3 and the
 x-left face holds E = 1 erg/cm^3.  Diffusion alone has no signal speed: with
 the limiter replaced by the constant coefficient that the same cells would
 have without a gradient (D = c / (3 kappa_f)), the profile is nearly flat
-across the 1 cm cube after 8.3391 ps.  With the limiter of Eq. 12 the front
-(E = 1/2) sits near c t = 0.25 cm, behind it by the lag the paper describes
-(its size set by the step and the mesh; here 16 cells and 50 steps), E stays
-below the boundary value, decreases along x and is uniform across y and z.
+across the 1 cm cube after 8.3391 ps.  With the limiter of Eq. 12 evaluated
+at every iterate (as the residual of Eq. 29 has it) the front (E = 1/2) sits
+near c t = 0.25 cm, behind it by less than one cell (measured 0.197 cm with
+16 cells whatever the step count from 25 to 200, 0.216 cm with 32 cells: the
+lag shrinks with the mesh, as the paper reports; a limiter held at the
+step's start lags to 0.175 cm here), E stays below the boundary value,
+decreases along x and is uniform across y and z.
 """
 import numpy as np
 import pytest
@@ -48,7 +51,7 @@ def test_limited_front_near_ct():
     ct = C_LIGHT * W.dt * W.steps
     assert ct == pytest.approx(0.25, rel=1e-4)
     xf, prof = front(E, W.n)
-    assert 0.15 < xf < ct + 0.01, xf
+    assert ct - W.dx < xf < ct + 0.01, xf
     assert E.max() <= W.E_dirichlet * (1 + 1e-12)
     assert np.all(np.diff(prof) <= 1e-12)
     assert np.ptp(E, axis=(1, 2)).max() <= 1e-9
