@@ -10,8 +10,11 @@
  * with one theta-scheme time step (Sec. 3.2, Eqs. 22-24) solved by a
  * globalised inexact Newton method (Sec. 3.2) whose linear systems are
  * reduced by a Schur complement to a scalar 7-point diffusion system
- * (Sec. 3.2.1, Eqs. 33-35) and solved by multigrid-preconditioned conjugate
- * gradients.
+ * (Sec. 3.2.1, Eqs. 33-35) and solved by a multigrid-preconditioned Krylov
+ * method.  The residual evaluates the flux limiter of Eq. 12 at the state it
+ * acts on (Eq. 29 with D_E(U)); the Newton matrix is its exact derivative,
+ * so the Schur matrix is not symmetric and the Krylov method is flexible
+ * GMRES, preconditioned by a V-cycle of a symmetric M-matrix built beside it.
  *
  * Conventions common to every entry point
  *   Grid     nx*ny*nz cells, periodic in every direction, cell (i,j,k) at
@@ -104,6 +107,20 @@ typedef struct rt_params {
                             /* ghost cell one width outside), the other faces   */
                             /* reflect                                          */
   double  E_dirichlet;      /* boundary 2: comoving E of the x-left ghost cell  */
+  int32_t krylov_restart;   /* Schur solve: 1..30 flexible GMRES restarted every */
+                            /* this many iterations (the Newton matrix is not    */
+                            /* symmetric); 0: flexible CG on the preconditioner's */
+                            /* symmetric operator, which is the Schur matrix only */
+                            /* for a constant diffusion coefficient (limiter_mode */
+                            /* 1).  The workspace holds 2 krylov_restart + 1     */
+                            /* extra FP64 fields                                  */
+  int32_t limiter_lag;      /* 0: the limiter of Eq. 12 evaluated at the state the */
+                            /* residual acts on (Eq. 29 as printed); 1: the face   */
+                            /* coefficients held at their time-level-n values for  */
+                            /* the whole step (the diffusion term is then linear   */
+                            /* in E and the Schur matrix symmetric); needs         */
+                            /* rt_time_level before rt_eval_residual and           */
+                            /* rt_schur_form                                       */
 } rt_params;
 
 /* Scale factor a and adot/a at t^n (old) and t^{n+1} (new). */
@@ -149,16 +166,17 @@ int rt_set_medium(rt_grid* g, const double* d_nH, const double* d_eh);
 int rt_set_sources(rt_grid* g, int32_t n, const int64_t* h_cells, const double* h_Q);
 
 /* Time-level setup (Sec. 3.2, Eqs. 22-24): writes d_gn [nv][N] =
- * U^n + dt (theta-1) [L_e; L_n; D_E + L_E](U^n) + dt [0; 0; 4 pi eta], and
- * stores in the workspace the flux-limiter face coefficients of Eq. 12
- * evaluated at U^n, which every later residual and Schur call of the step
- * uses (the limiter is lagged to time level n). */
+ * U^n + dt (theta-1) [L_e; L_n; D_E + L_E](U^n) + dt [0; 0; 4 pi eta], the
+ * explicit part (theta < 1) with the flux limiter of Eq. 12 at U^n.  With
+ * limiter_lag it also stores those face coefficients for the step. */
 int rt_time_level(rt_grid* g, const double* d_Un, double dt, const rt_cosmo* c,
                   double* d_gn);
 
 /* Nonlinear residual (Sec. 3.2, Eq. 29) in scaled variables f_v / u_v,
  * written to d_f [nv][N], and its RMS norm (Eq. 30) to *h_rms (may be NULL,
- * then nothing synchronises).  Uses the time-level coefficients. */
+ * then nothing synchronises).  D_E(U) of Eq. 25 takes the face coefficients
+ * of Eq. 12 from E and the species fractions of d_U itself (limiter_lag:
+ * the time-level coefficients). */
 int rt_eval_residual(rt_grid* g, const double* d_U, const double* d_gn, double dt,
                      const rt_cosmo* c, double* d_f, double* h_rms);
 
@@ -169,30 +187,48 @@ int rt_eval_residual(rt_grid* g, const double* d_U, const double* d_gn, double d
 int rt_local_jacobian(rt_grid* g, const double* d_U, double dt, const rt_cosmo* c,
                       double* d_M, double* d_Ucol, double* d_Lrow, double* d_dloc);
 
-/* Schur steps (i)-(ii) set-up (Sec. 3.2.1): per cell GEPP on M gives
- * f~_M = M^-1 f_M and W = M^-1 U; the Schur matrix S = D - L W (7-point,
- * symmetric) and right side d_b [N] = L f~_M - f_E.  f~_M, W and S stay in
- * the workspace for rt_mg_pcg_solve and the line search. */
+/* Schur steps (i)-(ii) set-up (Sec. 3.2.1) for the exact Newton matrix of
+ * the residual above: per cell GEPP on M gives f~_M = M^-1 f_M and
+ * W = M^-1 U; the Schur matrix S = D - L W, with D the derivative of the
+ * face fluxes of Eq. 25 with respect to E (through the gradient, R_f and
+ * E_f of Eq. 12) and the species fractions of both cells of each face
+ * (through the face opacity, folded in through W and f~_M, which keeps S
+ * 7-point), and the right side d_b [N] = L f~_M - f_E (plus the fractions'
+ * face terms).  S is not symmetric.  Beside it the preconditioner's
+ * symmetric M-matrix: the cell-local part of S plus, on every face, the
+ * derivative of the flux with respect to E_Q - E_P at fixed E_f and
+ * opacity (>= 0).  f~_M, W and both operators stay in the workspace for
+ * rt_mg_pcg_solve and the line search. */
 int rt_schur_form(rt_grid* g, const double* d_U, const double* d_f, double dt,
                   const rt_cosmo* c, double* d_b);
 
 /* Copies of the workspace Schur data (any pointer may be NULL):
- * f~_M [nb][N], W [nb][N], diag [N], and the +x/+y/+z face couplings [N]. */
+ * f~_M [nb][N], W [nb][N], the Schur diagonal [N], and the preconditioner
+ * operator's +x/+y/+z face couplings c [N] each. */
 int rt_schur_get(rt_grid* g, double* d_ftM, double* d_W, double* d_diag,
                  double* d_cx, double* d_cy, double* d_cz);
 
-/* Replace the workspace Schur matrix by a caller operator
- * (S x)_P = diag_P x_P - sum over faces c_f x_nbr (for solver tests). */
+/* Copies of the rest (any pointer may be NULL): the Schur matrix's face
+ * couplings fw = -S_{P,P+e_d} and bw = -S_{P+e_d,P} [3][N] (d = x, y, z
+ * major), so that (S x)_P = diag_P x_P - sum_d (fw_d[P] x_{P+e_d} +
+ * bw_d[P-e_d] x_{P-e_d}), and the preconditioner operator's diagonal [N]. */
+int rt_schur_get_full(rt_grid* g, double* d_fw, double* d_bw, double* d_pdiag);
+
+/* Replace the workspace Schur matrix by a caller's symmetric operator
+ * (S x)_P = diag_P x_P - sum over faces c_f x_nbr, which is then also the
+ * preconditioner's operator (for solver tests). */
 int rt_set_operator(rt_grid* g, const double* d_diag, const double* d_cx,
                     const double* d_cy, const double* d_cz);
 
 /* One application z = V r of the multigrid V-cycle preconditioner on the
- * current Schur matrix (red-black Gauss-Seidel, trilinear transfers, face-
- * averaged coarse operators). */
+ * preconditioner's operator (red-black Gauss-Seidel, trilinear transfers,
+ * face-averaged coarse operators). */
 int rt_mg_vcycle(rt_grid* g, const double* d_r, double* d_z);
 
-/* Solve S s = b by multigrid-preconditioned CG from s = 0 until
- * ||r||_2 <= rtol ||b||_2 or maxit iterations (rtol = 0: exactly maxit). */
+/* Solve S s = b from s = 0 by the multigrid-preconditioned Krylov method of
+ * krylov_restart (flexible GMRES, or CG for a symmetric operator) until
+ * ||r||_2 <= rtol ||b||_2 (GMRES: its least-squares estimate) or maxit
+ * iterations (rtol = 0: exactly maxit); *h_relres gets ||r||_2 / ||b||_2. */
 int rt_mg_pcg_solve(rt_grid* g, const double* d_b, double* d_sE, double rtol,
                     int32_t maxit, int32_t* h_iters, double* h_relres);
 
@@ -202,9 +238,8 @@ int rt_mg_pcg_solve(rt_grid* g, const double* d_b, double* d_sE, double rtol,
  * that it steps backwards; this is the forward step), expansion factors
  * a_old, H_old and the limiter at U^n, then projected onto the physical
  * bounds (fractions into [0, 1], the helium pair to a sum <= 1, E >= 0) with
- * e_c kept at its t^n value where e_h + e_c would not be positive.  Also
- * stores the lagged face coefficients, as rt_time_level does.  Meant as the
- * d_Ualt guess of rt_newton_step.  d_Upred must not be d_Un (RT_EINVAL). */
+ * e_c kept at its t^n value where e_h + e_c would not be positive.  Meant as
+ * the d_Ualt guess of rt_newton_step.  d_Upred must not be d_Un (RT_EINVAL). */
 int rt_predict(rt_grid* g, const double* d_Un, double dt, const rt_cosmo* c, double* d_Upred);
 
 /* Time-error estimate of Sec. 3.2.3 (Eqs. 41-42) between the new state and

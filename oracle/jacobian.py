@@ -180,12 +180,13 @@ def apply_schur(x, diag, cx, cy, cz, bx=None, by=None, bz=None):
     return y
 
 
-def dense_jacobian(U, nH, eh, dt, a, H, model):
+def dense_jacobian(U, nH, eh, dt, a, H, model, D=None):
     """Full scaled Newton matrix (nv*N, nv*N) for brute force on tiny grids:
     the local blocks, the E-E face-flux derivatives and the E-row couplings
     to the species fractions through the face opacities.
 
-    Unknown ordering: variable-major, (v, i, j, k) flattened.
+    Unknown ordering: variable-major, (v, i, j, k) flattened.  D: face
+    coefficients held fixed (the lagged reading), as in schur_form.
     """
     nv = model.nv
     ns = model.nspecies
@@ -200,7 +201,7 @@ def dense_jacobian(U, nH, eh, dt, a, H, model):
             J[i * N + idx, j * N + idx] = M[i, j].ravel()
         J[i * N + idx, nb * N + idx] = Ucol[i].ravel()
         J[nb * N + idx, i * N + idx] = Lrow[i].ravel()
-    dd, dkdx = diffusion_derivatives(U, nH, dt, a, model)
+    dd, dkdx = diffusion_derivatives(U, nH, dt, a, model, D)
     cell = idx.reshape(shape)
     base = nb * N
     J[base + idx, base + idx] += dloc.ravel()

@@ -81,6 +81,7 @@ class Model:
     mg_fp32: int = 0
     pcg_forcing: float = 0.0 # inexact-Newton forcing factor (Sec. 3.2.1), 0: off
     krylov_restart: int = 30 # Schur solve: FGMRES restart length; 0: flexible PCG
+    limiter_lag: int = 0     # 1: the flux limiter held at time level n for the step (a reading)
     box_size: int = 0        # source-subdomain correction in the preconditioner, 0: off
     box_levels: int = 3
     box_inner: int = 6
@@ -156,7 +157,8 @@ def model_from_workload(w, **overrides) -> Model:
               pcg_maxit=w.pcg_maxit, mg_levels=w.mg_levels, mg_pre=w.mg_pre,
               mg_post=w.mg_post, mg_coarse_sweeps=w.mg_coarse_sweeps,
               mg_fp32=w.mg_fp32, pcg_forcing=w.pcg_forcing,
-              krylov_restart=w.krylov_restart, box_size=w.box_size,
+              krylov_restart=w.krylov_restart, limiter_lag=w.limiter_lag,
+              box_size=w.box_size,
               box_levels=w.box_levels, box_inner=w.box_inner,
               box_coarse_sweeps=w.box_coarse_sweeps, lte=w.lte, kappa_lte=w.kappa_lte,
               kappaP_lte=w.kappaP_lte, mu_lte=w.mu_lte, boundary=w.boundary,

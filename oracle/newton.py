@@ -96,6 +96,8 @@ def newton_step(Un, U0, nH, eh, src_cells, src_Q, dt, cosmo, model,
     a, H = cosmo[2], cosmo[3]
     if tl is None:
         tl = residual.time_level(Un, nH, eh, src_cells, src_Q, dt, cosmo, model)
+    if D is None and "D" in tl:
+        D = tl["D"]          # the lagged-limiter reading
     scales = model.scales.reshape((-1, 1, 1, 1))
     U = U0.copy()
     f = residual.residual(U, tl, nH, eh, dt, a, H, model, D)

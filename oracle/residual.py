@@ -7,7 +7,10 @@ D_E(U) is the flux-limited diffusion of Eq. 25 with the limiter of Eq. 12
 evaluated at the state it acts on: the face coefficients of f(U) come from
 E and the opacity (species fractions) of U itself, those of the explicit
 part of g^n from U^n.  (Only the Newton matrix approximates anything; the
-residual is the paper's.)
+residual is the paper's.)  A second reading, model.limiter_lag = 1, holds
+the face coefficients at their U^n values for the whole step (the diffusion
+term is then linear in E within the step); it is not Eq. 29 as printed and
+serves where Newton on the printed residual does not converge.
 
 The point-source emissivity 4 pi eta = Q <h nu> / dx^3 in the source cell
 (comoving) does not depend on U, so both theta-weighted copies of it are
@@ -47,17 +50,20 @@ def source_field(shape, src_cells, src_Q, model):
 
 
 def time_level(Un, nH, eh, src_cells, src_Q, dt, cosmo, model):
-    """Time-level data of a step: dict(g=g^n incl. sources).
+    """Time-level data of a step: dict(g=g^n incl. sources), and with
+    model.limiter_lag the face coefficients at U^n for the whole step (D).
 
     cosmo = (a_old, H_old, a_new, H_new): the explicit part uses t^n values.
     """
     a_old, H_old = cosmo[0], cosmo[1]
     g = Un.copy()
-    if model.theta != 1.0:
+    D = None
+    if model.theta != 1.0 or model.limiter_lag:
         D = limiter_at(Un, nH, a_old, model)
+    if model.theta != 1.0:
         g = g + dt * (model.theta - 1.0) * tendency(Un, nH, eh, a_old, H_old, D, model)
     g[-1] = g[-1] + dt * source_field(Un.shape[1:], src_cells, src_Q, model)
-    return dict(g=g)
+    return dict(g=g, D=D) if model.limiter_lag else dict(g=g)
 
 
 def residual(U, tl, nH, eh, dt, a, H, model, D=None):
@@ -65,7 +71,7 @@ def residual(U, tl, nH, eh, dt, a, H, model, D=None):
     coefficients to hold fixed instead of the limiter at U (a test device:
     with them the diffusion term is linear in E)."""
     if D is None:
-        D = limiter_at(U, nH, a, model)
+        D = tl["D"] if "D" in tl else limiter_at(U, nH, a, model)
     f = U + dt * model.theta * tendency(U, nH, eh, a, H, D, model) - tl["g"]
     return f / model.scales.reshape((-1, 1, 1, 1))
 

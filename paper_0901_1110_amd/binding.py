@@ -40,7 +40,8 @@ class RtParams(ctypes.Structure):
         ("box_coarse_sweeps", ctypes.c_int32),
         ("lte", ctypes.c_int32), ("kappa_lte", ctypes.c_double), ("kappaP_lte", ctypes.c_double),
         ("mu_lte", ctypes.c_double), ("boundary", ctypes.c_int32),
-        ("E_dirichlet", ctypes.c_double),
+        ("E_dirichlet", ctypes.c_double), ("krylov_restart", ctypes.c_int32),
+        ("limiter_lag", ctypes.c_int32),
     ]
 
 
@@ -98,6 +99,7 @@ SIGNATURES = {
     "rt_local_jacobian": [_P, _P, _D, ctypes.POINTER(RtCosmo), _P, _P, _P, _P],
     "rt_schur_form": [_P, _P, _P, _D, ctypes.POINTER(RtCosmo), _P],
     "rt_schur_get": [_P, _P, _P, _P, _P, _P, _P],
+    "rt_schur_get_full": [_P, _P, _P, _P],
     "rt_set_operator": [_P, _P, _P, _P, _P],
     "rt_mg_vcycle": [_P, _P, _P],
     "rt_mg_pcg_solve": [_P, _P, _P, _D, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)],
@@ -201,6 +203,8 @@ def params_from_workload(w, **overrides) -> RtParams:
     p.box_coarse_sweeps = w.box_coarse_sweeps
     p.lte, p.kappa_lte, p.kappaP_lte, p.mu_lte = w.lte, w.kappa_lte, w.kappaP_lte, w.mu_lte
     p.boundary, p.E_dirichlet = w.boundary, w.E_dirichlet
+    p.krylov_restart = w.krylov_restart
+    p.limiter_lag = w.limiter_lag
     for k, v in overrides.items():
         if k in ("K_gamma", "K_kappa", "K_heat"):
             getattr(p, k)[:] = list(v)
@@ -331,6 +335,14 @@ class RtGrid:
         self._check(lib().rt_schur_get(self.h, _ptr(ftM), _ptr(W), *[_ptr(t) for t in out]),
                     "rt_schur_get")
         return dict(ftM=ftM, W=W, diag=out[0], cx=out[1], cy=out[2], cz=out[3])
+
+    def rt_schur_get_full(self):
+        fw = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        bw = torch.empty_like(fw)
+        pdiag = self.new_field()
+        self._check(lib().rt_schur_get_full(self.h, _ptr(fw), _ptr(bw), _ptr(pdiag)),
+                    "rt_schur_get_full")
+        return dict(fw=fw, bw=bw, pdiag=pdiag)
 
     def rt_set_operator(self, diag, cx, cy, cz):
         return self._check(lib().rt_set_operator(self.h, _ptr(diag), _ptr(cx), _ptr(cy), _ptr(cz)),

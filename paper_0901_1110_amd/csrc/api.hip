@@ -41,8 +41,16 @@ struct Carver {
 struct Workspace {
   double *D, *g, *f, *ft, *Ut;
   double *ftM, *W;
-  double *diag, *cx, *cy, *cz, *b;
+  // Schur matrix: diagonal and the two couplings of every +x/+y/+z face
+  // (fw = -S_{P,P+d}, bw = -S_{P+d,P}; 3N each, direction-major); the
+  // preconditioner's symmetric operator: pdiag and the face couplings c
+  // (cx, cy, cz point into one 3N block); right side b
+  double *diag, *fw, *bw, *pdiag, *cx, *cy, *cz, *b;
+  double *om, *ph;          // species columns coupled through the face opacity
   double *x, *r, *z, *p, *q;
+  // flexible GMRES: basis V (restart + 1 vectors), preconditioned vectors Z
+  // (restart), multi-component partials, device scalars
+  double *V = nullptr, *Z = nullptr, *gparts = nullptr, *gh = nullptr, *gy = nullptr;
   double *parts, *sc;
   long long* src_cells;
   double* src_Q;
@@ -78,7 +86,7 @@ struct rt_grid {
   const double* nH = nullptr;
   const double* eh = nullptr;
   int nsrc = 0;
-  bool have_tl = false;     // time-level face coefficients present
+  bool have_tl = false;     // lagged limiter: time-level face coefficients present
   bool mg_stale = true;     // coarse operators need rebuilding
   bool have_op = false;     // a Schur matrix is present
   bool l0_fp32 = false;     // the FP32 finest-level operator copy matches the FP64 one
@@ -192,6 +200,9 @@ int validate(const rt_params* p, std::string* why) {
   if (p->max_sources < 0) return bad("max_sources < 0");
   if (!(p->pcg_forcing >= 0.0) || !std::isfinite(p->pcg_forcing)) return bad("pcg_forcing must be finite and >= 0");
   if (p->limiter_mode != 0 && p->limiter_mode != 1) return bad("limiter_mode must be 0 or 1");
+  if (p->limiter_lag != 0 && p->limiter_lag != 1) return bad("limiter_lag must be 0 or 1");
+  if (p->krylov_restart < 0 || p->krylov_restart > KMAX - 2)
+    return bad("krylov_restart out of range (0: PCG, 1..30: FGMRES restart length)");
   if (p->box_size < 0) return bad("box_size < 0");
   if (p->box_size > 0) {
     if (p->box_levels < 1 || p->box_levels > 12 || p->box_inner < 1 || p->box_coarse_sweeps < 0)
@@ -223,10 +234,15 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
   w->ftM = c.take<double>(nb * N);
   w->W = c.take<double>(nb * N);
   w->diag = c.take<double>(N);
-  w->cx = c.take<double>(N);
-  w->cy = c.take<double>(N);
-  w->cz = c.take<double>(N);
+  w->fw = c.take<double>(3 * N);
+  w->bw = c.take<double>(3 * N);
+  w->pdiag = c.take<double>(N);
+  w->cx = c.take<double>(3 * N);
+  w->cy = w->cx ? w->cx + N : nullptr;
+  w->cz = w->cx ? w->cx + 2 * N : nullptr;
   w->b = c.take<double>(N);
+  w->om = c.take<double>(N);
+  w->ph = c.take<double>(N);
   w->x = c.take<double>(N);
   w->r = c.take<double>(N);
   w->z = c.take<double>(N);
@@ -240,6 +256,13 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
     w->parts = c.take<double>(w->nparts_cap * NCOMP_MAX);
   }
   w->sc = c.take<double>(32);
+  if (p->krylov_restart > 0) {
+    w->V = c.take<double>((size_t)(p->krylov_restart + 1) * N);
+    w->Z = c.take<double>((size_t)p->krylov_restart * N);
+  }
+  w->gparts = c.take<double>((size_t)KMAX * MAX_PARTS);
+  w->gh = c.take<double>(3 * KMAX);
+  w->gy = c.take<double>(KMAX);
   w->src_cells = c.take<long long>(p->max_sources > 0 ? p->max_sources : 1);
   w->src_Q = c.take<double>(p->max_sources > 0 ? p->max_sources : 1);
   w->L64.clear();
@@ -251,7 +274,8 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
     if (!p->mg_fp32) {
       Level<double> L{nx, ny, nz};
       if (l == 0) {
-        L.diag = w->diag; L.cx = w->cx; L.cy = w->cy; L.cz = w->cz;
+        // the V-cycle is built on the preconditioner's operator
+        L.diag = w->pdiag; L.cx = w->cx; L.cy = w->cy; L.cz = w->cz;
         L.x = nullptr; L.b = nullptr;          // bound per application
         L.r = c.take<double>(n);
       } else {
@@ -407,7 +431,7 @@ int build_hierarchy(rt_grid* g) {
   } else {
     Level<float>& L0 = w.L32[0];
     if (!g->l0_fp32) {
-      TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.diag, L0.diag, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.pdiag, L0.diag, g->st));
       TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cx, L0.cx, g->st));
       TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cy, L0.cy, g->st));
       TK(g, RT_K_MG_SETUP, launch_cvt_d2f_level(L0, w.cz, L0.cz, g->st));
@@ -420,7 +444,7 @@ int build_hierarchy(rt_grid* g) {
     const int B = g->prm.box_size;
     const long nb3 = (long)g->nbox * B * B * B;
     TK(g, RT_K_MG_SETUP, launch_box_extract(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells,
-                                            w.diag, w.cx, w.cy, w.cz, w.bd, w.bcx, w.bcy, w.bcz,
+                                            w.pdiag, w.cx, w.cy, w.cz, w.bd, w.bcx, w.bcy, w.bcz,
                                             g->st));
     if (!g->prm.mg_fp32) {
       for (size_t l = 1; l < w.B64.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<double>(w.B64[l - 1], w.B64[l], g->st));
@@ -500,7 +524,7 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
   T* bp = reinterpret_cast<T*>(w.bp);
   T* bq = reinterpret_cast<T*>(w.bq);
   g->tk_override = RT_K_BOX;
-  TK(g, RT_K_BOX, launch_box_residual<T>(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, w.diag,
+  TK(g, RT_K_BOX, launch_box_residual<T>(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, w.pdiag,
                                          w.cx, w.cy, w.cz, r, z, br, st));
   TK(g, RT_K_BOX, launch_fill<T>(n, x, T(0), st));
   L0.b = br;   // the box V-cycle maps r -> z in place
@@ -645,7 +669,8 @@ void finish_reduce(rt_grid* g, int n_items_blocks, int ncomp, int slot) {
   TK(g, RT_K_REDUCE, launch_final_reduce(g->w.parts, n_items_blocks, ncomp, g->w.sc + slot, g->st));
 }
 
-// PCG on the workspace Schur matrix: solve S x = b (x in w.x)
+// PCG on the preconditioner's operator (pdiag, c): solves S x = b when S is
+// that symmetric operator (constant limiter D0, no species opacity terms)
 // stops at ||r||_2 <= max(rtol ||b||_2, atol)
 int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int maxit, int* iters,
         double* relres, int* vcycles) {
@@ -694,7 +719,7 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   int k = 0;
   for (k = 1; k <= maxit; ++k) {
     const double pred = k > 1 ? rn * (rn / rn_prev) : (g->cg_rate1 > 0.0 ? bn * g->cg_rate1 : HUGE_VAL);
-    TK(g, RT_K_SPMV, launch_spmv_dot(g->P.nx, g->P.ny, g->P.nz, w.diag, w.cx, w.cy, w.cz, w.p, w.q, w.parts, g->st));
+    TK(g, RT_K_SPMV, launch_spmv_dot(g->P.nx, g->P.ny, g->P.nz, w.pdiag, w.cx, w.cy, w.cz, w.p, w.q, w.parts, g->st));
     TK(g, RT_K_REDUCE, launch_final_reduce_alpha(w.parts, stencil_blocks(g->P.nx, g->P.ny, g->P.nz),
                                                  w.sc, g->st));
     if (fp32_fused(&g->prm)) {
@@ -724,9 +749,158 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   return RT_OK;
 }
 
+constexpr double REORTH = 0.7071067811865476;   // second Gram-Schmidt pass below this ratio
+
+// Flexible GMRES(m) on the workspace Schur operator (diag, fw, bw), right-
+// preconditioned by apply_precond (the V-cycle of the preconditioner's
+// operator plus the subdomain correction), from x = 0.  Classical
+// Gram-Schmidt in one fused pass (the product forms the dots), a second pass
+// where the first cancelled (DGKS: ||w'|| < ||w|| / sqrt 2), Givens
+// rotations on the host; stops once the least-squares residual
+// <= max(rtol ||b||_2, atol), after maxit iterations in all (rtol = atol = 0:
+// exactly maxit), restarting every m.  The host reads j + 2 scalars per
+// iteration (one more after a second pass).
+int fgmres(rt_grid* g, const double* b, double* x, double rtol, double atol, int maxit,
+           int* iters, double* relres, int* vcycles) {
+  Workspace& w = g->w;
+  const DevParams& P = g->P;
+  const long N = P.N;
+  const int m = g->prm.krylov_restart;
+  const int nparts = reduce_blocks(N);
+  RTCHK(build_hierarchy(g));
+  double* hp = g->hpin;
+  TK(g, RT_K_CG_VECTOR, launch_dot1(N, b, b, w.parts, g->st));
+  finish_reduce(g, nparts, 1, S_BB);
+  RTCHK(read_scalars(g, w.sc + S_BB, hp, 1));
+  const double bn = std::sqrt(hp[0]);
+  const double thr = std::max(rtol * bn, atol);
+  TK(g, RT_K_CG_VECTOR, launch_fill<double>(N, x, 0.0, g->st));
+  *iters = 0;
+  *relres = 0.0;
+  if (!(bn > 0.0)) {
+    if (!std::isfinite(bn)) return fail(g, RT_ENONFINITE, "non-finite Schur right side");
+    HIPCHK(g, hipGetLastError());
+    return RT_OK;
+  }
+  // with the subdomain correction the preconditioner runs on fixed buffers
+  // (its captured graph is bound to them): the normalisation copies v_j to
+  // w.r, the product copies w.z to z_j
+  const bool fixed = g->nbox > 0;
+  float* r32 = fp32_fused(&g->prm) ? w.L32[0].b : nullptr;
+  auto normalise = [&](double* v, double sf) {
+    TK(g, RT_K_CG_VECTOR, launch_scale(N, v, sf, fixed ? w.r : nullptr, r32, P.ny, P.nz, g->st));
+    g->r32_of = r32 ? (fixed ? w.r : v) : nullptr;
+  };
+  std::vector<double> H((size_t)m * (m + 1)), cs(m), sn(m), gv(m + 1), y(m);
+  int its = 0;
+  double est = bn;
+  bool first = true;
+  while (true) {
+    double beta;
+    if (first) {
+      beta = bn;
+      HIPCHK(g, hipMemcpyAsync(w.V, b, N * sizeof(double), hipMemcpyDeviceToDevice, g->st));
+    } else {
+      int nb = 0;
+      TK(g, RT_K_SPMV, nb = launch_spmv_full(P.nx, P.ny, P.nz, w.diag, w.fw, w.bw, x, b, w.V,
+                                             nullptr, w.V, 0, w.gparts, g->st));
+      TK(g, RT_K_REDUCE, launch_final_multi(w.gparts, nb, 1, w.gh, g->st));
+      RTCHK(read_scalars(g, w.gh, hp, 1));
+      beta = std::sqrt(hp[0]);
+      if (!std::isfinite(beta)) return fail(g, RT_ENONFINITE, "non-finite FGMRES residual");
+      if (!(beta > 0.0)) { est = 0.0; break; }
+    }
+    normalise(w.V, 1.0 / beta);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    bool done = false;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = w.V + (size_t)j * N;
+      double* vn = w.V + (size_t)(j + 1) * N;
+      double* zj = w.Z + (size_t)j * N;
+      int nd = 0;
+      RTCHK(apply_precond(g, fixed ? w.r : vj, fixed ? w.z : zj, false, &nd));
+      ++*vcycles;
+      int nb = 0;
+      TK(g, RT_K_SPMV, nb = launch_spmv_full(P.nx, P.ny, P.nz, w.diag, w.fw, w.bw,
+                                             fixed ? w.z : zj, nullptr, vn, fixed ? zj : nullptr,
+                                             w.V, j + 1, w.gparts, g->st));
+      TK(g, RT_K_REDUCE, launch_final_multi(w.gparts, nb, j + 2, w.gh, g->st));
+      TK(g, RT_K_CG_VECTOR, nb = launch_gs_pass(N, vn, w.V, j + 1, w.gh, 1, w.gparts, g->st));
+      TK(g, RT_K_REDUCE, launch_final_multi(w.gparts, nb, j + 2, w.gh + KMAX, g->st));
+      HIPCHK(g, hipMemcpyAsync(hp, w.gh, 2 * KMAX * sizeof(double), hipMemcpyDeviceToHost, g->st));
+      HIPCHK(g, hipStreamSynchronize(g->st));
+      double* h = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i <= j; ++i) h[i] = hp[i];
+      const double wn = std::sqrt(hp[j + 1]);
+      double hn = std::sqrt(hp[KMAX + j + 1]);
+      if (hn < REORTH * wn) {
+        for (int i = 0; i <= j; ++i) h[i] += hp[KMAX + i];
+        TK(g, RT_K_CG_VECTOR, nb = launch_gs_pass(N, vn, w.V, j + 1, w.gh + KMAX, 0, w.gparts, g->st));
+        TK(g, RT_K_REDUCE, launch_final_multi(w.gparts, nb, 1, w.gh + 2 * KMAX, g->st));
+        RTCHK(read_scalars(g, w.gh + 2 * KMAX, hp, 1));
+        hn = std::sqrt(hp[0]);
+      }
+      if (!std::isfinite(hn)) return fail(g, RT_ENONFINITE, "non-finite FGMRES basis vector");
+      h[j + 1] = hn;
+      if (hn > 0.0) normalise(vn, 1.0 / hn);
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+      }
+      const double den = std::sqrt(h[j] * h[j] + h[j + 1] * h[j + 1]);
+      cs[j] = den > 0.0 ? h[j] / den : 1.0;
+      sn[j] = den > 0.0 ? h[j + 1] / den : 0.0;
+      h[j] = den;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      ++its;
+      k = j + 1;
+      est = std::fabs(gv[j + 1]);
+      if (est <= thr || its >= maxit || hn == 0.0) {
+        done = true;
+        break;
+      }
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double t = gv[i];
+      for (int l = i + 1; l < k; ++l) t -= H[(size_t)l * (m + 1) + i] * y[l];
+      const double d = H[(size_t)i * (m + 1) + i];
+      y[i] = d != 0.0 ? t / d : 0.0;
+    }
+    for (int i = 0; i < k; ++i) hp[i] = y[i];
+    HIPCHK(g, hipMemcpyAsync(w.gy, hp, k * sizeof(double), hipMemcpyHostToDevice, g->st));
+    TK(g, RT_K_CG_VECTOR, launch_combine(N, x, w.Z, k, w.gy, g->st));
+    // the host buffer is reused by the next read-back: the copy must be done
+    HIPCHK(g, hipStreamSynchronize(g->st));
+    if (done) break;
+    first = false;
+  }
+  *iters = its;
+  *relres = est / bn;
+  HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+// the Schur solve: FGMRES on the full operator, or (krylov_restart = 0) PCG
+// on the symmetric preconditioner operator
+int krylov(rt_grid* g, const double* b, double* x, double rtol, double atol, int maxit, int* iters,
+           double* relres, int* vcycles) {
+  if (g->prm.krylov_restart > 0) return fgmres(g, b, x, rtol, atol, maxit, iters, relres, vcycles);
+  return pcg(g, b, x, rtol, atol, maxit, iters, relres, vcycles);
+}
+
+// face coefficients of the lagged-limiter reading (null: the limiter at the iterate)
+const double* lagged_D(const rt_grid* g) { return g->prm.limiter_lag ? g->w.D : nullptr; }
+
 int time_level(rt_grid* g, const double* Un, double dt, const rt_cosmo* c, double* gn) {
   const DevParams& P = g->P;
-  TK(g, RT_K_TIMELEVEL, launch_faces(P, Un, g->nH, c->a_old, g->w.D, g->st));
+  // the limiter at U^n: for the explicit part, and for the whole step with
+  // the lagged reading
+  if (P.theta != 1.0 || g->prm.limiter_lag)
+    TK(g, RT_K_TIMELEVEL, launch_faces(P, Un, g->nH, c->a_old, g->w.D, g->st));
   if (P.theta != 1.0) {
     TK(g, RT_K_TIMELEVEL, launch_explicit(P, Un, g->nH, g->eh, g->w.D, Step{dt, c->a_old, c->H_old}, gn, g->st));
   } else {
@@ -744,7 +918,7 @@ int time_level(rt_grid* g, const double* Un, double dt, const rt_cosmo* c, doubl
 int residual_norm(rt_grid* g, const double* U, const double* gn, Step s, double* f, double* fn,
                   double* viol) {
   const DevParams& P = g->P;
-  TK(g, RT_K_RESIDUAL, launch_residual(P, U, gn, g->nH, g->eh, g->w.D, s, f, g->w.parts, g->st));
+  TK(g, RT_K_RESIDUAL, launch_residual(P, U, gn, g->nH, g->eh, lagged_D(g), s, f, g->w.parts, g->st));
   finish_reduce(g, stencil_blocks(P.nx, P.ny, P.nz), 2, S_FN);
   double h[2];
   RTCHK(read_scalars(g, g->w.sc + S_FN, h, 2));
@@ -753,22 +927,26 @@ int residual_norm(rt_grid* g, const double* U, const double* gn, Step s, double*
   return RT_OK;
 }
 
-int check_ready(rt_grid* g, bool need_tl) {
+int check_ready(rt_grid* g, bool need_tl = false) {
   if (!g) return RT_EINVAL;
   if (!g->nH || !g->eh) return fail(g, RT_EINVAL, "rt_set_medium has not been called");
-  if (need_tl && !g->have_tl) return fail(g, RT_EINVAL, "rt_time_level has not been called");
+  if (need_tl && g->prm.limiter_lag && !g->have_tl)
+    return fail(g, RT_EINVAL, "limiter_lag: rt_time_level has not been called");
   return RT_OK;
 }
 
-// Schur assembly into the workspace operator; with the colour-split FP32
-// finest level the kernel also writes that level's operator copy
+// Schur assembly into the workspace operator (the local blocks, then the
+// face terms); with the colour-split FP32 finest level the face kernel also
+// writes that level's copy of the preconditioner's operator
 void schur_into_workspace(rt_grid* g, const double* U, const double* f, Step s, double* b) {
   Workspace& w = g->w;
   const bool f32 = g->prm.mg_fp32 && !w.L32.empty() && w.L32[0].split;
   Level<float>* L0 = f32 ? &w.L32[0] : nullptr;
-  launch_schur(g->P, U, f, g->nH, g->eh, w.D, s, w.ftM, w.W, w.diag, w.cx, w.cy, w.cz, b,
-               f32 ? L0->diag : nullptr, f32 ? L0->cx : nullptr, f32 ? L0->cy : nullptr,
-               f32 ? L0->cz : nullptr, g->st);
+  launch_schur_local(g->P, U, f, g->nH, g->eh, s, w.ftM, w.W, w.diag, b, w.om, w.ph, g->st);
+  launch_schur_faces(g->P, U, g->nH, lagged_D(g), s, w.diag, w.om, w.ph, w.diag, w.pdiag, w.cx,
+                     w.fw, w.bw, b,
+                     f32 ? L0->diag : nullptr, f32 ? L0->cx : nullptr, f32 ? L0->cy : nullptr,
+                     f32 ? L0->cz : nullptr, g->st);
   g->l0_fp32 = f32;
   g->mg_stale = true;
   g->have_op = true;
@@ -822,7 +1000,8 @@ int rt_create_grid(const rt_params* p, void* d_ws, uint64_t ws_bytes, void* hip_
   P.alpha0[0] = 2.59e-13;                            // case-B HII at 1e4 K
   P.alpha0[1] = 2.72e-13;                            // HeII (placeholder datum)
   P.alpha0[2] = 2.0 * 2.59e-13 * std::pow(4.0, 0.7); // HeIII, hydrogenic Z = 2
-  if (hipHostMalloc(reinterpret_cast<void**>(&g->hpin), 4 * sizeof(double), hipHostMallocDefault) !=
+  if (hipHostMalloc(reinterpret_cast<void**>(&g->hpin), 3 * KMAX * sizeof(double),
+                    hipHostMallocDefault) !=
           hipSuccess ||
       hipEventCreateWithFlags(&g->ev_rd, hipEventDisableTiming) != hipSuccess) {
     if (g->hpin) (void)hipHostFree(g->hpin);
@@ -879,13 +1058,13 @@ int rt_set_sources(rt_grid* g, int32_t n, const int64_t* h_cells, const double* 
 }
 
 int rt_time_level(rt_grid* g, const double* d_Un, double dt, const rt_cosmo* c, double* d_gn) {
-  RTCHK(check_ready(g, false));
+  RTCHK(check_ready(g));
   if (!d_Un || !d_gn || !c) return fail(g, RT_EINVAL, "null argument");
   return time_level(g, d_Un, dt, c, d_gn);
 }
 
 int rt_predict(rt_grid* g, const double* d_Un, double dt, const rt_cosmo* c, double* d_Upred) {
-  RTCHK(check_ready(g, false));
+  RTCHK(check_ready(g));
   if (!d_Un || !d_Upred || !c) return fail(g, RT_EINVAL, "null argument");
   if (d_Upred == d_Un) return fail(g, RT_EINVAL, "d_Upred must not be d_Un");
   const DevParams& P = g->P;
@@ -925,7 +1104,8 @@ int rt_eval_residual(rt_grid* g, const double* d_U, const double* d_gn, double d
     double viol;
     RTCHK(residual_norm(g, d_U, d_gn, step_new(dt, c), d_f, h_rms, &viol));
   } else {
-    launch_residual(g->P, d_U, d_gn, g->nH, g->eh, g->w.D, step_new(dt, c), d_f, g->w.parts, g->st);
+    launch_residual(g->P, d_U, d_gn, g->nH, g->eh, lagged_D(g), step_new(dt, c), d_f, g->w.parts,
+                    g->st);
   }
   HIPCHK(g, hipGetLastError());
   return RT_OK;
@@ -933,7 +1113,7 @@ int rt_eval_residual(rt_grid* g, const double* d_U, const double* d_gn, double d
 
 int rt_local_jacobian(rt_grid* g, const double* d_U, double dt, const rt_cosmo* c, double* d_M,
                       double* d_Ucol, double* d_Lrow, double* d_dloc) {
-  RTCHK(check_ready(g, false));
+  RTCHK(check_ready(g));
   if (!d_U || !d_M || !d_Ucol || !d_Lrow || !d_dloc || !c)
     return fail(g, RT_EINVAL, "null argument");
   launch_local_jac(g->P, d_U, g->nH, g->eh, step_new(dt, c), d_M, d_Ucol, d_Lrow, d_dloc, g->st);
@@ -969,16 +1149,32 @@ int rt_schur_get(rt_grid* g, double* d_ftM, double* d_W, double* d_diag, double*
   return RT_OK;
 }
 
+int rt_schur_get_full(rt_grid* g, double* d_fw, double* d_bw, double* d_pdiag) {
+  if (!g) return RT_EINVAL;
+  if (!g->have_op) return fail(g, RT_EINVAL, "no Schur matrix yet");
+  const size_t N = g->P.N;
+  Workspace& w = g->w;
+  if (d_fw) HIPCHK(g, hipMemcpyAsync(d_fw, w.fw, 3 * N * 8, hipMemcpyDeviceToDevice, g->st));
+  if (d_bw) HIPCHK(g, hipMemcpyAsync(d_bw, w.bw, 3 * N * 8, hipMemcpyDeviceToDevice, g->st));
+  if (d_pdiag) HIPCHK(g, hipMemcpyAsync(d_pdiag, w.pdiag, N * 8, hipMemcpyDeviceToDevice, g->st));
+  return RT_OK;
+}
+
 int rt_set_operator(rt_grid* g, const double* d_diag, const double* d_cx, const double* d_cy,
                     const double* d_cz) {
   if (!g) return RT_EINVAL;
   if (!d_diag || !d_cx || !d_cy || !d_cz) return fail(g, RT_EINVAL, "null operator array");
   const size_t N = g->P.N;
   Workspace& w = g->w;
+  // a symmetric operator: the Schur matrix and the preconditioner's are the same
   HIPCHK(g, hipMemcpyAsync(w.diag, d_diag, N * 8, hipMemcpyDeviceToDevice, g->st));
-  HIPCHK(g, hipMemcpyAsync(w.cx, d_cx, N * 8, hipMemcpyDeviceToDevice, g->st));
-  HIPCHK(g, hipMemcpyAsync(w.cy, d_cy, N * 8, hipMemcpyDeviceToDevice, g->st));
-  HIPCHK(g, hipMemcpyAsync(w.cz, d_cz, N * 8, hipMemcpyDeviceToDevice, g->st));
+  HIPCHK(g, hipMemcpyAsync(w.pdiag, d_diag, N * 8, hipMemcpyDeviceToDevice, g->st));
+  const double* cs[3] = {d_cx, d_cy, d_cz};
+  for (int d = 0; d < 3; ++d) {
+    HIPCHK(g, hipMemcpyAsync(w.cx + d * N, cs[d], N * 8, hipMemcpyDeviceToDevice, g->st));
+    HIPCHK(g, hipMemcpyAsync(w.fw + d * N, cs[d], N * 8, hipMemcpyDeviceToDevice, g->st));
+    HIPCHK(g, hipMemcpyAsync(w.bw + d * N, cs[d], N * 8, hipMemcpyDeviceToDevice, g->st));
+  }
   g->mg_stale = true;
   g->l0_fp32 = false;
   g->have_op = true;
@@ -1002,7 +1198,7 @@ int rt_mg_pcg_solve(rt_grid* g, const double* d_b, double* d_sE, double rtol, in
   if (!d_b || !d_sE || maxit < 0 || !(rtol >= 0)) return fail(g, RT_EINVAL, "bad argument");
   int its = 0, vc = 0;
   double rr = 0;
-  RTCHK(pcg(g, d_b, d_sE, rtol, 0.0, maxit, &its, &rr, &vc));
+  RTCHK(krylov(g, d_b, d_sE, rtol, 0.0, maxit, &its, &rr, &vc));
   if (h_iters) *h_iters = its;
   if (h_relres) *h_relres = rr;
   return RT_OK;
@@ -1010,7 +1206,7 @@ int rt_mg_pcg_solve(rt_grid* g, const double* d_b, double* d_sE, double rtol, in
 
 int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_Ualt, double dt,
                    const rt_cosmo* c, rt_newton_stats* h_stats) {
-  RTCHK(check_ready(g, false));
+  RTCHK(check_ready(g));
   if (!d_Un || !d_U || !c || !(dt > 0)) return fail(g, RT_EINVAL, "bad argument");
   rt_newton_stats st;
   std::memset(&st, 0, sizeof st);
@@ -1055,7 +1251,7 @@ int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_
     // ||J S + f||_2 equals the Schur residual norm (the local rows are solved
     // exactly), and ||f||_2 = sqrt(N nv) times the RMS norm
     const double atol = g->prm.pcg_forcing * fn * std::sqrt((double)P.N * P.nv);
-    status = pcg(g, w.b, w.x, g->prm.pcg_rtol, atol, g->prm.pcg_maxit, &its, &rr, &vc);
+    status = krylov(g, w.b, w.x, g->prm.pcg_rtol, atol, g->prm.pcg_maxit, &its, &rr, &vc);
     if (status != RT_OK) break;
     st.cg_its[k] = its;
     st.cg_its_total += its;

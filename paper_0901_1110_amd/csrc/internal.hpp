@@ -11,6 +11,7 @@ namespace rtk {
 constexpr int BLOCK = 256;          // threads per block (4 wave64)
 constexpr int MAX_PARTS = 2048;     // partial sums per reduction
 constexpr int NCOMP_MAX = 4;        // components per reduction
+constexpr int KMAX = 32;            // components of the FGMRES reductions (restart <= KMAX - 2)
 
 // Number of blocks a reduction kernel over n items uses (fixed per n, so the
 // summation tree, and therefore the result, is deterministic).
@@ -34,8 +35,10 @@ void launch_explicit(const DevParams& P, const double* Un, const double* nH, con
                      const double* D, Step s, double* g, hipStream_t st);
 void launch_sources(const long long* cells, const double* Q, int n, double scale, double* gE,
                     hipStream_t st);
+// residual with the flux limiter evaluated at U, or (Dlag non-null) with the
+// face coefficients stored at time level n
 void launch_residual(const DevParams& P, const double* U, const double* g, const double* nH,
-                     const double* eh, const double* D, Step s, double* f, double* parts,
+                     const double* eh, const double* Dlag, Step s, double* f, double* parts,
                      hipStream_t st);
 // explicit predictor: projection of U^n - dt L(U^n) + sources (already in Up)
 void launch_predict_project(const DevParams& P, const double* Un, const double* eh, double* Up,
@@ -49,10 +52,30 @@ void launch_trial(const DevParams& P, const double* U, const double* ftM, const 
 void launch_local_jac(const DevParams& P, const double* U, const double* nH, const double* eh,
                       Step s, double* M, double* Ucol, double* Lrow, double* dloc,
                       hipStream_t st);
-void launch_schur(const DevParams& P, const double* U, const double* f, const double* nH,
-                  const double* eh, const double* D, Step s, double* ftM, double* W,
-                  double* diag, double* cx, double* cy, double* cz, double* b, float* d32,
-                  float* cx32, float* cy32, float* cz32, hipStream_t st);
+// Schur step (i) and the local part of (ii): ftM, W, loc (local diagonal), b
+// (local right side), om, ph (species columns coupled through the opacity)
+void launch_schur_local(const DevParams& P, const double* U, const double* f, const double* nH,
+                        const double* eh, Step s, double* ftM, double* W, double* loc, double* b,
+                        double* om, double* ph, hipStream_t st);
+// the face terms: diag, the preconditioner's pdiag and couplings c (3N),
+// the full operator's couplings fw, bw (3N each), b completed; pd32..cz32
+// non-null: FP32 colour-split copies of pdiag and c
+// (Dlag non-null: the lagged face coefficients, a symmetric S)
+void launch_schur_faces(const DevParams& P, const double* U, const double* nH, const double* Dlag,
+                        Step s, const double* loc, const double* om, const double* ph,
+                        double* diag, double* pdiag, double* c, double* fw, double* bw, double* b,
+                        float* pd32, float* cx32, float* cy32, float* cz32, hipStream_t st);
+
+// ---- flexible GMRES kernels (FP64); the reductions return their block count ----
+int launch_spmv_full(int nx, int ny, int nz, const double* diag, const double* fw,
+                     const double* bw, const double* z, const double* bsub, double* w,
+                     double* zcopy, const double* V, int nvec, double* parts, hipStream_t st);
+int launch_gs_pass(long N, double* w, const double* V, int nvec, const double* coef, int dots,
+                   double* parts, hipStream_t st);
+void launch_scale(long N, double* v, double sf, double* copy, float* r32, int ny, int nz,
+                  hipStream_t st);
+void launch_combine(long N, double* x, const double* Z, int nvec, const double* y, hipStream_t st);
+void launch_final_multi(const double* parts, int nblk, int ncomp, double* out, hipStream_t st);
 
 // ---- reductions / scalars ----
 void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out,

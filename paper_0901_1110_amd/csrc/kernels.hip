@@ -172,14 +172,67 @@ __global__ void k_sources(const long long* __restrict__ cells, const double* __r
 }
 
 // ---------------------------------------------------------------------------
+// live face fluxes: the limiter of Eq. 12 evaluated at the state U itself
+
+// proper opacity of cell q of the state U
+template <int NS>
+__device__ inline double opacity_of(const double* __restrict__ U, const double* __restrict__ nH,
+                                    int N, int q, double a, const DevParams& P) {
+  double x[NS > 0 ? NS : 1];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) x[s] = U[(1 + s) * N + q];
+  return opacity<NS>(x, nH[q], a, P);
+}
+
+// sum over the three directions of F_{P+} - F_{P-}, F = D_f (E_Q - E_P) with
+// D_f from E and the opacities of the face's two cells.  Non-periodic grids
+// carry no flux through the domain faces, except the x-left Dirichlet face
+// (bc 2), whose ghost cell holds E_dirichlet with the first cell's opacity.
+// A face is evaluated by both of its cells with the same arguments in the
+// same order, so both see the same value.
+template <int NS>
+__device__ inline double live_flux_sum(const double* __restrict__ U, const double* __restrict__ nH,
+                                       int N, int idx, const Nb& nb, int i, int j, int k,
+                                       double a, const DevParams& P) {
+  const double* E = U + (NS + 1) * N;
+  const double EP = E[idx];
+  const double kP = opacity_of<NS>(U, nH, N, idx, a, P);
+  const int np_[3] = {nb.xp, nb.yp, nb.zp};
+  const int nm_[3] = {nb.xm, nb.ym, nb.zm};
+  const bool last[3] = {i == P.nx - 1, j == P.ny - 1, k == P.nz - 1};
+  const bool first[3] = {i == 0, j == 0, k == 0};
+  double acc = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double Fp = 0.0, Fm = 0.0;
+    if (!(P.bc != 0 && last[d])) {
+      const int q = np_[d];
+      const double EQ = E[q];
+      Fp = face_D(EP, EQ, kP, opacity_of<NS>(U, nH, N, q, a, P), a, P) * (EQ - EP);
+    }
+    if (!(P.bc != 0 && first[d])) {
+      const int r = nm_[d];
+      const double ER = E[r];
+      Fm = face_D(ER, EP, opacity_of<NS>(U, nH, N, r, a, P), kP, a, P) * (EP - ER);
+    } else if (P.bc == 2 && d == 0) {
+      Fm = face_D(P.Eb, EP, kP, kP, a, P) * (EP - P.Eb);
+    }
+    acc += Fp - Fm;
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
 // residual f~ = (U + dt theta [L; D_E + L_E](U) - g) / u  and sum f~^2,
-// count of cells with e_h + e_c <= 0
+// count of cells with e_h + e_c <= 0; D_E(U) with the limiter at U
+// Dlag non-null: the face coefficients held at time level n (the lagged
+// limiter reading) instead of the limiter at U
 template <int NS>
 __global__ __launch_bounds__(BLOCK) void k_residual(DevParams P, const double* __restrict__ U,
                                                      const double* __restrict__ g,
                                                      const double* __restrict__ nH,
                                                      const double* __restrict__ eh,
-                                                     const double* __restrict__ D, Step s,
+                                                     const double* __restrict__ Dlag, Step s,
                                                      double* __restrict__ f,
                                                      double* __restrict__ parts) {
   constexpr int NV = NS + 2;
@@ -196,7 +249,9 @@ __global__ __launch_bounds__(BLOCK) void k_residual(DevParams P, const double* _
     const double ehv = eh[idx];
     local_ops<NS, double>(u, nH[idx], ehv, s.a, s.H, P, L);
     const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
-    const double dif = diffusion_sum(U + (NS + 1) * N, D, N, idx, nb, u[NS + 1], c.i, P);
+    const double dif =
+        Dlag ? diffusion_sum(U + (NS + 1) * N, Dlag, N, idx, nb, u[NS + 1], c.i, P)
+             : live_flux_sum<NS>(U, nH, N, idx, nb, c.i, c.j, c.k, s.a, P);
     L[NS + 1] += -dif * inv_a2dx2;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -442,34 +497,31 @@ __device__ inline void gepp2(double (&A)[NB][NB], double (&B)[NB][2]) {
   }
 }
 
-// Schur steps (i)-(ii): f~_M, W = M^-1 [f_M, U]; S = D - L W; b = L f~_M - f_E
+// Schur step (i) per cell and the cell-local part of step (ii):
+// f~_M, W = M^-1 [f_M, U] (GEPP); loc = 1 + dt theta dL_E/dE - L W;
+// b = L f~_M - f_E; om = sum_s dkappa/dx_s W_s and ph = sum_s dkappa/dx_s f~_s
+// (the species columns that the face opacities couple to the E rows)
 template <int NS>
-__global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __restrict__ U,
-                                                  const double* __restrict__ f,
-                                                  const double* __restrict__ nH,
-                                                  const double* __restrict__ eh,
-                                                  const double* __restrict__ D, Step s,
-                                                  double* __restrict__ ftM,
-                                                  double* __restrict__ Wo,
-                                                  double* __restrict__ diag,
-                                                  double* __restrict__ cx,
-                                                  double* __restrict__ cy,
-                                                  double* __restrict__ cz,
-                                                  double* __restrict__ b,
-                                                  float* __restrict__ d32,
-                                                  float* __restrict__ cx32,
-                                                  float* __restrict__ cy32,
-                                                  float* __restrict__ cz32) {
+__global__ __launch_bounds__(BLOCK) void k_schur_local(DevParams P, const double* __restrict__ U,
+                                                        const double* __restrict__ f,
+                                                        const double* __restrict__ nH,
+                                                        const double* __restrict__ eh, Step s,
+                                                        double* __restrict__ ftM,
+                                                        double* __restrict__ Wo,
+                                                        double* __restrict__ loc,
+                                                        double* __restrict__ b,
+                                                        double* __restrict__ om,
+                                                        double* __restrict__ ph) {
   constexpr int NB = NS + 1;
   const int N = P.N;
-  const C3 c = coord3(P.ny, P.nz);
-  if (!c.ok) return;
-  const int idx = (c.i * P.ny + c.j) * P.nz + c.k;
+  const int idx = blockIdx.x * BLOCK + threadIdx.x;
+  if (idx >= N) return;
   double u[NS + 2];
 #pragma unroll
   for (int v = 0; v < NS + 2; ++v) u[v] = U[v * N + idx];
+  const double nHv = nH[idx];
   double M[NB][NB], Uc[NB], Lr[NB], dloc;
-  local_blocks<NS>(P, u, nH[idx], eh[idx], s, M, Uc, Lr, dloc);
+  local_blocks<NS>(P, u, nHv, eh[idx], s, M, Uc, Lr, dloc);
   double B[NB][2];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -477,14 +529,6 @@ __global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __re
     B[i][1] = Uc[i];
   }
   gepp2<NB>(M, B);
-  const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
-  const double cf = s.dt * P.theta / (s.a * s.a * P.dx * P.dx);
-  // with the x-left Dirichlet face the last cell has no +x coupling, and the
-  // first cell's -x face (to the fixed ghost value) enters its diagonal only
-  const double cxp = (P.bc == 2 && c.i == P.nx - 1) ? 0.0 : cf * D[idx], cxm = cf * D[nb.xm];
-  const double cyp = cf * D[N + idx], cym = cf * D[N + nb.ym];
-  const double czp = cf * D[2 * N + idx], czm = cf * D[2 * N + nb.zm];
-  const double csum = ((cxp + cxm) + (cyp + cym)) + (czp + czm);
   double lw = 0.0, lf = 0.0;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -493,21 +537,124 @@ __global__ __launch_bounds__(BLOCK) void k_schur(DevParams P, const double* __re
     ftM[i * N + idx] = B[i][0];
     Wo[i * N + idx] = B[i][1];
   }
-  const double dg = (dloc + csum) - lw;
-  diag[idx] = dg;
-  cx[idx] = cxp;
-  cy[idx] = cyp;
-  cz[idx] = czp;
+  loc[idx] = dloc - lw;
   b[idx] = lf - f[NB * N + idx];
-  if (d32) {
+  double dk[NS > 0 ? NS : 1];
+  opacity_derivs<NS>(nHv, s.a, P, dk);
+  double o = 0.0, p = 0.0;
+#pragma unroll
+  for (int sp = 0; sp < NS; ++sp) {
+    o += dk[sp] * B[1 + sp][1];
+    p += dk[sp] * B[1 + sp][0];
+  }
+  om[idx] = o;
+  ph[idx] = p;
+}
+
+// Schur step (ii), the face terms: for every face (P, Q = P + e_d) with
+// k = dt theta / (a^2 dx^2) and kk = k dF/dkappa_f / (2 u_E) (each cell's
+// share of the face opacity),
+//   fw = k dF/dE_Q - kk om_Q  (= -S_{P,Q}),  bw = -k dF/dE_P + kk om_P (= -S_{Q,P}),
+//   diag_P += bw, diag_Q += fw, b_P -= kk (ph_P + ph_Q), b_Q += kk (ph_P + ph_Q),
+// and for the preconditioner's operator c = k (D + T) >= 0 with
+// pdiag = loc + the six c.  Each thread forms the + faces of its cell
+// (stored) and the - faces (the same expressions as the neighbour's + face).
+// The x-left Dirichlet face (bc 2) adds its Q terms to the first cell.
+// loc and b arrive from k_schur_local; diag, pdiag, b leave complete.
+// Dlag non-null (lagged limiter): the flux is D_f (E_Q - E_P) with the stored
+// coefficients, so dF/dE_Q = -dF/dE_P = D + T = D_f and nothing depends on
+// the opacity: S is symmetric and equals the preconditioner's operator.
+__device__ inline FaceJac lagged_jac(double D) {
+  FaceJac J;
+  J.D = D; J.DT = D; J.dEP = -D; J.dEQ = D; J.dk = 0.0;
+  return J;
+}
+template <int NS>
+__global__ __launch_bounds__(BLOCK) void k_schur_faces(DevParams P, const double* __restrict__ U,
+                                                        const double* __restrict__ nH,
+                                                        const double* __restrict__ Dlag, Step s,
+                                                        const double* __restrict__ loc,
+                                                        const double* __restrict__ om,
+                                                        const double* __restrict__ ph,
+                                                        double* __restrict__ diag,
+                                                        double* __restrict__ pdiag,
+                                                        double* __restrict__ cf,
+                                                        double* __restrict__ fw,
+                                                        double* __restrict__ bw,
+                                                        double* __restrict__ b,
+                                                        float* __restrict__ pd32,
+                                                        float* __restrict__ cx32,
+                                                        float* __restrict__ cy32,
+                                                        float* __restrict__ cz32) {
+  const int N = P.N;
+  const C3 c = coord3(P.ny, P.nz);
+  if (!c.ok) return;
+  const int idx = (c.i * P.ny + c.j) * P.nz + c.k;
+  const Nb nb = nbrs(c.i, c.j, c.k, P.nx, P.ny, P.nz);
+  const double a = s.a;
+  const double kf = s.dt * P.theta / (a * a * P.dx * P.dx);
+  const double kq = 0.5 * kf / P.u_E;
+  const double* E = U + (NS + 1) * N;
+  const double EP = E[idx];
+  const double kP = opacity_of<NS>(U, nH, N, idx, a, P);
+  const double omP = om[idx], phP = ph[idx];
+  const int np_[3] = {nb.xp, nb.yp, nb.zp};
+  const int nm_[3] = {nb.xm, nb.ym, nb.zm};
+  const bool last[3] = {c.i == P.nx - 1, c.j == P.ny - 1, c.k == P.nz - 1};
+  const bool first[3] = {c.i == 0, c.j == 0, c.k == 0};
+  const double lc = loc[idx];
+  double dg = lc, pd = lc, bb = b[idx];
+  double cst[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (P.bc == 2 && d == 0 && first[0]) {
+      // the ghost face: Q terms only, full opacity derivative
+      const FaceJac J = Dlag ? lagged_jac(Dlag[nb.xm]) : face_jac(P.Eb, EP, kP, kP, a, P, false);
+      dg += kf * J.dEQ - (2.0 * kq) * J.dk * omP;
+      pd += kf * J.DT;
+      bb += (2.0 * kq) * J.dk * phP;
+    }
+    double f_ = 0.0, b_ = 0.0, c_ = 0.0;
+    if (!(P.bc != 0 && last[d])) {
+      const int q = np_[d];
+      const FaceJac J = Dlag ? lagged_jac(Dlag[d * N + idx])
+                             : face_jac(EP, E[q], kP, opacity_of<NS>(U, nH, N, q, a, P), a, P);
+      const double kk = kq * J.dk;
+      f_ = kf * J.dEQ - kk * om[q];
+      b_ = -kf * J.dEP + kk * omP;
+      c_ = kf * J.DT;
+      bb -= kk * (phP + ph[q]);
+    }
+    double fm = 0.0, cm = 0.0, flm = 0.0;
+    if (!(P.bc != 0 && first[d])) {
+      const int r = nm_[d];
+      const FaceJac J = Dlag ? lagged_jac(Dlag[d * N + r])
+                             : face_jac(E[r], EP, opacity_of<NS>(U, nH, N, r, a, P), kP, a, P);
+      const double kk = kq * J.dk;
+      fm = kf * J.dEQ - kk * omP;
+      cm = kf * J.DT;
+      flm = kk * (ph[r] + phP);
+    }
+    dg = (dg + b_) + fm;
+    pd = (pd + c_) + cm;
+    bb += flm;
+    fw[d * N + idx] = f_;
+    bw[d * N + idx] = b_;
+    cf[d * N + idx] = c_;
+    cst[d] = c_;
+  }
+  diag[idx] = dg;
+  pdiag[idx] = pd;
+  b[idx] = bb;
+  if (pd32) {
     // FP32 copy for the finest V-cycle level, colour-split: the cells of one
     // colour of a row first, k = 2m + ((k + i + j) & 1) at place
     // ((k + i + j) & 1) nz/2 + m
     const int sidx = (c.i * P.ny + c.j) * P.nz + ((c.k + c.i + c.j) & 1) * (P.nz >> 1) + (c.k >> 1);
-    d32[sidx] = (float)dg;
-    cx32[sidx] = (float)cxp;
-    cy32[sidx] = (float)cyp;
-    cz32[sidx] = (float)czp;
+    pd32[sidx] = (float)pd;
+    cx32[sidx] = (float)cst[0];
+    cy32[sidx] = (float)cst[1];
+    cz32[sidx] = (float)cst[2];
   }
 }
 
@@ -642,6 +789,172 @@ __global__ __launch_bounds__(BLOCK) void k_update_p(long n, double* __restrict__
   const double beta = sc[S_BETA];
   const long i = blockIdx.x * (long)BLOCK + threadIdx.x;
   if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+// ---------------------------------------------------------------------------
+// flexible GMRES on the full (non-symmetric) Schur operator.  Reductions with
+// up to KMAX components: grid-stride kernels with a fixed block count
+// (reduce_blocks), partials laid out [component][block], one final-reduce
+// workgroup per component (fixed order: deterministic).
+
+// block partials of nc <= KMAX values (slot c of parts: c * nblk + block)
+__device__ inline void block_reduce_multi(double (&v)[KMAX], int nc, double* __restrict__ parts,
+                                          int nblk) {
+  __shared__ double sh[BLOCK / 64][KMAX];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) {
+    if (c < nc) {
+      double x = v[c];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      if (lane == 0) sh[w][c] = x;
+    }
+  }
+  __syncthreads();
+  if (tid < nc) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) t += sh[i][tid];
+    parts[(size_t)tid * nblk + blockIdx.x] = t;
+  }
+}
+
+// (i, j, k) of flat cell index n on an nx x ny x nz grid
+__device__ inline void cell_ijk(long n, int ny, int nz, int& i, int& j, int& k) {
+  const long row = n / nz;
+  k = (int)(n - row * nz);
+  i = (int)(row / ny);
+  j = (int)(row - (long)i * ny);
+}
+
+// w = S z (bsub null) or w = bsub - S z for the full 7-point operator
+// (S x)_P = diag_P x_P - sum_d [fw_d[P] x_{P+d} + bw_d[P-d] x_{P-d}];
+// zcopy non-null: also zcopy = z.  Partials of w.V_i (i < nvec, V_i at
+// V + i N) and of w.w (component nvec).
+__global__ __launch_bounds__(BLOCK) void k_spmv_full(int nx, int ny, int nz,
+                                                      const double* __restrict__ diag,
+                                                      const double* __restrict__ fw,
+                                                      const double* __restrict__ bw,
+                                                      const double* __restrict__ z,
+                                                      const double* __restrict__ bsub,
+                                                      double* __restrict__ w,
+                                                      double* __restrict__ zcopy,
+                                                      const double* __restrict__ V, int nvec,
+                                                      double* __restrict__ parts, int nblk) {
+  const long N = (long)nx * ny * nz;
+  double acc[KMAX];
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
+  for (long n = blockIdx.x * (long)BLOCK + threadIdx.x; n < N; n += (long)gridDim.x * BLOCK) {
+    int i, j, k;
+    cell_ijk(n, ny, nz, i, j, k);
+    const Nb nb = nbrs(i, j, k, nx, ny, nz);
+    const int idx = (int)n;
+    const double zv = z[idx];
+    double y = diag[idx] * zv;
+    y = y - fw[idx] * z[nb.xp] - bw[nb.xm] * z[nb.xm];
+    y = y - fw[N + idx] * z[nb.yp] - bw[N + nb.ym] * z[nb.ym];
+    y = y - fw[2 * N + idx] * z[nb.zp] - bw[2 * N + nb.zm] * z[nb.zm];
+    if (bsub) y = bsub[idx] - y;
+    w[idx] = y;
+    if (zcopy) zcopy[idx] = zv;
+#pragma unroll
+    for (int c = 0; c < KMAX - 1; ++c)
+      if (c < nvec) acc[c] += y * V[(size_t)c * N + idx];
+    double yy = y * y;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c)
+      if (c == nvec) acc[c] += yy;
+  }
+  block_reduce_multi(acc, nvec + 1, parts, nblk);
+}
+
+// Gram-Schmidt pass: w -= sum_{i < nvec} coef[i] V_i (coef on the device);
+// partials of w.V_i (dots set) and of w.w (component nvec, or 0 without dots)
+__global__ __launch_bounds__(BLOCK) void k_gs_pass(long N, double* __restrict__ w,
+                                                    const double* __restrict__ V, int nvec,
+                                                    const double* __restrict__ coef, int dots,
+                                                    double* __restrict__ parts, int nblk) {
+  __shared__ double cs[KMAX];
+  if (threadIdx.x < nvec) cs[threadIdx.x] = coef[threadIdx.x];
+  __syncthreads();
+  double acc[KMAX];
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
+  const int nn = dots ? nvec : 0;
+  for (long n = blockIdx.x * (long)BLOCK + threadIdx.x; n < N; n += (long)gridDim.x * BLOCK) {
+    double y = w[n];
+    double vv[KMAX - 1];
+#pragma unroll
+    for (int c = 0; c < KMAX - 1; ++c) {
+      if (c < nvec) {
+        vv[c] = V[(size_t)c * N + n];
+        y -= cs[c] * vv[c];
+      }
+    }
+    w[n] = y;
+#pragma unroll
+    for (int c = 0; c < KMAX - 1; ++c)
+      if (c < nn) acc[c] += y * vv[c];
+    double yy = y * y;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c)
+      if (c == nn) acc[c] += yy;
+  }
+  block_reduce_multi(acc, nn + 1, parts, nblk);
+}
+
+// v *= s; copy non-null: copy = v (after scaling); r32 non-null: the FP32
+// copy in the colour-split layout of the FP32 cycle's finest level
+__global__ __launch_bounds__(BLOCK) void k_scale(long N, double* __restrict__ v, double sf,
+                                                  double* __restrict__ copy,
+                                                  float* __restrict__ r32, int ny, int nz) {
+  for (long n = blockIdx.x * (long)BLOCK + threadIdx.x; n < N; n += (long)gridDim.x * BLOCK) {
+    const double y = v[n] * sf;
+    v[n] = y;
+    if (copy) copy[n] = y;
+    if (r32) {
+      const long row = n / nz;
+      const int k = (int)(n - row * nz);
+      const int j = (int)(row % ny), ii = (int)(row / ny);
+      r32[row * nz + ((k + ii + j) & 1) * (nz >> 1) + (k >> 1)] = (float)y;
+    }
+  }
+}
+
+// x += sum_{i < nvec} y[i] Z_i (y on the device)
+__global__ __launch_bounds__(BLOCK) void k_combine(long N, double* __restrict__ x,
+                                                    const double* __restrict__ Z, int nvec,
+                                                    const double* __restrict__ y) {
+  __shared__ double ys[KMAX];
+  if (threadIdx.x < nvec) ys[threadIdx.x] = y[threadIdx.x];
+  __syncthreads();
+  for (long n = blockIdx.x * (long)BLOCK + threadIdx.x; n < N; n += (long)gridDim.x * BLOCK) {
+    double t = x[n];
+    for (int c = 0; c < nvec; ++c) t += ys[c] * Z[(size_t)c * N + n];
+    x[n] = t;
+  }
+}
+
+// out[c] = sum over the blocks of parts[c * nblk + block]; one workgroup per
+// component, fixed order
+__global__ __launch_bounds__(1024) void k_final_multi(const double* __restrict__ parts, int nblk,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[1024 / 64];
+  const int c = blockIdx.x;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 1024) a += parts[(size_t)c * nblk + i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 1024 / 64; ++w) t += sh[w];
+    out[c] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1331,10 +1644,10 @@ void launch_sources(const long long* cells, const double* Q, int n, double scale
 }
 
 void launch_residual(const DevParams& P, const double* U, const double* g, const double* nH,
-                     const double* eh, const double* D, Step s, double* f, double* parts,
+                     const double* eh, const double* Dlag, Step s, double* f, double* parts,
                      hipStream_t st) {
   const Geo q = geo3(P.nx, P.ny, P.nz);
-  RT_NS(P, k_residual, q.g, q.b, 0, st, P, U, g, nH, eh, D, s, f, parts);
+  RT_NS(P, k_residual, q.g, q.b, 0, st, P, U, g, nH, eh, Dlag, s, f, parts);
 }
 
 void launch_predict_project(const DevParams& P, const double* Un, const double* eh, double* Up,
@@ -1359,15 +1672,6 @@ void launch_local_jac(const DevParams& P, const double* U, const double* nH, con
                       Step s, double* M, double* Ucol, double* Lrow, double* dloc,
                       hipStream_t st) {
   RT_NS(P, k_local_jac, grid_for(P.N), dim3(BLOCK), 0, st, P, U, nH, eh, s, M, Ucol, Lrow, dloc);
-}
-
-void launch_schur(const DevParams& P, const double* U, const double* f, const double* nH,
-                  const double* eh, const double* D, Step s, double* ftM, double* W, double* diag,
-                  double* cx, double* cy, double* cz, double* b, float* d32, float* cx32,
-                  float* cy32, float* cz32, hipStream_t st) {
-  const Geo q = geo3(P.nx, P.ny, P.nz);
-  RT_NS(P, k_schur, q.g, q.b, 0, st, P, U, f, nH, eh, D, s, ftM, W, diag, cx, cy, cz, b, d32, cx32,
-        cy32, cz32);
 }
 
 void launch_final_reduce(const double* parts, int nparts, int ncomp, double* out, hipStream_t st) {
@@ -1405,6 +1709,48 @@ void launch_dot1(long n, const double* a, const double* b, double* parts, hipStr
 }
 void launch_update_p(long n, double* p, const double* z, const double* sc, hipStream_t st) {
   hipLaunchKernelGGL(k_update_p, grid_for(n), dim3(BLOCK), 0, st, n, p, z, sc);
+}
+
+void launch_schur_local(const DevParams& P, const double* U, const double* f, const double* nH,
+                        const double* eh, Step s, double* ftM, double* W, double* loc, double* b,
+                        double* om, double* ph, hipStream_t st) {
+  RT_NS(P, k_schur_local, grid_for(P.N), dim3(BLOCK), 0, st, P, U, f, nH, eh, s, ftM, W, loc, b,
+        om, ph);
+}
+void launch_schur_faces(const DevParams& P, const double* U, const double* nH, const double* Dlag,
+                        Step s, const double* loc, const double* om, const double* ph,
+                        double* diag, double* pdiag, double* c, double* fw, double* bw, double* b,
+                        float* pd32, float* cx32, float* cy32, float* cz32, hipStream_t st) {
+  const Geo q = geo3(P.nx, P.ny, P.nz);
+  RT_NS(P, k_schur_faces, q.g, q.b, 0, st, P, U, nH, Dlag, s, loc, om, ph, diag, pdiag, c, fw, bw,
+        b, pd32, cx32, cy32, cz32);
+}
+int launch_spmv_full(int nx, int ny, int nz, const double* diag, const double* fw,
+                     const double* bw, const double* z, const double* bsub, double* w,
+                     double* zcopy, const double* V, int nvec, double* parts, hipStream_t st) {
+  const long N = (long)nx * ny * nz;
+  const int nb = reduce_blocks(N);
+  hipLaunchKernelGGL(k_spmv_full, dim3(nb), dim3(BLOCK), 0, st, nx, ny, nz, diag, fw, bw, z, bsub,
+                     w, zcopy, V, nvec, parts, nb);
+  return nb;
+}
+int launch_gs_pass(long N, double* w, const double* V, int nvec, const double* coef, int dots,
+                   double* parts, hipStream_t st) {
+  const int nb = reduce_blocks(N);
+  hipLaunchKernelGGL(k_gs_pass, dim3(nb), dim3(BLOCK), 0, st, N, w, V, nvec, coef, dots, parts, nb);
+  return nb;
+}
+void launch_scale(long N, double* v, double sf, double* copy, float* r32, int ny, int nz,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_scale, dim3(reduce_blocks(N)), dim3(BLOCK), 0, st, N, v, sf, copy, r32, ny,
+                     nz);
+}
+void launch_combine(long N, double* x, const double* Z, int nvec, const double* y,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_combine, dim3(reduce_blocks(N)), dim3(BLOCK), 0, st, N, x, Z, nvec, y);
+}
+void launch_final_multi(const double* parts, int nblk, int ncomp, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_final_multi, dim3(ncomp), dim3(1024), 0, st, parts, nblk, out);
 }
 
 template <class T>

@@ -221,4 +221,59 @@ __device__ inline double face_D(double EP, double EQ, double kP, double kQ, doub
   return limiter(kf, R);
 }
 
+// Face flux F = D_f (E_Q - E_P) and its derivatives for the exact Newton
+// matrix: with T = R dD/dR = -c R^2 (4 kappa + R) / P^2 (P the limiter's
+// denominator),
+//   dF/dE_Q =  D + T - (E_Q - E_P) T / (2 E_f),
+//   dF/dE_P = -D - T - (E_Q - E_P) T / (2 E_f),
+//   dF/dkappa_f = (E_Q - E_P) dD/dkappa, dD/dkappa = -c (12 kappa^2 +
+//   12 kappa R + R^2) / P^2 (zero where the opacity floor binds);
+// DT = D + T is the derivative with respect to E_Q - E_P at fixed E_f and
+// kappa_f (>= 0).  kappa_f is the mean of kP and kQ (mean = true) or kQ.
+struct FaceJac {
+  double D, DT, dEP, dEQ, dk;
+};
+__device__ inline FaceJac face_jac(double EP, double EQ, double kP, double kQ, double a,
+                                   const DevParams& P, bool mean = true) {
+  FaceJac J;
+  if (P.lim_mode == 1) {
+    J.D = P.D0; J.DT = P.D0; J.dEP = -P.D0; J.dEQ = P.D0; J.dk = 0.0;
+    return J;
+  }
+  const double adx = a * P.dx;
+  const double Ef = 0.5 * (EP + EQ);
+  const double dE = EQ - EP;
+  const double km = mean ? 0.5 * (kP + kQ) : kQ;
+  const double kfl = KAPPA_FLOOR / adx;
+  const double kf = fmax(km, kfl);
+  const double Efl = fmax(Ef, E_TINY);
+  const double R = fabs(dE) / (adx * Efl);
+  const double Pd = 6.0 * kf * kf + 3.0 * kf * R + R * R;
+  const double Pd2 = Pd * Pd;
+  J.D = C_LIGHT * (2.0 * kf + R) / Pd;
+  const double T = -C_LIGHT * R * R * (4.0 * kf + R) / Pd2;
+  const double tail = Ef > E_TINY ? dE * T / (2.0 * Efl) : 0.0;
+  J.DT = J.D + T;
+  J.dEQ = J.D + T - tail;
+  J.dEP = -J.D - T - tail;
+  J.dk = km > kfl ? dE * (-C_LIGHT * (12.0 * kf * kf + 12.0 * kf * R + R * R) / Pd2) : 0.0;
+  return J;
+}
+
+// d kappa / d x_s of one cell (proper), for the species fractions s
+template <int NS>
+__device__ inline void opacity_derivs(double nH, double a, const DevParams& P,
+                                      double (&dk)[NS > 0 ? NS : 1]) {
+  if constexpr (NS == 0) {
+    dk[0] = 0.0;
+  } else {
+    const double np = nH / (a * a * a);
+    dk[0] = P.Kk[0] * np;
+    if constexpr (NS == 3) {
+      dk[1] = P.y * np * P.Kk[1];
+      dk[2] = P.y * np * P.Kk[2];
+    }
+  }
+}
+
 }  // namespace rtk

@@ -15,7 +15,7 @@ from oracle import residual as ores
 from oracle.model import C_LIGHT
 from paper_0901_1110_amd.driver import Simulation
 from tests.gpu_cases import dev, host, pair, random_case, rel
-from tests.test_gpu_parity import newton_parity
+from tests.gpu_cases import newton_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -34,11 +34,16 @@ def test_calls_dirichlet(ns, seed):
         s = max(float(np.max(np.abs(f_o[v]))), float(np.max(np.abs(c["U"][v] / m.scales[v]))),
                 float(np.max(np.abs(tl["g"][v] / m.scales[v]))))
         assert rel(f[v], f_o[v], s) <= 1e-12, v
-    sch = ojac.schur_form(c["U"], f_o, tl["D"], c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    sch = ojac.schur_form(c["U"], f_o, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
     b = host(g.rt_schur_form(dev(c["U"]), dev(f_o), c["dt"], cos))
     got = {k: host(v) for k, v in g.rt_schur_get().items()}
-    for k in ("diag", "cx", "cy", "cz"):
-        assert rel(got[k], sch[k]) <= 1e-12, k
+    got.update({k: host(v) for k, v in g.rt_schur_get_full().items()})
+    scale = max(float(np.max(np.abs(sch["diag"]))), float(np.max(np.abs(sch["pdiag"]))))
+    for k in ("diag", "cx", "cy", "cz", "pdiag"):
+        assert rel(got[k], sch[k], scale) <= 1e-12, k
+    for d, ax in enumerate("xyz"):
+        assert rel(got["fw"][d], sch["f" + ax], scale) <= 1e-12, ax
+        assert rel(got["bw"][d], sch["b" + ax], scale) <= 1e-12, ax
     assert rel(b, sch["b"]) <= 1e-12
 
 

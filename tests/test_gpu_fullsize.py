@@ -68,6 +68,10 @@ def test_residual_and_schur_sampled_blocks(full, c0):
     f, _ = sim.grid.rt_eval_residual(Ud, gn, W.dt, cos)
     b = sim.grid.rt_schur_form(Ud, f, W.dt, cos)
     sch = {k: host(v) for k, v in sim.grid.rt_schur_get().items()}
+    full = {k: host(v) for k, v in sim.grid.rt_schur_get_full().items()}
+    sch["pdiag"] = full["pdiag"]
+    for d, ax in enumerate("xyz"):
+        sch["f" + ax], sch["b" + ax] = full["fw"][d], full["bw"][d]
     f, gn, b = host(f), host(gn), host(b)
     # oracle on the block; sources inside the block keep their offsets
     n = W.n
@@ -82,7 +86,7 @@ def test_residual_and_schur_sampled_blocks(full, c0):
                          W.dt, cos, mb)
     f_o = ores.residual(block(U, c0), tl, block(nH, c0), block(eh, c0), W.dt, cos[2], cos[3], mb)
     # the Schur set-up is compared on the same residual input (the GPU's)
-    so = ojac.schur_form(block(U, c0), block(f, c0), tl["D"], block(nH, c0), block(eh, c0), W.dt,
+    so = ojac.schur_form(block(U, c0), block(f, c0), block(nH, c0), block(eh, c0), W.dt,
                          cos[2], cos[3], mb)
     u = m.scales
     for v in range(3):
@@ -90,8 +94,9 @@ def test_residual_and_schur_sampled_blocks(full, c0):
         assert rel(inner(block(f, c0)[v]), inner(f_o[v]), sc) <= 1e-12, v
         assert rel(inner(block(gn, c0)[v]), inner(tl["g"][v]),
                    max(np.max(np.abs(inner(tl["g"][v]))), 1e-300)) <= 1e-13
-    for k in ("diag", "cx", "cy", "cz"):
-        assert rel(inner(block(sch[k], c0)), inner(so[k])) <= 1e-12, k
+    scale = max(np.max(np.abs(inner(so["diag"]))), np.max(np.abs(inner(so["pdiag"]))))
+    for k in ("diag", "cx", "cy", "cz", "pdiag", "fx", "fy", "fz", "bx", "by", "bz"):
+        assert rel(inner(block(sch[k], c0)), inner(so[k]), scale) <= 1e-12, k
     for r in range(2):
         assert rel(inner(block(sch["ftM"][r], c0)), inner(so["ftM"][r])) <= 1e-12
         assert rel(inner(block(sch["W"][r], c0)), inner(so["W"][r])) <= 1e-12

@@ -2,11 +2,10 @@
 
 Every case feeds identical seeded inputs to the CPU FP64 oracle and to the
 HIP library.  Tolerances (FP64 on both sides; differences come only from
-summation order and from the flexible-CG beta formula, which is algebraically
-identical):
+summation order):
   time level, residual, local blocks, Schur set-up, one V-cycle   1e-12
-  CG with a fixed iteration count                                  1e-11
-  a full Newton step                                               1e-10
+  Krylov solves with a fixed iteration count                       1e-11
+  a full Newton step                         1e-10 normwise, 1e-8 per element
 Sizes span several 256-thread blocks and a ragged last block (n^3 = 4096,
 32768), and the 256^3 workload of the benchmark is checked at full size.
 """
@@ -20,7 +19,7 @@ from oracle import jacobian as ojac
 from oracle import mg as omg
 from oracle import newton as onewt
 from oracle import residual as ores
-from tests.gpu_cases import dev, host, pair, random_case, rel
+from tests.gpu_cases import dev, host, newton_parity, pair, random_case, rel, replay_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -75,17 +74,21 @@ def test_schur_form(ns, n, theta, a, seed):
     cos = c["cosmo"]
     tl = ores.time_level(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], c["dt"], cos, m)
     f_o = ores.residual(c["U"], tl, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
-    sch = ojac.schur_form(c["U"], f_o, tl["D"], c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
-    gn = g.rt_time_level(dev(c["Un"]), c["dt"], cos)
+    sch = ojac.schur_form(c["U"], f_o, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
     fd = dev(f_o)                                  # same residual input on both sides
     b = host(g.rt_schur_form(dev(c["U"]), fd, c["dt"], cos))
     got = {k: host(v) for k, v in g.rt_schur_get().items()}
-    del gn
+    full = {k: host(v) for k, v in g.rt_schur_get_full().items()}
     for k in ("ftM", "W"):
         for r in range(m.nb):
             assert rel(got[k][r], sch[k][r]) <= 1e-12, (k, r)
+    scale = scale_of(sch["diag"], sch["pdiag"])
     for k in ("diag", "cx", "cy", "cz"):
-        assert rel(got[k], sch[k]) <= 1e-12, k
+        assert rel(got[k], sch[k], scale) <= 1e-12, k
+    assert rel(full["pdiag"], sch["pdiag"], scale) <= 1e-12
+    for d, ax in enumerate("xyz"):
+        assert rel(full["fw"][d], sch["f" + ax], scale) <= 1e-12, ax
+        assert rel(full["bw"][d], sch["b" + ax], scale) <= 1e-12, ax
     assert rel(b, sch["b"]) <= 1e-12
 
 
@@ -129,73 +132,74 @@ def test_vcycle_fp32(n, levels, pre, post):
     assert np.array_equal(host(g.rt_mg_vcycle(dev(r))), z)
 
 
-@pytest.mark.parametrize("k", [1, 3, 6])
-def test_pcg_fixed_iterations(k):
-    n, levels = 32, 3
-    w, c = random_case(1, n, 1.0, 1.0, 31, levels=levels)
+def schur_case(n, levels, seed, **kw):
+    """A random state's Schur system on both sides (the library's in its
+    workspace through rt_schur_form)."""
+    w, c = random_case(1, n, 1.0, 1.0, seed, levels=levels, **kw)
     m, g = pair(w, c)
     cos = c["cosmo"]
     tl = ores.time_level(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], c["dt"], cos, m)
     f_o = ores.residual(c["U"], tl, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
-    sch = ojac.schur_form(c["U"], f_o, tl["D"], c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
-    op = (sch["diag"], sch["cx"], sch["cy"], sch["cz"])
-    g.rt_set_operator(*[dev(o) for o in op])
+    sch = ojac.schur_form(c["U"], f_o, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    g.rt_schur_form(dev(c["U"]), dev(f_o), c["dt"], cos)
+    return m, g, sch
+
+
+@pytest.mark.parametrize("k", [1, 3, 6, 12])
+def test_fgmres_fixed_iterations(k):
+    """k FGMRES iterations on the (non-symmetric) Schur matrix, restarted
+    every 4 (so k = 6, 12 cross restarts), with the V-cycle preconditioner."""
+    m, g, sch = schur_case(32, 3, 31, krylov_restart=4)
     s, its, rr = g.rt_mg_pcg_solve(dev(sch["b"]), 0.0, k)
-    s_o, its_o, rr_o = omg.pcg(op, sch["b"], m, rtol=0.0, maxit=k)
+    s_o, its_o, rr_o = omg.fgmres(ojac.operator(sch), ojac.preconditioner_operator(sch),
+                                  sch["b"], m, rtol=0.0, maxit=k, restart=4)
     assert its == its_o == k
     assert rel(host(s), s_o) <= 1e-11
     assert abs(rr - rr_o) <= 1e-9 * max(rr_o, 1e-30) + 1e-14
 
 
-def test_pcg_converges_to_direct_solution():
-    n, levels = 16, 3
-    w, c = random_case(1, n, 1.0, 1.0, 41, levels=levels)
+@pytest.mark.parametrize("k", [4, 11])
+def test_fgmres_fixed_iterations_with_boxes(k):
+    """The same with the source-subdomain correction in the preconditioner
+    (8^3 boxes around the case's three sources, 4 inner iterations)."""
+    m, g, sch = schur_case(32, 3, 33, box_size=8, box_levels=2, box_inner=4, box_coarse_sweeps=3)
+    w_cells = g._cells
+    centres = [np.unravel_index(int(c), sch["b"].shape) for c in w_cells]
+    s, its, rr = g.rt_mg_pcg_solve(dev(sch["b"]), 0.0, k)
+    s_o, its_o, rr_o = omg.fgmres(ojac.operator(sch), ojac.preconditioner_operator(sch),
+                                  sch["b"], m, rtol=0.0, maxit=k, centres=centres)
+    assert its == its_o == k
+    assert rel(host(s), s_o) <= 1e-11
+    assert abs(rr - rr_o) <= 1e-9 * max(rr_o, 1e-30) + 1e-14
+
+
+def test_fgmres_converges_to_direct_solution():
+    m, g, sch = schur_case(16, 3, 41)
+    s, its, rr = g.rt_mg_pcg_solve(dev(sch["b"]), 1e-12, 200)
+    assert rr <= 1e-12
+    s_direct = onewt.direct_solve(ojac.operator(sch), sch["b"])
+    assert rel(host(s), s_direct) <= 1e-10
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_pcg_fixed_iterations(k):
+    """Flexible CG (krylov_restart = 0) on a symmetric operator."""
+    n, levels = 32, 3
+    w, c = random_case(1, n, 1.0, 1.0, 31, levels=levels, krylov_restart=0)
     m, g = pair(w, c)
-    cos = c["cosmo"]
-    tl = ores.time_level(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], c["dt"], cos, m)
-    f_o = ores.residual(c["U"], tl, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
-    sch = ojac.schur_form(c["U"], f_o, tl["D"], c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
-    op = (sch["diag"], sch["cx"], sch["cy"], sch["cz"])
+    m.krylov_restart = 0
+    rng = np.random.default_rng(9)
+    d0 = 1.0 + rng.uniform(0, 20, (n,) * 3)
+    cs = [rng.uniform(0.1, 10, (n,) * 3) for _ in range(3)]
+    csum = sum(cc + np.roll(cc, 1, axis=dd) for dd, cc in enumerate(cs))
+    op = (d0 + csum, cs[0], cs[1], cs[2])
     g.rt_set_operator(*[dev(o) for o in op])
-    s, its, rr = g.rt_mg_pcg_solve(dev(sch["b"]), 1e-13, 200)
-    assert rr <= 1e-13
-    s_direct = onewt.direct_solve(op, sch["b"])
-    assert rel(host(s), s_direct) <= 1e-11
-
-
-def newton_parity(w, state, steps=1, tol_fields=1e-10, mg_fp32=0, last_cg_slack=0):
-    """Run `steps` steps on both sides from the same state; compare each step.
-    last_cg_slack: the CG count of a step's last Newton iteration may differ by
-    this much when that iteration starts from a residual below 1e-3 (its right
-    side is then the rounding-level structure of the iterate)."""
-    m = oracle.model_from_workload(w)
-    from paper_0901_1110_amd.driver import Simulation
-    sim = Simulation(w, state={k: v.copy() if hasattr(v, "copy") else v
-                               for k, v in state.items()})
-    Un, eh = state["U"].copy(), state["eh"].copy()
-    out = []
-    for n in range(steps):
-        cos = w.cosmology(n)
-        U_o, st_o = onewt.newton_step(Un, Un, state["nH"], eh, state["src_cells"],
-                                      state["src_Q"], w.dt, cos, m)
-        st = sim.step()
-        assert st["status"] == 0 and st_o["status"] == 0, (st, st_o)
-        assert st["newton_its"] == st_o["newton_its"], (st, st_o)
-        if last_cg_slack and st_o["fnorms"][-2] < 1e-3:
-            assert st["cg_its"][:-1] == st_o["cg_its"][:-1], (st, st_o)
-            assert abs(st["cg_its"][-1] - st_o["cg_its"][-1]) <= last_cg_slack, (st, st_o)
-        else:
-            assert st["cg_its"] == st_o["cg_its"], (st, st_o)
-        assert st["lambdas"] == st_o["lambdas"]
-        U = host(sim.U)
-        for v in range(m.nv):
-            assert rel(U[v], U_o[v]) <= tol_fields, (n, v, rel(U[v], U_o[v]))
-        out.append((st, st_o))
-        sim.advance()
-        eh = eh + U_o[0]
-        U_o[0] = 0.0
-        Un = U_o
-    return out
+    b = rng.standard_normal((n,) * 3)
+    s, its, rr = g.rt_mg_pcg_solve(dev(b), 0.0, k)
+    s_o, its_o, rr_o = omg.pcg(op, b, m, rtol=0.0, maxit=k)
+    assert its == its_o == k
+    assert rel(host(s), s_o) <= 1e-11
+    assert abs(rr - rr_o) <= 1e-9 * max(rr_o, 1e-30) + 1e-14
 
 
 def test_newton_step_small_config():
@@ -234,11 +238,21 @@ def test_newton_steps_source_box_unfused_dots(levels, post):
     newton_parity(w, synth.initial_state(w), steps=2)
 
 
+# The expanding lognormal media (16 sources, 1.25 kpc proper cells, steps of
+# 5e13 and 1e14 s: hundreds of light-crossings of a cell per step) do not
+# converge with Newton on the residual with the limiter at the iterate (both
+# sides stop in the line search: measured), nor does the corner-source HII
+# region past its second step; their workloads hold the limiter at time
+# level n (limiter_lag = 1: a linear diffusion term within the step).
+LAG = dict(limiter_lag=1)
+
+
 def test_newton_steps_overlapping_boxes():
     """16 sources in a 32^3 lognormal cut: the 8^3 boxes overlap and their
     corrections add in source order on both sides."""
     w = synth.CFG_COSMO.replace(n=32, mg_levels=3, dx=synth.CFG_COSMO.dx, box_size=8,
                                 box_levels=2, box_inner=3)
+    assert w.limiter_lag == 1
     newton_parity(w, synth.initial_state(w), steps=2)
 
 
@@ -246,6 +260,25 @@ def test_newton_steps_expanding_lognormal():
     """Expanding lognormal medium with 16 sources (32^3 cut of the 128^3 workload)."""
     w = synth.CFG_COSMO.replace(n=32, mg_levels=3, dx=synth.CFG_COSMO.dx)
     newton_parity(w, synth.initial_state(w), steps=2)
+
+
+def test_newton_step_expanding_lognormal_live_fails_alike():
+    """With the limiter at the iterate the same step fails on both sides in
+    the same way (equal Newton iterates up to the failing line search)."""
+    w = synth.CFG_COSMO.replace(n=32, mg_levels=3, dx=synth.CFG_COSMO.dx, newton_maxit=4,
+                                limiter_lag=0)
+    m = oracle.model_from_workload(w)
+    s = synth.initial_state(w)
+    from paper_0901_1110_amd.driver import Simulation
+    sim = Simulation(w, state={k: v.copy() if hasattr(v, "copy") else v for k, v in s.items()})
+    st = sim.step()
+    U_o, st_o = onewt.newton_step(s["U"], s["U"], s["nH"], s["eh"], s["src_cells"], s["src_Q"],
+                                  w.dt, w.cosmology(0), m)
+    assert st["status"] == st_o["status"] != 0
+    assert st["newton_its"] == st_o["newton_its"] and st["lambdas"] == st_o["lambdas"]
+    U = host(sim.U)
+    for v in range(m.nv):
+        assert rel(U[v], U_o[v]) <= 1e-10, v
 
 
 def test_newton_step_hydrogen_helium():
@@ -256,6 +289,14 @@ def test_newton_step_hydrogen_helium():
 def test_newton_step_theta_051():
     w = synth.CFG_SMALL.replace(theta=0.51, dt=1e10)
     newton_parity(w, synth.initial_state(w), steps=2)
+
+
+def test_replay_256_spacing_forcing():
+    """Replay mode: the oracle executes the library's Krylov counts and line
+    search factors on five steps at the 256^3 cell size with the paper's
+    forcing; every iterate agrees."""
+    w = synth.CFG_256.replace(n=64, mg_levels=4, pcg_forcing=1e-6)
+    replay_parity(w, synth.initial_state(w), steps=5)
 
 
 @pytest.mark.parametrize("ns,seed", [(1, 31), (3, 32)])
@@ -275,16 +316,19 @@ def test_time_level_and_residual_reflecting(ns, seed):
 
 def test_newton_steps_reflecting_corner():
     """The paper's Sec. 4.5 geometry: source in the corner cell, reflecting walls."""
-    w = synth.CFG_256.replace(n=32, mg_levels=3, boundary=1, corner_source=True)
+    w = synth.CFG_256.replace(n=32, mg_levels=3, boundary=1, corner_source=True, **LAG)
     newton_parity(w, synth.initial_state(w), steps=3)
+
+
+def test_newton_steps_reflecting_corner_live():
+    """The same geometry with the limiter at the iterate: its first two steps."""
+    w = synth.CFG_256.replace(n=32, mg_levels=3, boundary=1, corner_source=True)
+    newton_parity(w, synth.initial_state(w), steps=2)
 
 
 def test_newton_steps_reflecting_lognormal_boxes():
     """Reflecting walls with the lognormal medium, 16 sources and overlapping
-    8^3 correction boxes that reach across the walls.  The first step's last
-    Newton iteration starts at ||f|| = 4e-5: with the library's own iterate
-    its CG solve needs 2 iterations, with the oracle's 3 (measured with both
-    iterates through the same calls), so that count may differ by one."""
+    8^3 correction boxes that reach across the walls."""
     w = synth.CFG_COSMO.replace(n=32, mg_levels=3, boundary=1, box_size=8, box_levels=2,
                                 box_inner=3)
-    newton_parity(w, synth.initial_state(w), steps=2, last_cg_slack=1)
+    newton_parity(w, synth.initial_state(w), steps=2)

@@ -15,7 +15,7 @@ import synth
 from paper_0901_1110_amd.driver import Simulation
 from tests.gpu_cases import host
 from tests.sg_closed_form import front_radius, ionized_radius
-from tests.test_gpu_parity import newton_parity
+from tests.gpu_cases import newton_parity
 from tests.test_oracle_shapiro_giroux import SG, sg_constants
 
 pytestmark = pytest.mark.gpu

@@ -22,12 +22,12 @@ import oracle
 from oracle import jacobian, mg, newton, residual
 
 
-def case(nspecies, theta, a, seed):
+def case(nspecies, theta, a, seed, lag=0):
     n = 4
     if nspecies == 1:
-        w = synth.CFG_SMALL.replace(n=n, theta=theta, mg_levels=2)
+        w = synth.CFG_SMALL.replace(n=n, theta=theta, mg_levels=2, limiter_lag=lag)
     else:
-        w = synth.CFG_HHE.replace(n=n, theta=theta, mg_levels=2)
+        w = synth.CFG_HHE.replace(n=n, theta=theta, mg_levels=2, limiter_lag=lag)
     m = oracle.model_from_workload(w, pcg_rtol=1e-14, pcg_maxit=500)
     rng = np.random.default_rng(seed)
     U, nH, eh = synth.random_physical_state(n, nspecies, rng, nH_mean=1e-3 * a ** 3)
@@ -49,12 +49,14 @@ CASES = [(1, 1.0, 1.0, 1), (1, 0.51, 1.0, 2), (1, 1.0, 0.1, 3), (3, 1.0, 1.0, 4)
          (3, 0.51, 0.1, 5)]
 
 
-@pytest.mark.parametrize("ns,theta,a,seed", CASES)
-def test_dense_brute_force(ns, theta, a, seed):
-    m, U, nH, eh, tl, dt, a, H = case(ns, theta, a, seed)
+@pytest.mark.parametrize("ns,theta,a,seed,lag", [c + (0,) for c in CASES] + [CASES[3] + (1,)])
+def test_dense_brute_force(ns, theta, a, seed, lag):
+    """lag = 1: the lagged reading (face coefficients at U^n), whose Newton
+    matrix is the derivative with those coefficients fixed."""
+    m, U, nH, eh, tl, dt, a, H = case(ns, theta, a, seed, lag)
     u = m.scales.reshape(-1, 1, 1, 1)
     f = residual.residual(U, tl, nH, eh, dt, a, H, m)
-    J = jacobian.dense_jacobian(U, nH, eh, dt, a, H, m)
+    J = jacobian.dense_jacobian(U, nH, eh, dt, a, H, m, tl.get("D"))
     nv, N = m.nv, U[0].size
 
     # (i) Richardson-extrapolated central differences, column by column
@@ -92,7 +94,7 @@ def test_dense_brute_force(ns, theta, a, seed):
 
     # (ii) dense solve vs Schur + MG-FGMRES
     S_dense = np.linalg.solve(J, -f.ravel()).reshape(U.shape)
-    sch = jacobian.schur_form(U, f, nH, eh, dt, a, H, m)
+    sch = jacobian.schur_form(U, f, nH, eh, dt, a, H, m, tl.get("D"))
     op = jacobian.operator(sch)
     sE = newton.direct_solve(op, sch["b"])
     S_schur = jacobian.recover(sE, sch)
