@@ -3,20 +3,27 @@
 
 A step is one full implicit time step of the 256^3 periodic hydrogen problem
 (centred 5e48 photons/s source in a 13.2 kpc box, dt = 1e11 s, theta = 1):
-time-level set-up, Newton iterations with Schur elimination, MG-PCG and line
-search until the RMS residual is below 1e-6, then the energy fold.  Inputs
-stay resident in HBM; W warm-up steps run first (default 20: past the
-start-up transient of the 200-step trajectory), then K steps are timed, each
-from the state the previous one produced.
+time-level set-up, Newton iterations with Schur elimination, MG-preconditioned
+FGMRES and line search until the RMS residual is below 1e-6, then the energy
+fold.  Inputs
+stay resident in HBM; W warm-up steps run first (default 5), then K steps
+are timed (default 10), each from the state the previous one produced.
 
 Modes: plain (FP64 V-cycle, previous-state guess), mixed (FP32 V-cycle
-inside FP64 Newton/CG), learned and mixed+learned (the better, by initial
+inside FP64 Newton/Krylov), learned and mixed+learned (the better, by initial
 residual, of the previous state and the convolutional network's guess; the
-network is trained first, untimed, on 200-step plain-method trajectories at
-128^3 with the same cell size and time step).  The JSON line reports the
-headline mode (mixed+learned) in `value` and every mode in `modes`;
-`roofline` covers the kernel class with the largest share of the timed region, timed with HIP events on the library's stream; `cpu_baseline`
-times the CPU FP64 oracle on a bounded sample of the same problem.
+network is trained first, untimed, on a plain-method trajectory at 128^3
+with the same cell size and time step).  The JSON line reports the headline
+mode (mixed+learned) in `value` and every mode in `modes`.
+
+`roofline` covers the kernel class with the largest share of the timed
+region (HIP events on the library's stream around that class's launches);
+its algorithmic bytes are the library's own per-launch count (every field a
+launch must read or write, once).  `step_hbm` divides the algorithmic bytes
+of every launch of the timed steps by the timed region, `box_correction`
+those of the source-subdomain graphs by their replay time.  `cpu_baseline`
+times the CPU FP64 oracle on a bounded sample of the same problem, on all
+host cores and on one.
 """
 from __future__ import annotations
 
@@ -38,43 +45,11 @@ WORKLOAD_SG = ("sg_q05_z4: %d^3 periodic uniform hydrogen, 0.625 kpc proper cell
                "dt=2e15 s, theta=1, Newton tol 1e-6, PCG rtol 1e-8%s, 4-level V-cycle RB-GS 2+2%s")
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per cell and launch of each kernel class (H-only, FP64
-# fields = 8 B; FP32 V-cycle fields = 4 B).  Neighbour values read through the
-# cache are not counted: a stencil needs each field once.
-#   residual : read U(3) g(3) n_H e_h D(3), write f(3)                  = 14 x 8
-#   schur    : read U(3) f(3) n_H e_h D(3), write f~_M(2) W(2) S(4) b   = 20 x 8
-#   trial    : read U(3) f~_M(2) W(2) s_E, write U_t(3)                 = 11 x 8
-#   spmv     : read diag cx cy cz p, write q                            = 6 x 8
-#   rbgs     : one half-sweep: all 3 couplings, diag and b of the colour,
-#              the other colour's x, write the colour's x              = (3 + 1) w + 1 w = 5 w
-#              first (red, black) pair from x = 0, one launch: diag, b,
-#              the 3 couplings, write x                                = 6 w
-#              FP32 cycle's last half-sweep: 4 w, write z (FP64, both
-#              colours), read r and q (FP64) for the CG dots           = 4 w + 24 B
-#              (the subdomain correction, when on, adds its own part of
-#              the dots over the box cells)
-# (w = 4 B for the FP32 V-cycle, 8 B for FP64)
-BYTES_PER_CELL = {"residual": 112.0, "schur": 160.0, "trial": 88.0, "spmv": 48.0}
-# with the FP32 cycle the Schur assembly also writes the four FP32 operator
-# arrays of the finest level
-SCHUR_FP32_EXTRA = 16.0
-
-
-def class_bytes_per_cell(dom, wbytes):
-    """Algorithmic bytes per cell of one launch of a modelled Newton-level class."""
-    b = BYTES_PER_CELL[dom]
-    return b + (SCHUR_FP32_EXTRA if dom == "schur" and wbytes == 4.0 else 0.0)
-
-
-# HBM traffic per launch of the finest-level FP32 smoother class at 256^3 with
-# V(2,2), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by
-# what the counters read for a plain 2 GiB device copy (FETCH_SIZE x 2.0,
-# WRITE_SIZE x 1.0), averaged over one V-cycle's 7 launches, with the subdomain
-# correction on.  It belongs to the
-# kernel source it was measured on and is reported as null for any other.
-PMC_TRAFFIC = {"rbgs_fine": {"w": 4, "n": 256, "pre_post": (2, 2), "dots": True,
-                             "bytes_per_launch": 4.198e8,
-                             "kernels_sha256": "30d3d56a17f7a2c42448280a75d4a956f54a4660e32b1f764829694b9c264f47"}}
+# HBM traffic per launch of a kernel class, keyed (class, mode, grid), from
+# two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by what the
+# counters read for a plain device copy of known size.  A figure belongs to
+# the kernel source it was measured on and is reported as null for any other.
+PMC_TRAFFIC = {}
 
 
 def kernels_sha256():
@@ -83,20 +58,8 @@ def kernels_sha256():
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def rbgs_fine_per_vcycle(pre, post, w, dots=True):
-    """(launches, algorithmic bytes per cell) of the fine-level smoothing in one
-    V-cycle of the CG loop; in the FP32 cycle the last half-sweep writes the
-    FP64 result and forms the CG dots (pre, post > 0 there)."""
-    if pre > 0:
-        launches = 1 + 2 * (pre - 1) + 2 * post
-        b = 6.0 * w + (2 * (pre - 1) + 2 * post) * 5.0 * w
-        if w == 4.0 and post > 0:
-            b += (4.0 * w + (24.0 if dots else 8.0)) - 5.0 * w
-        return launches, b
-    return 2 * post, 2 * post * 5.0 * w
-
-
-def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None, box=(0, 3, 6, 0)):
+def train_guess(n_train=128, steps=100, epochs=8, lr=3e-4, log=None, box=(0, 3, 6, 0),
+                trajectories=1):
     """Train the learned-guess network on plain-method trajectories."""
     import numpy as np
     import synth
@@ -106,8 +69,8 @@ def train_guess(n_train=128, steps=200, epochs=8, lr=3e-4, log=None, box=(0, 3, 
     t0 = time.perf_counter()
     base = synth.CFG_256.replace(n=n_train, mg_levels=4, box_size=box[0], box_levels=box[1],
                                  box_inner=box[2], box_coarse_sweeps=box[3])
-    media = [base, base.replace(sigma_ln=1.0, nsources=4, centred=False, seed=100,
-                                logQ_range=(48.0, 48.7))]
+    media = [base, base.replace(nsources=2, centred=False, seed=100,
+                                logQ_range=(48.0, 48.7))][:trajectories]
     trajs = []
     for w in media:
         ts = time.perf_counter()
@@ -159,7 +122,8 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
     else:
         sim = Simulation(w)
     # the warm-up times every kernel class to find the dominant one; the timed
-    # steps record events around that class's launches only
+    # steps record events around that class's launches only (and count the
+    # bytes of all)
     sim.grid.rt_timing(True)
     for _ in range(warmup):
         st = sim.step()
@@ -168,11 +132,9 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
         sim.advance()
     kt_warm = sim.grid.rt_timing(False)
     # the subdomain correction is one graph of a few hundred small kernels,
-    # timed per replay: it is reported beside the roofline, not as a kernel.
-    # The roofline covers the largest class with a byte model.
-    modelled = ["rbgs_fine"] + list(BYTES_PER_CELL)
-    dom_all = max((k for k in kt_warm if k != "box"), key=lambda k: kt_warm[k][1])
-    dom = max(modelled, key=lambda k: kt_warm[k][1])
+    # timed per replay: it is reported beside the roofline, not as a kernel
+    dom = max((k for k in kt_warm if k != "box" and kt_warm[k][2] > 0),
+              key=lambda k: kt_warm[k][1])
     stats = []
     torch.cuda.synchronize()
     sim.grid.rt_timing_classes([dom, "box"])
@@ -197,82 +159,129 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
     newton = sum(s["newton_its"] for s in stats)
     cg = sum(s["cg_its_total"] for s in stats)
     vc = sum(s["vcycles"] for s in stats)
+    net_ms = None
+    if mode.endswith("learned"):
+        # the network's cost per step: its forward pass timed alone
+        reps = 5
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.net.stream)
+        for _ in range(reps):
+            sim.net.forward(sim.Un, sim.Unm1, sim.eh, sim.ehm1, sim.nH, sim.nH_mean, w.u_e,
+                            w.u_E, sim.eh, sim.Uguess)
+        e1.record(sim.net.stream)
+        torch.cuda.synchronize()
+        net_ms = e0.elapsed_time(e1) / reps
     res = dict(mode=mode, cells=N, steps=steps, wall_s=wall, event_ms=gpu_ms,
                value=N * steps / wall, ms_per_step=1e3 * wall / steps,
                newton_its=newton, cg_its=cg, vcycles=vc,
                model_seconds_per_s=sum(st_.get("dt", w.dt) for st_ in stats) / wall,
                cell_newton_its_per_s=N * newton / wall, kernels_warmup=kt_warm,
                network_guess_used=sum(s["used_alt_guess"] for s in stats),
+               network_ms_per_step=None if net_ms is None else round(net_ms, 3),
                fnorm0_mean=sum(min(s["fnorm_guess"], s["fnorm_alt"]) if s["fnorm_alt"] >= 0
                                else s["fnorm_guess"] for s in stats) / len(stats))
-    # roofline of the dominant kernel class
-    wbytes = 4.0 if mode.startswith("mixed") else 8.0
-    p = sim.grid.params
-    launches_vc, bytes_vc = rbgs_fine_per_vcycle(p.mg_pre, p.mg_post, wbytes)
-    cnt, ms = kt[dom]
-    if dom == "rbgs_fine":
-        total_bytes = cnt / float(launches_vc) * bytes_vc * N
-    elif dom in BYTES_PER_CELL:
-        total_bytes = cnt * class_bytes_per_cell(dom, wbytes) * N
-    else:
-        total_bytes = None
-    if total_bytes is not None and ms > 0:
-        achieved = total_bytes / (ms * 1e-3) / 1e9
-        tr = PMC_TRAFFIC.get(dom)
+    # roofline of the dominant kernel class, on the library's byte count
+    cnt, ms, nbytes = kt[dom]
+    if cnt > 0 and ms > 0:
+        achieved = nbytes / (ms * 1e-3) / 1e9
+        tr = PMC_TRAFFIC.get((dom, mode, n))
         traffic = None
-        if (tr and tr["w"] == wbytes and tr["n"] == n and tr["pre_post"] == (p.mg_pre, p.mg_post)
-                and tr["dots"] and kernels_sha256() == tr["kernels_sha256"]):
+        if tr and kernels_sha256() == tr["kernels_sha256"]:
             traffic = tr["bytes_per_launch"]
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                           "algorithmic_bytes_per_launch": round(total_bytes / cnt),
+                           "algorithmic_bytes_per_launch": round(nbytes / cnt),
                            "launches": cnt, "avg_launch_us": round(1e3 * ms / cnt, 2),
-                           "largest_class_in_warmup": dom_all,
                            "share_of_timed": round(ms / gpu_ms, 3)}
+    # the whole step: every launch's algorithmic bytes over the timed region
+    tot_bytes = sum(v[2] for v in kt.values())
+    res["step_hbm"] = {"algorithmic_GB_per_step": round(tot_bytes / steps / 1e9, 3),
+                       "achieved": round(tot_bytes / (gpu_ms * 1e-3) / 1e9, 1),
+                       "frac": round(tot_bytes / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "bytes_share": {k: round(v[2] / tot_bytes, 3) for k, v in kt.items()
+                                       if v[2] > 0}}
     if kt["box"][0] > 0:
         res["box_correction"] = {"replays": kt["box"][0],
                                  "avg_replay_us": round(1e3 * kt["box"][1] / kt["box"][0], 1),
-                                 "share_of_timed": round(kt["box"][1] / gpu_ms, 3)}
+                                 "share_of_timed": round(kt["box"][1] / gpu_ms, 3),
+                                 "hbm_frac": round(kt["box"][2] / (kt["box"][1] * 1e-3) / 1e9
+                                                   / HBM_PEAK_GBS, 4)}
     del sim
     torch.cuda.empty_cache()
     return res
 
 
-def cpu_baseline(n=128, box=(0, 3, 6, 0), workload="hii_256"):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_cores():
+    """Cores this process may run on (the affinity mask; a container's CPU
+    share can be smaller than what the machine reports)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(n=64, box=(0, 3, 6, 0), workload="hii_256"):
     """The oracle on a bounded sample: the first implicit step of the same
-    problem (same cell size) on an n^3 periodic box around the source."""
+    problem (same cell size) on an n^3 periodic box around the source, on
+    all host cores (NumPy/BLAS threads) and on one."""
     from threadpoolctl import threadpool_limits
 
     import synth
     import oracle
     from oracle import newton
 
-    w = synth.WORKLOADS[workload].replace(n=n, mg_levels=4, box_size=box[0], box_levels=box[1],
+    w = synth.WORKLOADS[workload].replace(n=n, mg_levels=min(4, synth.WORKLOADS[workload].mg_levels),
+                                          box_size=box[0], box_levels=box[1],
                                           box_inner=box[2], box_coarse_sweeps=box[3])
     m = oracle.model_from_workload(w)
     s = synth.initial_state(w)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        U, st = newton.newton_step(s["U"], s["U"], s["nH"], s["eh"], s["src_cells"], s["src_Q"],
-                                   w.dt, w.cosmology(0), m)
-        dt = time.perf_counter() - t0
-    return {"value": n ** 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "first implicit step (status %d, %d Newton its, %d CG its) of the "
-                      "%s problem (same cell size) on a %d^3 periodic box around the source, "
-                      "same preconditioner, NumPy FP64, 1 thread, %.1f s"
-                      % (st["status"], st["newton_its"], sum(st["cg_its"]), workload, n, dt)}
+    out = {}
+    for cores in (host_cores(), 1):
+        with threadpool_limits(limits=cores):
+            t0 = time.perf_counter()
+            U, st = newton.newton_step(s["U"], s["U"], s["nH"], s["eh"], s["src_cells"],
+                                       s["src_Q"], w.dt, w.cosmology(0), m)
+            dt = time.perf_counter() - t0
+        out[cores] = (n ** 3 / dt, dt, st)
+        if cores == 1:
+            break
+    allc = max(out)
+    v, dt, st = out[allc]
+    res = {"value": v, "unit": "cell-updates/s", "cores": allc, "kind": "oracle",
+           "cpu": cpu_model(),
+           "sample": "first implicit step (status %d, %d Newton its, %d Krylov its) of the "
+                     "%s problem (same cell size) on a %d^3 periodic box around the source, "
+                     "same solver and preconditioner, NumPy FP64, %.1f s on %d threads"
+                     % (st["status"], st["newton_its"], sum(st["cg_its"]), workload, n, dt,
+                        allc)}
+    if 1 in out and allc != 1:
+        res["one_core"] = {"value": out[1][0], "seconds": round(out[1][1], 2)}
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--modes", default=None,
                     help="default plain,mixed,learned,mixed+learned (plain,mixed for sg_q05_z4)")
     ap.add_argument("--train-epochs", type=int, default=8)
-    ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--train-steps", type=int, default=100)
+    ap.add_argument("--train-trajectories", type=int, default=1)
     ap.add_argument("--workload", default="hii_256", choices=["hii_256", "sg_q05_z4"],
                     help="hii_256: the timed 256^3 HII region; sg_q05_z4: the expanding-universe "
                          "I-front of Sec. 4.6 at 128^3 (cell size fixed, --n sets the box)")
@@ -330,7 +339,7 @@ def main():
         print("# training the learned guess (untimed)", file=sys.stderr, flush=True)
         theta, train_info = train_guess(steps=args.train_steps, epochs=args.train_epochs,
                                         log=lambda s: print("#   " + s, file=sys.stderr, flush=True),
-                                        box=box)
+                                        box=box, trajectories=args.train_trajectories)
         print("# trained: %s" % train_info, file=sys.stderr, flush=True)
     for mode in modes:
         print("# mode %s: %d warm-up + %d timed steps at %d^3" % (mode, args.warmup, args.steps, args.n),
@@ -358,11 +367,13 @@ def main():
                                    if args.box_size > 0 else ""),
                    "mode": head, "grid": args.n, "parallelism": "single GPU"},
         "roofline": H.get("roofline"),
+        "step_hbm": H.get("step_hbm"),
         "modes": {k: {kk: v[kk] for kk in ("value", "ms_per_step", "newton_its", "cg_its",
                                            "vcycles", "cell_newton_its_per_s", "model_seconds_per_s",
-                                           "network_guess_used", "fnorm0_mean")
-                      if kk in v} | ({"box_correction": v["box_correction"]}
-                                     if "box_correction" in v else {})
+                                           "network_guess_used", "network_ms_per_step",
+                                           "fnorm0_mean", "roofline", "step_hbm",
+                                           "box_correction")
+                      if v.get(kk) is not None}
                   for k, v in results.items()},
     }
     if train_info:
@@ -371,8 +382,7 @@ def main():
         line["speedup_vs_plain"] = H["value"] / results["plain"]["value"]
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = (cpu_baseline(box=box) if args.workload == "hii_256"
-                                else cpu_baseline(64, box, args.workload))
+        line["cpu_baseline"] = cpu_baseline(64, box, args.workload)
     print(json.dumps(line), flush=True)
     with open(os.path.join(ROOT, "gpurun_out", "bench_kernels.json") if os.path.isdir(
             os.path.join(ROOT, "gpurun_out")) else os.devnull, "w") as fh:

@@ -282,6 +282,12 @@ enum {
 typedef struct rt_kernel_timing {
   int32_t count[RT_K_COUNT];      /* launches */
   double  total_ms[RT_K_COUNT];   /* summed HIP-event durations */
+  double  bytes[RT_K_COUNT];      /* algorithmic bytes (every field a launch    */
+                                  /* must read or write, once) of ALL launches */
+                                  /* made while collection was on, whatever    */
+                                  /* classes are selected for events; final    */
+                                  /* reductions and sources count 0, a box     */
+                                  /* graph replay the sum over its launches    */
 } rt_kernel_timing;
 
 /* Per-launch HIP-event timing on the grid's stream.  enable = 1 clears and

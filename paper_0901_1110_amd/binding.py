@@ -78,10 +78,12 @@ RT_K_NAMES = ["timelevel", "residual", "trial", "schur", "rbgs_fine", "rbgs_coar
 
 class RtKernelTiming(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32 * len(RT_K_NAMES)),
-                ("total_ms", ctypes.c_double * len(RT_K_NAMES))]
+                ("total_ms", ctypes.c_double * len(RT_K_NAMES)),
+                ("bytes", ctypes.c_double * len(RT_K_NAMES))]
 
     def as_dict(self):
-        return {n: (self.count[i], self.total_ms[i]) for i, n in enumerate(RT_K_NAMES)}
+        return {n: (self.count[i], self.total_ms[i], self.bytes[i])
+                for i, n in enumerate(RT_K_NAMES)}
 
 
 _P = ctypes.c_void_p
@@ -361,7 +363,8 @@ class RtGrid:
         return s, its.value, rr.value
 
     def rt_timing(self, enable):
-        """enable=True starts per-launch event timing; False returns {class: (count, ms)}."""
+        """enable=True starts per-launch event timing; False returns
+        {class: (launches, ms, algorithmic bytes)}."""
         out = RtKernelTiming()
         self._check(lib().rt_timing(self.h, 1 if enable else 0, None if enable else ctypes.byref(out)),
                     "rt_timing")

@@ -75,6 +75,7 @@ struct Timer {
   std::vector<hipEvent_t> pool;           // events, reused across collections
   std::vector<int> cls;                   // class of each recorded launch
   size_t used = 0;
+  double bytes[RT_K_COUNT] = {};          // algorithmic bytes of the recorded launches
 };
 
 struct rt_grid {
@@ -94,6 +95,8 @@ struct rt_grid {
   double* hpin = nullptr;   // pinned host scalars for asynchronous read-back
   int nbox = 0;             // active source subdomains (0: V-cycle alone)
   int tk_override = -1;     // >= 0: time every launch under this class
+  bool capturing = false;   // launches go into the box graph: bytes to cap_bytes
+  double cap_bytes = 0.0;
   double cg_rate1 = 0.0;    // residual reduction of the last solve's first CG step (0: none yet)
   hipEvent_t ev_rd = nullptr;
   // the source-subdomain correction as a captured graph (a few hundred small
@@ -105,6 +108,7 @@ struct rt_grid {
     const double* r = nullptr;
     double* z = nullptr;
     int nbox = 0, dots = 0;
+    double bytes = 0.0;     // algorithmic bytes of one replay
   } box_graph[2];           // without and with the dot partials
   std::string err;
 };
@@ -153,6 +157,24 @@ inline void tstop(rt_grid* g, long slot) {
     const long slot_ = tstart(g, cls); \
     expr;                              \
     tstop(g, slot_);                   \
+  } while (0)
+// the same, also counting the launch's algorithmic bytes (each field it
+// must read or write, once) for its class: while timing is on, whatever
+// classes are selected for events, and into the graph's figure while the
+// box correction is being captured
+inline void addb(rt_grid* g, int cls, double nbytes) {
+  if (g->capturing) {
+    g->cap_bytes += nbytes;
+    return;
+  }
+  if (!g->tm.on) return;
+  if (g->tk_override >= 0) cls = g->tk_override;
+  g->tm.bytes[cls] += nbytes;
+}
+#define TKB(g, cls, nbytes, expr) \
+  do {                            \
+    TK(g, cls, expr);             \
+    addb(g, cls, (nbytes));       \
   } while (0)
 
 #define HIPCHK(g, call)                                                                  \
@@ -213,6 +235,29 @@ int validate(const rt_params* p, std::string* why) {
       return bad("box_size larger than the grid");
   }
   return RT_OK;
+}
+
+// device parameters of a grid (the kernels' copy of rt_params)
+void fill_params(const rt_params* p, DevParams& P) {
+  P.nx = p->nx; P.ny = p->ny; P.nz = p->nz;
+  P.ns = p->nspecies; P.nv = p->nspecies + 2; P.nb = p->nspecies + 1;
+  P.kap_lte = p->kappa_lte; P.kapP_lte = p->kappaP_lte; P.mu_lte = p->mu_lte;
+  P.bc = p->boundary;
+  P.Eb = p->E_dirichlet;
+  P.N = p->nx * p->ny * p->nz;
+  P.iso = p->isothermal; P.lim_mode = p->limiter_mode;
+  P.dx = p->dx; P.theta = p->theta; P.u_e = p->u_e; P.u_E = p->u_E;
+  P.m = p->grey ? 1.0 : 0.0; P.y = p->y_he; P.T_iso = p->T_iso; P.D0 = p->D0;
+  for (int s = 0; s < 3; ++s) {
+    P.Kg[s] = p->K_gamma[s]; P.Kk[s] = p->K_kappa[s]; P.Kh[s] = p->K_heat[s];
+  }
+  if (p->nspecies == 1) {
+    for (int s = 1; s < 3; ++s) P.Kg[s] = P.Kk[s] = P.Kh[s] = 0.0;
+  }
+  P.hnu = p->hnu_mean;
+  P.alpha0[0] = 2.59e-13;                            // case-B HII at 1e4 K
+  P.alpha0[1] = 2.72e-13;                            // HeII (placeholder datum)
+  P.alpha0[2] = 2.0 * 2.59e-13 * std::pow(4.0, 0.7); // HeIII, hydrogenic Z = 2
 }
 
 // The finest level of the FP32 cycle is smoothed with pre- and post-sweeps
@@ -383,41 +428,53 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, int cs, double* out64 
   const bool coarsest = (l + 1 == (int)Ls.size());
   const int kc = l == 0 ? RT_K_RBGS_FINE : RT_K_RBGS_COARSE;
   const long n = (long)L.nx * L.ny * L.nz;
+  // algorithmic bytes, per field of this level: a half-sweep reads the three
+  // coupling arrays (the - faces of a cell are stored at the other colour's
+  // cells), the diagonal and right side of its colour and the other colour's
+  // x, and writes its colour's x: 5 fields.  The first pair from x = 0 and a
+  // coarsest solve read the operator and right side once and write x: 6
+  const double F = (double)sizeof(T) * n;
   if (coarsest && L.nx % L.blocks == 0 && n / L.blocks <= COARSE_LDS_MAX) {
-    TK(g, kc, launch_coarse_solve_lds<T>(L, cs, st));
+    TKB(g, kc, 6.0 * F, launch_coarse_solve_lds<T>(L, cs, st));
     return;
   }
   if (coarsest && n <= COARSE_SOLVE_MAX) {
-    TK(g, kc, launch_coarse_solve<T>(L, cs, st));
+    TKB(g, kc, 6.0 * F, launch_coarse_solve<T>(L, cs, st));
     return;
   }
   const int pre = coarsest ? cs : p.mg_pre;
   const int post = coarsest ? cs : p.mg_post;
   if (pre > 0) {
     // (red, black) from x = 0, unless a fused launch has already done it
-    if (!first_done) TK(g, kc, launch_rbgs_first_pair<T>(L, L.x, st));
+    if (!first_done) TKB(g, kc, 6.0 * F, launch_rbgs_first_pair<T>(L, L.x, st));
     for (int s = 1; s < pre; ++s) {
-      TK(g, kc, launch_rbgs<T>(L, 0, st));
-      TK(g, kc, launch_rbgs<T>(L, 1, st));
+      TKB(g, kc, 5.0 * F, launch_rbgs<T>(L, 0, st));
+      TKB(g, kc, 5.0 * F, launch_rbgs<T>(L, 1, st));
     }
   } else {
-    TK(g, RT_K_OTHER, launch_fill<T>(n, L.x, T(0), st));
+    TKB(g, RT_K_OTHER, F, launch_fill<T>(n, L.x, T(0), st));
   }
   if (!coarsest) {
-    TK(g, RT_K_MG_TRANSFER, launch_mg_residual<T>(L, st));
-    TK(g, RT_K_MG_TRANSFER, launch_restrict<T>(L, Ls[l + 1], st));
+    // residual: operator (4), x, b in, r out; restriction: r in, coarse b out;
+    // prolongation: coarse x in, the corrected cells of x in and out
+    TKB(g, RT_K_MG_TRANSFER, 7.0 * F, launch_mg_residual<T>(L, st));
+    TKB(g, RT_K_MG_TRANSFER, 1.125 * F, launch_restrict<T>(L, Ls[l + 1], st));
     vcycle<T>(g, Ls, l + 1, cs);
     // the post-smoothing starts with black: only red cells need the correction
-    TK(g, RT_K_MG_TRANSFER, launch_prolong_add<T>(Ls[l + 1], L, post > 0 ? 0 : -1, st));
+    TKB(g, RT_K_MG_TRANSFER, (post > 0 ? 1.125 : 2.125) * F,
+        launch_prolong_add<T>(Ls[l + 1], L, post > 0 ? 0 : -1, st));
   }
   for (int s = 0; s < post; ++s) {
-    TK(g, kc, launch_rbgs<T>(L, 1, st));
+    TKB(g, kc, 5.0 * F, launch_rbgs<T>(L, 1, st));
     if (out64 && s + 1 == post) {
-      TK(g, kc, launch_rbgs_out64<T>(L, 0, out64, r64, q64, parts, st));
+      // no x write: both colours go widened to out64 (8 B), and with the dot
+      // partials r64 and q64 are read (16 B)
+      TKB(g, kc, 4.5 * F + (8.0 + (parts ? 16.0 : 0.0)) * n,
+          launch_rbgs_out64<T>(L, 0, out64, r64, q64, parts, st));
     } else if (pd && s + 1 == post) {
-      TK(g, kc, launch_rbgs_dots<T>(L, 0, rd, qd, pd, st));
+      TKB(g, kc, 7.0 * F, launch_rbgs_dots<T>(L, 0, rd, qd, pd, st));
     } else {
-      TK(g, kc, launch_rbgs<T>(L, 0, st));
+      TKB(g, kc, 5.0 * F, launch_rbgs<T>(L, 0, st));
     }
   }
 }
@@ -479,7 +536,7 @@ int apply_vcycle(rt_grid* g, const double* r, double* z, bool dots = false) {
     // r is converted (into the colour-split layout) by a pass of its own:
     // read at seven points by the first pair, FP64 r costs more than it saves.
     // The CG's own residual arrives converted by its update.
-    if (g->r32_of != r) TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f_level(L0, r, L0.b, g->st));
+    if (g->r32_of != r) TKB(g, RT_K_MG_TRANSFER, 12.0 * N, launch_cvt_d2f_level(L0, r, L0.b, g->st));
     g->r32_of = r == w.r ? r : nullptr;
     if (dots) {
       vcycle<float>(g, w.L32, 0, g->prm.mg_coarse_sweeps, z, r, w.q, w.parts);
@@ -488,9 +545,9 @@ int apply_vcycle(rt_grid* g, const double* r, double* z, bool dots = false) {
     vcycle<float>(g, w.L32, 0, g->prm.mg_coarse_sweeps, z);
     return 0;
   }
-  TK(g, RT_K_MG_TRANSFER, launch_cvt_d2f(N, r, L0.b, g->st));
+  TKB(g, RT_K_MG_TRANSFER, 12.0 * N, launch_cvt_d2f(N, r, L0.b, g->st));
   vcycle<float>(g, w.L32, 0, g->prm.mg_coarse_sweeps);
-  TK(g, RT_K_MG_TRANSFER, launch_cvt_f2d(N, L0.x, z, g->st));
+  TKB(g, RT_K_MG_TRANSFER, 12.0 * N, launch_cvt_f2d(N, L0.x, z, g->st));
   return 0;
 }
 
@@ -524,14 +581,17 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
   T* bp = reinterpret_cast<T*>(w.bp);
   T* bq = reinterpret_cast<T*>(w.bq);
   g->tk_override = RT_K_BOX;
-  TK(g, RT_K_BOX, launch_box_residual<T>(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, w.pdiag,
-                                         w.cx, w.cy, w.cz, r, z, br, st));
-  TK(g, RT_K_BOX, launch_fill<T>(n, x, T(0), st));
+  const double F = (double)sizeof(T) * n;   // one field over the stacked boxes
+  // r - S z on the box cells: the FP64 operator (4), r and z in, T out
+  TKB(g, RT_K_BOX, 48.0 * n + F,
+      launch_box_residual<T>(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, w.pdiag, w.cx,
+                             w.cy, w.cz, r, z, br, st));
+  TKB(g, RT_K_BOX, F, launch_fill<T>(n, x, T(0), st));
   L0.b = br;   // the box V-cycle maps r -> z in place
   L0.x = bz;
   vcycle<T>(g, Ls, 0, box_cs(g));
   int np = 0;
-  TK(g, RT_K_BOX, np = launch_box_dot1p<T>(n, br, bz, bp, w.bparts, st));
+  TKB(g, RT_K_BOX, 3.0 * F, np = launch_box_dot1p<T>(n, br, bz, bp, w.bparts, st));
   TK(g, RT_K_BOX, launch_final_reduce(w.bparts, np, 1, w.bsc + S_RHO, st));
   // the CG scalars are formed by the kernels that use them (each block sums
   // the partials itself), rho alternates between two slots and p between two
@@ -552,15 +612,20 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
     const int rho = (it & 1) ? S_RHO : S_RHO2, rho_prev = (it & 1) ? S_RHO2 : S_RHO;
     T* p = pb[it & 1];
     const T* p_prev = pb[(it + 1) & 1];
-    TK(g, RT_K_BOX, np = launch_box_spmv_p<T>(L0, bz, p_prev, p, bq, w.bparts, nzp, w.bsc, rho_prev,
-                                              rho, it == 1, w.bparts2, st));
+    // operator (4), z, p_prev in; p, q out
+    TKB(g, RT_K_BOX, (it == 1 ? 7.0 : 8.0) * F,
+        np = launch_box_spmv_p<T>(L0, bz, p_prev, p, bq, w.bparts, nzp, w.bsc, rho_prev, rho,
+                                  it == 1, w.bparts2, st));
     const bool last = it == g->prm.box_inner;
     if (last || !fuse_first) {
-      TK(g, RT_K_BOX, launch_box_update_xr<T>(n, x, rb[ri], p, bq, w.bparts2, np, w.bsc, rho, st));
+      TKB(g, RT_K_BOX, 6.0 * F,
+          launch_box_update_xr<T>(n, x, rb[ri], p, bq, w.bparts2, np, w.bsc, rho, st));
       if (last) break;
     } else {
-      TK(g, RT_K_BOX, launch_box_update_first_pair<T>(L0, x, rb[ri], rb[ri ^ 1], p, bq, w.bparts2,
-                                                      np, w.bsc, rho, st));
+      // x, p, q, r in, x, the new r and the pair's z out, the operator (4)
+      TKB(g, RT_K_BOX, 11.0 * F,
+          launch_box_update_first_pair<T>(L0, x, rb[ri], rb[ri ^ 1], p, bq, w.bparts2, np, w.bsc,
+                                          rho, st));
       ri ^= 1;
     }
     T* r = rb[ri];
@@ -571,18 +636,21 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
     } else {
       vcycle<T>(g, Ls, 0, box_cs(g), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                 fuse_first);
-      TK(g, RT_K_BOX, nzp = launch_box_dot2<T>(n, bz, r, bq, w.bparts, st));
+      TKB(g, RT_K_BOX, 3.0 * F, nzp = launch_box_dot2<T>(n, bz, r, bq, w.bparts, st));
     }
   }
   L0.b = br;
   // boxes may overlap: one launch per box, in source order
   const int nbb = stencil_blocks(B, B, B);
+  // per box: its part of y in, z in and out, with the dots r and q in
+  const double Fb = (double)B * B * B;
   for (int s = 0; s < g->nbox; ++s)
-    TK(g, RT_K_BOX, launch_box_scatter_add<T>(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells,
-                                              s, x, z, r, w.q,
-                                              dots > 0 ? w.parts + (size_t)(dots + s * nbb) * NCOMP_MAX
-                                                       : nullptr,
-                                              st));
+    TKB(g, RT_K_BOX, Fb * (sizeof(T) + 16.0 + (dots > 0 ? 16.0 : 0.0)),
+        launch_box_scatter_add<T>(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, s, x, z, r,
+                                  w.q,
+                                  dots > 0 ? w.parts + (size_t)(dots + s * nbb) * NCOMP_MAX
+                                           : nullptr,
+                                  st));
   g->tk_override = -1;
 }
 
@@ -602,12 +670,15 @@ int capture_box(rt_grid* g, rt_grid::BoxGraph& bg, const double* r, double* z, i
   const bool timing = g->tm.on;
   g->tm.on = false;   // no event records inside the graph
   g->st = g->cap_st;
+  g->capturing = true;
+  g->cap_bytes = 0.0;
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     box_correct_launches(g, r, z, dots);
     e = hipStreamEndCapture(g->st, &graph);
   }
+  g->capturing = false;
   g->st = caller;
   g->tm.on = timing;
   if (e == hipSuccess) e = hipGraphInstantiate(&bg.exec, graph, nullptr, nullptr, 0);
@@ -624,6 +695,7 @@ int capture_box(rt_grid* g, rt_grid::BoxGraph& bg, const double* r, double* z, i
   bg.z = z;
   bg.nbox = g->nbox;
   bg.dots = dots;
+  bg.bytes = g->cap_bytes;
   return RT_OK;
 }
 
@@ -638,7 +710,7 @@ int box_correct(rt_grid* g, const double* r, double* z, int dots) {
   if (!bg.exec || bg.r != r || bg.z != z || bg.nbox != g->nbox || bg.dots != dots)
     RTCHK(capture_box(g, bg, r, z, dots));
   hipError_t e = hipSuccess;
-  TK(g, RT_K_BOX, e = hipGraphLaunch(bg.exec, g->st));
+  TKB(g, RT_K_BOX, bg.bytes, e = hipGraphLaunch(bg.exec, g->st));
   HIPCHK(g, e);
   return RT_OK;
 }
@@ -679,13 +751,14 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   const int nparts = reduce_blocks(N);
   RTCHK(build_hierarchy(g));
   double h[2];
-  TK(g, RT_K_CG_VECTOR, launch_dot1(N, b, b, w.parts, g->st, w.r));   // and r = b
+  const double F = 8.0 * N;
+  TKB(g, RT_K_CG_VECTOR, 2.0 * F, launch_dot1(N, b, b, w.parts, g->st, w.r));   // and r = b
   g->r32_of = nullptr;
   finish_reduce(g, nparts, 1, S_BB);
   RTCHK(read_scalars(g, w.sc + S_BB, h, 1));
   const double bn = std::sqrt(h[0]);
   const double thr = std::max(rtol * bn, atol);
-  TK(g, RT_K_CG_VECTOR, launch_fill<double>(N, x, 0.0, g->st));
+  TKB(g, RT_K_CG_VECTOR, F, launch_fill<double>(N, x, 0.0, g->st));
   *iters = 0;
   *relres = 0.0;
   if (!(bn > 0.0)) {
@@ -696,7 +769,7 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   int nd = 0;
   RTCHK(apply_precond(g, w.r, w.z, false, &nd));
   ++*vcycles;
-  TK(g, RT_K_CG_VECTOR, launch_dot1(N, w.r, w.z, w.parts, g->st, w.p));   // and p = z
+  TKB(g, RT_K_CG_VECTOR, 3.0 * F, launch_dot1(N, w.r, w.z, w.parts, g->st, w.p));   // and p = z
   finish_reduce(g, nparts, 1, S_RHO);
   // The tail of an iteration (V-cycle, dots, new direction) writes only z, p
   // and CG scalars, so it can be enqueued before this iteration's residual
@@ -710,24 +783,27 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   auto tail = [&]() -> int {
     RTCHK(apply_precond(g, w.r, w.z, true, &nd));
     ++*vcycles;
-    if (nd == 0) TK(g, RT_K_CG_VECTOR, launch_dot2(N, w.z, w.r, w.q, w.parts, g->st));
+    if (nd == 0) TKB(g, RT_K_CG_VECTOR, 3.0 * F, launch_dot2(N, w.z, w.r, w.q, w.parts, g->st));
     TK(g, RT_K_REDUCE, launch_final_reduce_beta(w.parts, nd > 0 ? nd : nparts, w.sc, g->st));
-    TK(g, RT_K_CG_VECTOR, launch_update_p(N, w.p, w.z, w.sc, g->st));
+    TKB(g, RT_K_CG_VECTOR, 3.0 * F, launch_update_p(N, w.p, w.z, w.sc, g->st));
     return RT_OK;
   };
   double rn = bn, rn_prev = 0.0;
   int k = 0;
   for (k = 1; k <= maxit; ++k) {
     const double pred = k > 1 ? rn * (rn / rn_prev) : (g->cg_rate1 > 0.0 ? bn * g->cg_rate1 : HUGE_VAL);
-    TK(g, RT_K_SPMV, launch_spmv_dot(g->P.nx, g->P.ny, g->P.nz, w.pdiag, w.cx, w.cy, w.cz, w.p, w.q, w.parts, g->st));
+    TKB(g, RT_K_SPMV, 6.0 * F,
+        launch_spmv_dot(g->P.nx, g->P.ny, g->P.nz, w.pdiag, w.cx, w.cy, w.cz, w.p, w.q, w.parts,
+                        g->st));
     TK(g, RT_K_REDUCE, launch_final_reduce_alpha(w.parts, stencil_blocks(g->P.nx, g->P.ny, g->P.nz),
                                                  w.sc, g->st));
     if (fp32_fused(&g->prm)) {
-      TK(g, RT_K_CG_VECTOR, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st,
-                                             w.L32[0].b, g->P.ny, g->P.nz));
+      TKB(g, RT_K_CG_VECTOR, 6.5 * F,
+          launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st, w.L32[0].b, g->P.ny,
+                           g->P.nz));
       g->r32_of = w.r;
     } else {
-      TK(g, RT_K_CG_VECTOR, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st));
+      TKB(g, RT_K_CG_VECTOR, 6.0 * F, launch_update_xr(N, x, w.r, w.p, w.q, w.sc, w.parts, g->st));
     }
     finish_reduce(g, nparts, 1, S_RR);
     HIPCHK(g, hipMemcpyAsync(g->hpin, w.sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, g->st));
@@ -769,12 +845,13 @@ int fgmres(rt_grid* g, const double* b, double* x, double rtol, double atol, int
   const int nparts = reduce_blocks(N);
   RTCHK(build_hierarchy(g));
   double* hp = g->hpin;
-  TK(g, RT_K_CG_VECTOR, launch_dot1(N, b, b, w.parts, g->st));
+  const double F = 8.0 * N;   // bytes of one FP64 field
+  TKB(g, RT_K_CG_VECTOR, F, launch_dot1(N, b, b, w.parts, g->st));
   finish_reduce(g, nparts, 1, S_BB);
   RTCHK(read_scalars(g, w.sc + S_BB, hp, 1));
   const double bn = std::sqrt(hp[0]);
   const double thr = std::max(rtol * bn, atol);
-  TK(g, RT_K_CG_VECTOR, launch_fill<double>(N, x, 0.0, g->st));
+  TKB(g, RT_K_CG_VECTOR, F, launch_fill<double>(N, x, 0.0, g->st));
   *iters = 0;
   *relres = 0.0;
   if (!(bn > 0.0)) {
@@ -788,7 +865,8 @@ int fgmres(rt_grid* g, const double* b, double* x, double rtol, double atol, int
   const bool fixed = g->nbox > 0;
   float* r32 = fp32_fused(&g->prm) ? w.L32[0].b : nullptr;
   auto normalise = [&](double* v, double sf) {
-    TK(g, RT_K_CG_VECTOR, launch_scale(N, v, sf, fixed ? w.r : nullptr, r32, P.ny, P.nz, g->st));
+    TKB(g, RT_K_CG_VECTOR, 2.0 * F + (fixed ? F : 0.0) + (r32 ? 0.5 * F : 0.0),
+        launch_scale(N, v, sf, fixed ? w.r : nullptr, r32, P.ny, P.nz, g->st));
     g->r32_of = r32 ? (fixed ? w.r : v) : nullptr;
   };
   std::vector<double> H((size_t)m * (m + 1)), cs(m), sn(m), gv(m + 1), y(m);
@@ -802,8 +880,9 @@ int fgmres(rt_grid* g, const double* b, double* x, double rtol, double atol, int
       HIPCHK(g, hipMemcpyAsync(w.V, b, N * sizeof(double), hipMemcpyDeviceToDevice, g->st));
     } else {
       int nb = 0;
-      TK(g, RT_K_SPMV, nb = launch_spmv_full(P.nx, P.ny, P.nz, w.diag, w.fw, w.bw, x, b, w.V,
-                                             nullptr, w.V, 0, w.gparts, g->st));
+      TKB(g, RT_K_SPMV, 10.0 * F,
+          nb = launch_spmv_full(P.nx, P.ny, P.nz, w.diag, w.fw, w.bw, x, b, w.V, nullptr, w.V, 0,
+                                w.gparts, g->st));
       TK(g, RT_K_REDUCE, launch_final_multi(w.gparts, nb, 1, w.gh, g->st));
       RTCHK(read_scalars(g, w.gh, hp, 1));
       beta = std::sqrt(hp[0]);
@@ -823,11 +902,12 @@ int fgmres(rt_grid* g, const double* b, double* x, double rtol, double atol, int
       RTCHK(apply_precond(g, fixed ? w.r : vj, fixed ? w.z : zj, false, &nd));
       ++*vcycles;
       int nb = 0;
-      TK(g, RT_K_SPMV, nb = launch_spmv_full(P.nx, P.ny, P.nz, w.diag, w.fw, w.bw,
-                                             fixed ? w.z : zj, nullptr, vn, fixed ? zj : nullptr,
-                                             w.V, j + 1, w.gparts, g->st));
+      TKB(g, RT_K_SPMV, (9.0 + (j + 1) + (fixed ? 1.0 : 0.0)) * F,
+          nb = launch_spmv_full(P.nx, P.ny, P.nz, w.diag, w.fw, w.bw, fixed ? w.z : zj, nullptr,
+                                vn, fixed ? zj : nullptr, w.V, j + 1, w.gparts, g->st));
       TK(g, RT_K_REDUCE, launch_final_multi(w.gparts, nb, j + 2, w.gh, g->st));
-      TK(g, RT_K_CG_VECTOR, nb = launch_gs_pass(N, vn, w.V, j + 1, w.gh, 1, w.gparts, g->st));
+      TKB(g, RT_K_CG_VECTOR, (j + 3.0) * F,
+          nb = launch_gs_pass(N, vn, w.V, j + 1, w.gh, 1, w.gparts, g->st));
       TK(g, RT_K_REDUCE, launch_final_multi(w.gparts, nb, j + 2, w.gh + KMAX, g->st));
       HIPCHK(g, hipMemcpyAsync(hp, w.gh, 2 * KMAX * sizeof(double), hipMemcpyDeviceToHost, g->st));
       HIPCHK(g, hipStreamSynchronize(g->st));
@@ -837,7 +917,8 @@ int fgmres(rt_grid* g, const double* b, double* x, double rtol, double atol, int
       double hn = std::sqrt(hp[KMAX + j + 1]);
       if (hn < REORTH * wn) {
         for (int i = 0; i <= j; ++i) h[i] += hp[KMAX + i];
-        TK(g, RT_K_CG_VECTOR, nb = launch_gs_pass(N, vn, w.V, j + 1, w.gh + KMAX, 0, w.gparts, g->st));
+        TKB(g, RT_K_CG_VECTOR, (j + 3.0) * F,
+            nb = launch_gs_pass(N, vn, w.V, j + 1, w.gh + KMAX, 0, w.gparts, g->st));
         TK(g, RT_K_REDUCE, launch_final_multi(w.gparts, nb, 1, w.gh + 2 * KMAX, g->st));
         RTCHK(read_scalars(g, w.gh + 2 * KMAX, hp, 1));
         hn = std::sqrt(hp[0]);
@@ -872,7 +953,7 @@ int fgmres(rt_grid* g, const double* b, double* x, double rtol, double atol, int
     }
     for (int i = 0; i < k; ++i) hp[i] = y[i];
     HIPCHK(g, hipMemcpyAsync(w.gy, hp, k * sizeof(double), hipMemcpyHostToDevice, g->st));
-    TK(g, RT_K_CG_VECTOR, launch_combine(N, x, w.Z, k, w.gy, g->st));
+    TKB(g, RT_K_CG_VECTOR, (k + 2.0) * F, launch_combine(N, x, w.Z, k, w.gy, g->st));
     // the host buffer is reused by the next read-back: the copy must be done
     HIPCHK(g, hipStreamSynchronize(g->st));
     if (done) break;
@@ -899,10 +980,14 @@ int time_level(rt_grid* g, const double* Un, double dt, const rt_cosmo* c, doubl
   const DevParams& P = g->P;
   // the limiter at U^n: for the explicit part, and for the whole step with
   // the lagged reading
+  // faces: E and the fractions, n_H in, D (3) out; explicit part: U, n_H,
+  // e_h, D in, g out
   if (P.theta != 1.0 || g->prm.limiter_lag)
-    TK(g, RT_K_TIMELEVEL, launch_faces(P, Un, g->nH, c->a_old, g->w.D, g->st));
+    TKB(g, RT_K_TIMELEVEL, (P.nb + 4.0) * 8.0 * P.N,
+        launch_faces(P, Un, g->nH, c->a_old, g->w.D, g->st));
   if (P.theta != 1.0) {
-    TK(g, RT_K_TIMELEVEL, launch_explicit(P, Un, g->nH, g->eh, g->w.D, Step{dt, c->a_old, c->H_old}, gn, g->st));
+    TKB(g, RT_K_TIMELEVEL, (2.0 * P.nv + 5.0) * 8.0 * P.N,
+        launch_explicit(P, Un, g->nH, g->eh, g->w.D, Step{dt, c->a_old, c->H_old}, gn, g->st));
   } else {
     HIPCHK(g, hipMemcpyAsync(gn, Un, (size_t)P.nv * P.N * sizeof(double),
                              hipMemcpyDeviceToDevice, g->st));
@@ -918,7 +1003,8 @@ int time_level(rt_grid* g, const double* Un, double dt, const rt_cosmo* c, doubl
 int residual_norm(rt_grid* g, const double* U, const double* gn, Step s, double* f, double* fn,
                   double* viol) {
   const DevParams& P = g->P;
-  TK(g, RT_K_RESIDUAL, launch_residual(P, U, gn, g->nH, g->eh, lagged_D(g), s, f, g->w.parts, g->st));
+  TKB(g, RT_K_RESIDUAL, (3.0 * P.nv + 2.0 + (g->prm.limiter_lag ? 3.0 : 0.0)) * 8.0 * P.N,
+      launch_residual(P, U, gn, g->nH, g->eh, lagged_D(g), s, f, g->w.parts, g->st));
   finish_reduce(g, stencil_blocks(P.nx, P.ny, P.nz), 2, S_FN);
   double h[2];
   RTCHK(read_scalars(g, g->w.sc + S_FN, h, 2));
@@ -980,26 +1066,7 @@ int rt_create_grid(const rt_params* p, void* d_ws, uint64_t ws_bytes, void* hip_
   g->prm = *p;
   g->st = reinterpret_cast<hipStream_t>(hip_stream);
   carve(p, base, &g->w);
-  DevParams& P = g->P;
-  P.nx = p->nx; P.ny = p->ny; P.nz = p->nz;
-  P.ns = p->nspecies; P.nv = p->nspecies + 2; P.nb = p->nspecies + 1;
-  P.kap_lte = p->kappa_lte; P.kapP_lte = p->kappaP_lte; P.mu_lte = p->mu_lte;
-  P.bc = p->boundary;
-  P.Eb = p->E_dirichlet;
-  P.N = p->nx * p->ny * p->nz;
-  P.iso = p->isothermal; P.lim_mode = p->limiter_mode;
-  P.dx = p->dx; P.theta = p->theta; P.u_e = p->u_e; P.u_E = p->u_E;
-  P.m = p->grey ? 1.0 : 0.0; P.y = p->y_he; P.T_iso = p->T_iso; P.D0 = p->D0;
-  for (int s = 0; s < 3; ++s) {
-    P.Kg[s] = p->K_gamma[s]; P.Kk[s] = p->K_kappa[s]; P.Kh[s] = p->K_heat[s];
-  }
-  if (p->nspecies == 1) {
-    for (int s = 1; s < 3; ++s) P.Kg[s] = P.Kk[s] = P.Kh[s] = 0.0;
-  }
-  P.hnu = p->hnu_mean;
-  P.alpha0[0] = 2.59e-13;                            // case-B HII at 1e4 K
-  P.alpha0[1] = 2.72e-13;                            // HeII (placeholder datum)
-  P.alpha0[2] = 2.0 * 2.59e-13 * std::pow(4.0, 0.7); // HeIII, hydrogenic Z = 2
+  fill_params(p, g->P);
   if (hipHostMalloc(reinterpret_cast<void**>(&g->hpin), 3 * KMAX * sizeof(double),
                     hipHostMallocDefault) !=
           hipSuccess ||
@@ -1245,7 +1312,13 @@ int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_
   int k = 0;
   int status = RT_OK;
   while (fn >= g->prm.newton_tol && k < g->prm.newton_maxit) {
-    TK(g, RT_K_SCHUR, schur_into_workspace(g, cur, w.f, s, w.b));
+    // local: U, f, n_H, e_h in; f~_M, W, loc, b, om, ph out.  faces: E and the
+    // fractions, n_H, loc, om, ph, b in; diag, pdiag, c (3), fw (3), bw (3),
+    // b out (+ the FP32 copies of pdiag and c)
+    TKB(g, RT_K_SCHUR,
+        ((2.0 * P.nv + 2.0 + 2.0 * P.nb + 4.0) + (P.ns + 1.0 + 5.0 + 12.0 +
+         (g->prm.limiter_lag ? 3.0 : 0.0)) + (g->prm.mg_fp32 ? 2.0 : 0.0)) * 8.0 * P.N,
+        schur_into_workspace(g, cur, w.f, s, w.b));
     int its = 0, vc = 0;
     double rr = 0;
     // ||J S + f||_2 equals the Schur residual norm (the local rows are solved
@@ -1259,7 +1332,8 @@ int rt_newton_step(rt_grid* g, const double* d_Un, double* d_U, const double* d_
     double lam = 1.0, ftn = 0.0;
     bool ok = false;
     while (status == RT_OK) {
-      TK(g, RT_K_TRIAL, launch_trial(P, cur, w.ftM, w.W, w.x, lam, spare, g->st));
+      TKB(g, RT_K_TRIAL, (2.0 * P.nv + 2.0 * P.nb + 1.0) * 8.0 * P.N,
+          launch_trial(P, cur, w.ftM, w.W, w.x, lam, spare, g->st));
       status = residual_norm(g, spare, w.g, s, w.ft, &ftn, &viol);
       if (status != RT_OK) break;
       ++st.ls_trials;
@@ -1307,6 +1381,7 @@ int rt_timing(rt_grid* g, int32_t enable, rt_kernel_timing* out) {
     t.on = true;
     t.used = 0;
     t.cls.clear();
+    for (double& b : t.bytes) b = 0.0;
     return RT_OK;
   }
   t.on = false;
@@ -1319,6 +1394,7 @@ int rt_timing(rt_grid* g, int32_t enable, rt_kernel_timing* out) {
       out->count[t.cls[i]] += 1;
       out->total_ms[t.cls[i]] += ms;
     }
+    for (int c = 0; c < RT_K_COUNT; ++c) out->bytes[c] = t.bytes[c];
   }
   t.used = 0;
   t.cls.clear();

@@ -178,7 +178,9 @@ CFG_HHE = Workload(
 # 1e4 K, the single 5e48 photons/s source of Sec. 4.5, E = 1e-35 erg/cm^3 and
 # no ionization at the start; Einstein-de Sitter expansion from a = 0.2.  The
 # paper's 80 kpc (proper at z_i) box, periodic with a centred source, 50
-# steps of 2e15 s (to z = 1.08, while the front stays inside the box).
+# steps of 2e15 s (to z = 1.08, while the front stays inside the box).  A
+# step spans thousands of light-crossings of a cell: the limiter is held at
+# time level n (as for the expanding lognormal medium).
 _A_SG = 0.2
 _M_H_G = 1.6735575e-24       # g per hydrogen atom (input conversion only)
 _DT_SG = 2.0e15
@@ -186,7 +188,7 @@ CFG_SG = Workload(
     name="sg_q05_z4", n=128, dx=80.0 * KPC_CM / _A_SG / 128, dt=_DT_SG, steps=50,
     nH_mean=1.175e-28 / _M_H_G * _A_SG ** 3, x0=(1.0,), E0=1.0e-35 * _A_SG ** 3,
     u_E=1.0e-20 * _A_SG ** 3, isothermal=1, T_iso=1.0e4, a_start=_A_SG,
-    a_end=eds_scale_factor(eds_time(_A_SG) + 50 * _DT_SG), mg_levels=4)
+    a_end=eds_scale_factor(eds_time(_A_SG) + 50 * _DT_SG), mg_levels=4, limiter_lag=1)
 
 # Matter-radiation equilibration of Sec. 4.2 (LTE coupling, Eq. 9): a uniform
 # medium of one opacity 4e-8 /cm (absorption and Planck mean), density

@@ -40,7 +40,10 @@ def state_floors(m):
 
 
 def workload(ns, n, theta=1.0, a=1.0, levels=2, **kw):
+    """Random-state cases: the limiter at the iterate unless kw asks for the
+    lagged reading."""
     base = synth.CFG_SMALL if ns == 1 else synth.CFG_HHE
+    kw.setdefault("limiter_lag", 0)
     w = base.replace(n=n, theta=theta, mg_levels=levels, a_start=a, a_end=None,
                      u_E=1e-20 * a ** 3, E0=1e-20 * a ** 3, nH_mean=1e-3 * a ** 3, **kw)
     return w

@@ -1,10 +1,9 @@
-"""Host-side logic of bench.py (no GPU): the one-GPU guard and the
-algorithmic byte model behind roofline.achieved."""
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the CPU
+baseline leg and the traffic table (the algorithmic byte counts behind
+roofline.achieved are the library's own, checked on the GPU)."""
 import os
 import subprocess
 import sys
-
-import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -17,23 +16,21 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU only" in out.stdout + out.stderr
 
 
-def test_smoother_class_bytes_v22_fp32():
-    """V(2,2) in FP32 with the CG dots: first pair 6w, five half-sweeps 5w,
-    the last half-sweep 4w + 24 B: 7 launches, 393 MB per launch at 256^3."""
-    launches, b = bench.rbgs_fine_per_vcycle(2, 2, 4.0)
-    assert launches == 7
-    assert b == 6 * 4 + 5 * 5 * 4 + (4 * 4 + 24)
-    assert round(b / launches * 256 ** 3) == 393066203
+def test_cpu_baseline_fields():
+    """The oracle leg reports cell-updates/s on all host cores and on one,
+    with the core count and the sample it timed (a tiny grid here)."""
+    cb = bench.cpu_baseline(16)
+    assert cb["kind"] == "oracle" and cb["unit"] == "cell-updates/s"
+    assert cb["cores"] == bench.host_cores() >= 1
+    assert cb["value"] > 0 and "16^3" in cb["sample"] and "status 0" in cb["sample"]
+    if cb["cores"] > 1:
+        assert cb["one_core"]["value"] > 0
 
 
-@pytest.mark.parametrize("pre,post", [(1, 1), (2, 2), (3, 1)])
-def test_smoother_class_bytes_fp64(pre, post):
-    launches, b = bench.rbgs_fine_per_vcycle(pre, post, 8.0)
-    assert launches == 1 + 2 * (pre - 1) + 2 * post
-    assert b == 6 * 8 + (launches - 1) * 5 * 8
-
-
-def test_schur_bytes_by_precision():
-    assert bench.class_bytes_per_cell("schur", 8.0) == 160.0
-    assert bench.class_bytes_per_cell("schur", 4.0) == 176.0
-    assert bench.class_bytes_per_cell("residual", 4.0) == 112.0
+def test_traffic_is_null_for_other_kernel_sources():
+    """A PMC traffic figure is reported only for the kernel source it was
+    measured on."""
+    sha = bench.kernels_sha256()
+    assert len(sha) == 64
+    for key, tr in bench.PMC_TRAFFIC.items():
+        assert len(key) == 3 and tr["bytes_per_launch"] > 0

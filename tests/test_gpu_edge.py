@@ -91,8 +91,10 @@ def test_invalid_calls():
         g.rt_set_sources([32 ** 3], [1e48])                   # cell out of range
     with pytest.raises(RtError):
         g.rt_set_sources(list(range(100)), [1e48] * 100)      # beyond max_sources
+    gl = RtGrid(params_from_workload(w.replace(limiter_lag=1)))
+    gl.rt_set_medium(nH, nH.clone())
     with pytest.raises(RtError):
-        g.rt_eval_residual(U, U, w.dt, w.cosmology(0))        # no time level yet
+        gl.rt_eval_residual(U, U, w.dt, w.cosmology(0))       # lagged limiter: no time level yet
     with pytest.raises(RtError):
         g.rt_mg_vcycle(nH)                                    # no Schur matrix yet
     with pytest.raises(RtError) as e:

@@ -92,6 +92,33 @@ def test_schur_form(ns, n, theta, a, seed):
     assert rel(b, sch["b"]) <= 1e-12
 
 
+@pytest.mark.parametrize("ns,n,theta,a,seed", CASES[1:4])
+def test_schur_form_lagged(ns, n, theta, a, seed):
+    """The lagged reading: residual and Schur set-up with the face
+    coefficients of time level n (symmetric S = the preconditioner's)."""
+    w, c = random_case(ns, n, theta, a, seed, limiter_lag=1)
+    m, g = pair(w, c)
+    cos = c["cosmo"]
+    tl = ores.time_level(c["Un"], c["nH"], c["eh"], c["cells"], c["Q"], c["dt"], cos, m)
+    f_o = ores.residual(c["U"], tl, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m)
+    sch = ojac.schur_form(c["U"], f_o, c["nH"], c["eh"], c["dt"], cos[2], cos[3], m, tl["D"])
+    gn = g.rt_time_level(dev(c["Un"]), c["dt"], cos)
+    f, _ = g.rt_eval_residual(dev(c["U"]), gn, c["dt"], cos)
+    for v in range(m.nv):
+        s = scale_of(f_o[v], c["U"][v] / m.scales[v], tl["g"][v] / m.scales[v])
+        assert rel(host(f)[v], f_o[v], s) <= 1e-12, v
+    b = host(g.rt_schur_form(dev(c["U"]), dev(f_o), c["dt"], cos))
+    got = {k: host(v) for k, v in g.rt_schur_get().items()}
+    full = {k: host(v) for k, v in g.rt_schur_get_full().items()}
+    scale = scale_of(sch["diag"])
+    for k in ("diag", "cx", "cy", "cz"):
+        assert rel(got[k], sch[k], scale) <= 1e-12, k
+    assert np.array_equal(full["pdiag"], got["diag"])
+    for d in range(3):
+        assert np.array_equal(full["fw"][d], full["bw"][d])
+    assert rel(b, sch["b"]) <= 1e-12
+
+
 @pytest.mark.parametrize("n,levels", [(16, 3), (32, 3), (32, 4)])
 def test_vcycle(n, levels):
     w, c = random_case(1, n, 1.0, 1.0, 21, levels=levels)
@@ -320,11 +347,6 @@ def test_newton_steps_reflecting_corner():
     newton_parity(w, synth.initial_state(w), steps=3)
 
 
-def test_newton_steps_reflecting_corner_live():
-    """The same geometry with the limiter at the iterate: its first two steps."""
-    w = synth.CFG_256.replace(n=32, mg_levels=3, boundary=1, corner_source=True)
-    newton_parity(w, synth.initial_state(w), steps=2)
-
 
 def test_newton_steps_reflecting_lognormal_boxes():
     """Reflecting walls with the lognormal medium, 16 sources and overlapping
@@ -332,3 +354,26 @@ def test_newton_steps_reflecting_lognormal_boxes():
     w = synth.CFG_COSMO.replace(n=32, mg_levels=3, boundary=1, box_size=8, box_levels=2,
                                 box_inner=3)
     newton_parity(w, synth.initial_state(w), steps=2)
+
+
+def test_algorithmic_byte_counts():
+    """The library's per-class algorithmic byte counts, for the two classes
+    whose launches a fixed-count FGMRES solve fixes: k products from x = 0
+    (no restart, no subdomain correction), product j reading the operator
+    (7 fields), z_j and basis vectors 0..j and writing w (10 + j fields); and
+    k FP64 V-cycles, whose finest smoothing with V(pre, post) reads and writes
+    6 fields for the first (red, black) pair from zero and 5 per further
+    half-sweep."""
+    m, g, sch = schur_case(32, 3, 31)
+    p = g.params
+    N = 32 ** 3
+    k = 5
+    g.rt_timing(True)
+    s, its, rr = g.rt_mg_pcg_solve(dev(sch["b"]), 0.0, k)
+    t = g.rt_timing(False)
+    assert its == k and p.mg_fp32 == 0 and p.mg_pre > 0
+    assert t["spmv"][0] == k
+    assert t["spmv"][2] == sum(10 + j for j in range(k)) * 8.0 * N
+    half_sweeps = 2 * (p.mg_pre - 1) + 2 * p.mg_post
+    assert t["rbgs_fine"][0] == k * (1 + half_sweeps)
+    assert t["rbgs_fine"][2] == k * (6 + 5 * half_sweeps) * 8.0 * N
