@@ -43,6 +43,7 @@
 #ifndef RT_H
 #define RT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -179,6 +180,34 @@ int rt_time_level(rt_grid* g, const double* d_Un, double dt, const rt_cosmo* c,
  * the time-level coefficients). */
 int rt_eval_residual(rt_grid* g, const double* d_U, const double* d_gn, double dt,
                      const rt_cosmo* c, double* d_f, double* h_rms);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual of rt_eval_residual without a grid or workspace, bit-identical to
+ * it for the same parameters, medium and time-level data.  It calls no
+ * hipMalloc, hipFree or allocating library routine: the reduction partials
+ * and sums live in a static device array of 16 MiB + 256 B (NCOMP 4 x 2^19
+ * block partials), which each GPU the library runs on holds until the
+ * process ends; its device address is looked up once per device with
+ * hipGetSymbolAddress on the first call (with that device current).
+ *   p       grid parameters, as for rt_create_grid (limiter_lag must be 0:
+ *           the lagged reading needs a grid's time-level coefficients)
+ *   d_nH, d_eh [N], d_U, d_gn [nv][N]  device inputs as for rt_set_medium,
+ *           rt_eval_residual (d_gn from rt_time_level of a grid, or the
+ *           caller's own g^n of Eqs. 22-24)
+ *   hip_stream  hipStream_t of the current device (NULL: default stream)
+ *   d_f [nv][N]  device output, scaled residual
+ *   h_rms   host output, RMS norm of Eq. 30 (NULL: none, and no host sync)
+ *   err, err_len  optional host buffer for the message of a failure
+ * Returns RT_EINVAL (message in err) for invalid parameters, the lagged
+ * reading, null pointers or a grid whose partials exceed the array (more
+ * than 2^19 stencil blocks: larger than 512^3); RT_EDEVICE for HIP errors.
+ * All calls on one GPU share its array and keep the last call's contents:
+ * calls that overlap on one GPU (other threads, other streams) race. */
+int rt_eval_residual_noalloc(const rt_params* p, const double* d_nH, const double* d_eh,
+                             const double* d_U, const double* d_gn, double dt,
+                             const rt_cosmo* c, void* hip_stream, double* d_f, double* h_rms,
+                             char* err, size_t err_len);
 
 /* Cell-local Newton blocks (Sec. 3.2.1, Eqs. 31-34) in scaled variables:
  * d_M [nb][nb][N] = I + dt theta J_MM (row-major per cell),

@@ -98,6 +98,9 @@ SIGNATURES = {
     "rt_set_sources": [_P, _I, _P, _P],
     "rt_time_level": [_P, _P, _D, ctypes.POINTER(RtCosmo), _P],
     "rt_eval_residual": [_P, _P, _P, _D, ctypes.POINTER(RtCosmo), _P, ctypes.POINTER(_D)],
+    "rt_eval_residual_noalloc": [ctypes.POINTER(RtParams), _P, _P, _P, _P, _D,
+                                 ctypes.POINTER(RtCosmo), _P, _P, ctypes.POINTER(_D),
+                                 ctypes.c_char_p, ctypes.c_size_t],
     "rt_local_jacobian": [_P, _P, _D, ctypes.POINTER(RtCosmo), _P, _P, _P, _P],
     "rt_schur_form": [_P, _P, _P, _D, ctypes.POINTER(RtCosmo), _P],
     "rt_schur_get": [_P, _P, _P, _P, _P, _P, _P],
@@ -217,6 +220,25 @@ def params_from_workload(w, **overrides) -> RtParams:
 
 def cosmo(c) -> RtCosmo:
     return RtCosmo(*[float(v) for v in c])
+
+
+def eval_residual_noalloc(params: RtParams, nH, eh, U, gn, dt, c, f=None, norm=True,
+                          stream=None):
+    """rt_eval_residual_noalloc: the residual (and its RMS norm) without a
+    grid or workspace; f is allocated here only when not given."""
+    f = torch.empty_like(U) if f is None else f
+    st = stream if stream is not None else torch.cuda.current_stream(U.device)
+    cc = cosmo(c)
+    r = ctypes.c_double()
+    msg = ctypes.create_string_buffer(512)
+    status = lib().rt_eval_residual_noalloc(ctypes.byref(params), _ptr(nH), _ptr(eh), _ptr(U),
+                                            _ptr(gn), float(dt), ctypes.byref(cc),
+                                            ctypes.c_void_p(st.cuda_stream), _ptr(f),
+                                            ctypes.byref(r) if norm else None, msg,
+                                            len(msg))
+    if status != RT_OK:
+        raise RtError(status, "rt_eval_residual_noalloc: %s" % msg.value.decode())
+    return f, (r.value if norm else None)
 
 
 class RtGrid:

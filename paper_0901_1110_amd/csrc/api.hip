@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -1041,6 +1042,61 @@ void schur_into_workspace(rt_grid* g, const double* U, const double* f, Step s, 
 }  // namespace
 
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// allocation-free residual: the block partials and the final sums of the
+// residual norm live in a static device array instead of a grid's workspace.
+// Every call on one GPU uses that GPU's copy; the reductions overwrite every
+// slot they read (each block writes its partial, the final reduction its
+// sums), so nothing has to start at zero.  Calls that overlap on one GPU race.
+
+namespace {
+constexpr long NOALLOC_MAX_BLOCKS = 1L << 19;   // the partials of a 512^3 grid
+constexpr size_t NOALLOC_SUMS = (size_t)NOALLOC_MAX_BLOCKS * NCOMP_MAX;
+constexpr size_t NOALLOC_DOUBLES = NOALLOC_SUMS + 32;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+
+std::mutex scratch_mu;
+double* scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int noalloc_fail(char* err, size_t len, int code, const char* fmt, ...) {
+  if (err && len > 0) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(err, len, fmt, ap);
+    va_end(ap);
+  }
+  return code;
+}
+
+// the device address of the current device's copy of `scratch`, looked up
+// once per device (the host-side name is not a device address)
+int scratch_on_device(double** out, char* err, size_t len) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return noalloc_fail(err, len, RT_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return noalloc_fail(err, len, RT_EDEVICE, "device %d beyond the %d supported", dev,
+                        NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return noalloc_fail(err, len, RT_EDEVICE, "hipGetSymbolAddress(scratch): %s",
+                          hipGetErrorString(e));
+    scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = scratch_ptr[dev];
+  return RT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int rt_workspace_bytes(const rt_params* p, uint64_t* bytes) {
@@ -1175,6 +1231,45 @@ int rt_eval_residual(rt_grid* g, const double* d_U, const double* d_gn, double d
                     g->st);
   }
   HIPCHK(g, hipGetLastError());
+  return RT_OK;
+}
+
+int rt_eval_residual_noalloc(const rt_params* p, const double* d_nH, const double* d_eh,
+                             const double* d_U, const double* d_gn, double dt, const rt_cosmo* c,
+                             void* hip_stream, double* d_f, double* h_rms, char* err,
+                             size_t err_len) {
+  std::string why;
+  if (validate(p, &why) != RT_OK)
+    return noalloc_fail(err, err_len, RT_EINVAL, "invalid parameters: %s", why.c_str());
+  if (p->limiter_lag)
+    return noalloc_fail(err, err_len, RT_EINVAL,
+                        "limiter_lag = 1 needs a grid's time-level face coefficients "
+                        "(rt_time_level, rt_eval_residual)");
+  const long blocks = stencil_blocks(p->nx, p->ny, p->nz);
+  if (blocks > NOALLOC_MAX_BLOCKS)
+    return noalloc_fail(err, err_len, RT_EINVAL,
+                        "grid %dx%dx%d needs %ld partial sums; the static scratch holds %ld "
+                        "(grids up to 512^3 cells)",
+                        p->nx, p->ny, p->nz, blocks, NOALLOC_MAX_BLOCKS);
+  if (!d_nH || !d_eh || !d_U || !d_gn || !d_f || !c)
+    return noalloc_fail(err, err_len, RT_EINVAL, "null argument");
+  double* scr = nullptr;
+  RTCHK(scratch_on_device(&scr, err, err_len));
+  DevParams P;
+  fill_params(p, P);
+  const hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  launch_residual(P, d_U, d_gn, d_nH, d_eh, nullptr, Step{dt, c->a_new, c->H_new}, d_f, scr, st);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && h_rms) {
+    launch_final_reduce(scr, (int)blocks, 2, scr + NOALLOC_SUMS, st);
+    double h[2] = {0.0, 0.0};
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h, scr + NOALLOC_SUMS, 2 * sizeof(double),
+                                            hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) *h_rms = std::sqrt(h[0] / ((double)P.N * P.nv));
+  }
+  if (e != hipSuccess) return noalloc_fail(err, err_len, RT_EDEVICE, "HIP: %s", hipGetErrorString(e));
   return RT_OK;
 }
 
