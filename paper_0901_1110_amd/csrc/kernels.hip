@@ -797,30 +797,6 @@ __global__ __launch_bounds__(BLOCK) void k_update_p(long n, double* __restrict__
 // (reduce_blocks), partials laid out [component][block], one final-reduce
 // workgroup per component (fixed order: deterministic).
 
-// block partials of nc <= KMAX values (slot c of parts: c * nblk + block)
-__device__ inline void block_reduce_multi(double (&v)[KMAX], int nc, double* __restrict__ parts,
-                                          int nblk) {
-  __shared__ double sh[BLOCK / 64][KMAX];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
-#pragma unroll
-  for (int c = 0; c < KMAX; ++c) {
-    if (c < nc) {
-      double x = v[c];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-      if (lane == 0) sh[w][c] = x;
-    }
-  }
-  __syncthreads();
-  if (tid < nc) {
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < BLOCK / 64; ++i) t += sh[i][tid];
-    parts[(size_t)tid * nblk + blockIdx.x] = t;
-  }
-}
-
 // (i, j, k) of flat cell index n on an nx x ny x nz grid
 __device__ inline void cell_ijk(long n, int ny, int nz, int& i, int& j, int& k) {
   const long row = n / nz;
@@ -829,10 +805,41 @@ __device__ inline void cell_ijk(long n, int ny, int nz, int& i, int& j, int& k) 
   j = (int)(row - (long)i * ny);
 }
 
+// block partials of NC compile-time components (slot c of parts: c * nblk + block)
+template <int NC>
+__device__ inline void block_reduce_n(const double (&v)[NC], double* __restrict__ parts,
+                                      int nblk) {
+  __shared__ double sh[BLOCK / 64][NC];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) sh[w][c] = x;
+  }
+  __syncthreads();
+  if (tid < NC) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) t += sh[i][tid];
+    parts[(size_t)tid * nblk + blockIdx.x] = t;
+  }
+}
+
+// The vector kernels below take the number of basis vectors as a template
+// argument: every load of a cell is then issued unconditionally, ahead of
+// its use, instead of behind a run-time test per vector (which serialised
+// the loads of a thread).  The grid-stride loops walk the cells of a fixed
+// number of blocks (reduce_blocks), so the partial sums, and hence the
+// results, do not depend on timing.
+
 // w = S z (bsub null) or w = bsub - S z for the full 7-point operator
 // (S x)_P = diag_P x_P - sum_d [fw_d[P] x_{P+d} + bw_d[P-d] x_{P-d}];
-// zcopy non-null: also zcopy = z.  Partials of w.V_i (i < nvec, V_i at
-// V + i N) and of w.w (component nvec).
+// zcopy non-null: also zcopy = z.  Partials of w.V_i (i < NV, V_i at
+// V + i N) and of w.w (component NV).
+template <int NV>
 __global__ __launch_bounds__(BLOCK) void k_spmv_full(int nx, int ny, int nz,
                                                       const double* __restrict__ diag,
                                                       const double* __restrict__ fw,
@@ -841,17 +848,20 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_full(int nx, int ny, int nz,
                                                       const double* __restrict__ bsub,
                                                       double* __restrict__ w,
                                                       double* __restrict__ zcopy,
-                                                      const double* __restrict__ V, int nvec,
+                                                      const double* __restrict__ V,
                                                       double* __restrict__ parts, int nblk) {
   const long N = (long)nx * ny * nz;
-  double acc[KMAX];
+  double acc[NV + 1];
 #pragma unroll
-  for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
+  for (int c = 0; c <= NV; ++c) acc[c] = 0.0;
   for (long n = blockIdx.x * (long)BLOCK + threadIdx.x; n < N; n += (long)gridDim.x * BLOCK) {
     int i, j, k;
     cell_ijk(n, ny, nz, i, j, k);
     const Nb nb = nbrs(i, j, k, nx, ny, nz);
     const int idx = (int)n;
+    double vv[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) vv[c] = V[(size_t)c * N + idx];
     const double zv = z[idx];
     double y = diag[idx] * zv;
     y = y - fw[idx] * z[nb.xp] - bw[nb.xm] * z[nb.xm];
@@ -861,49 +871,41 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_full(int nx, int ny, int nz,
     w[idx] = y;
     if (zcopy) zcopy[idx] = zv;
 #pragma unroll
-    for (int c = 0; c < KMAX - 1; ++c)
-      if (c < nvec) acc[c] += y * V[(size_t)c * N + idx];
-    double yy = y * y;
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c)
-      if (c == nvec) acc[c] += yy;
+    for (int c = 0; c < NV; ++c) acc[c] += y * vv[c];
+    acc[NV] += y * y;
   }
-  block_reduce_multi(acc, nvec + 1, parts, nblk);
+  block_reduce_n<NV + 1>(acc, parts, nblk);
 }
 
-// Gram-Schmidt pass: w -= sum_{i < nvec} coef[i] V_i (coef on the device);
-// partials of w.V_i (dots set) and of w.w (component nvec, or 0 without dots)
+// Gram-Schmidt pass: w -= sum_{i < NV} coef[i] V_i (coef on the device);
+// partials of w.V_i (DOTS) and of w.w (component NV, or 0 without DOTS)
+template <int NV, bool DOTS>
 __global__ __launch_bounds__(BLOCK) void k_gs_pass(long N, double* __restrict__ w,
-                                                    const double* __restrict__ V, int nvec,
-                                                    const double* __restrict__ coef, int dots,
+                                                    const double* __restrict__ V,
+                                                    const double* __restrict__ coef,
                                                     double* __restrict__ parts, int nblk) {
-  __shared__ double cs[KMAX];
-  if (threadIdx.x < nvec) cs[threadIdx.x] = coef[threadIdx.x];
+  __shared__ double cs[NV];
+  if (threadIdx.x < NV) cs[threadIdx.x] = coef[threadIdx.x];
   __syncthreads();
-  double acc[KMAX];
+  constexpr int NA = DOTS ? NV + 1 : 1;
+  double acc[NA];
 #pragma unroll
-  for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
-  const int nn = dots ? nvec : 0;
+  for (int c = 0; c < NA; ++c) acc[c] = 0.0;
   for (long n = blockIdx.x * (long)BLOCK + threadIdx.x; n < N; n += (long)gridDim.x * BLOCK) {
+    double vv[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) vv[c] = V[(size_t)c * N + n];
     double y = w[n];
-    double vv[KMAX - 1];
 #pragma unroll
-    for (int c = 0; c < KMAX - 1; ++c) {
-      if (c < nvec) {
-        vv[c] = V[(size_t)c * N + n];
-        y -= cs[c] * vv[c];
-      }
-    }
+    for (int c = 0; c < NV; ++c) y -= cs[c] * vv[c];
     w[n] = y;
+    if constexpr (DOTS) {
 #pragma unroll
-    for (int c = 0; c < KMAX - 1; ++c)
-      if (c < nn) acc[c] += y * vv[c];
-    double yy = y * y;
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c)
-      if (c == nn) acc[c] += yy;
+      for (int c = 0; c < NV; ++c) acc[c] += y * vv[c];
+    }
+    acc[NA - 1] += y * y;
   }
-  block_reduce_multi(acc, nn + 1, parts, nblk);
+  block_reduce_n<NA>(acc, parts, nblk);
 }
 
 // v *= s; copy non-null: copy = v (after scaling); r32 non-null: the FP32
@@ -924,16 +926,21 @@ __global__ __launch_bounds__(BLOCK) void k_scale(long N, double* __restrict__ v,
   }
 }
 
-// x += sum_{i < nvec} y[i] Z_i (y on the device)
+// x += sum_{i < NV} y[i] Z_i (y on the device)
+template <int NV>
 __global__ __launch_bounds__(BLOCK) void k_combine(long N, double* __restrict__ x,
-                                                    const double* __restrict__ Z, int nvec,
+                                                    const double* __restrict__ Z,
                                                     const double* __restrict__ y) {
-  __shared__ double ys[KMAX];
-  if (threadIdx.x < nvec) ys[threadIdx.x] = y[threadIdx.x];
+  __shared__ double ys[NV];
+  if (threadIdx.x < NV) ys[threadIdx.x] = y[threadIdx.x];
   __syncthreads();
   for (long n = blockIdx.x * (long)BLOCK + threadIdx.x; n < N; n += (long)gridDim.x * BLOCK) {
+    double zz[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) zz[c] = Z[(size_t)c * N + n];
     double t = x[n];
-    for (int c = 0; c < nvec; ++c) t += ys[c] * Z[(size_t)c * N + n];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) t += ys[c] * zz[c];
     x[n] = t;
   }
 }
@@ -1725,19 +1732,51 @@ void launch_schur_faces(const DevParams& P, const double* U, const double* nH, c
   RT_NS(P, k_schur_faces, q.g, q.b, 0, st, P, U, nH, Dlag, s, loc, om, ph, diag, pdiag, c, fw, bw,
         b, pd32, cx32, cy32, cz32);
 }
+// one case per vector count 0..KMAX-1 (a run-time count selects a
+// compile-time instantiation)
+#define RT_VEC_CASES_1(X)                                                                  \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)       \
+  X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29)    \
+  X(30) X(31)
+#define RT_VEC_CASES(X) X(0) RT_VEC_CASES_1(X)
+static_assert(KMAX == 32, "RT_VEC_CASES lists the vector counts 0..KMAX-1");
+
 int launch_spmv_full(int nx, int ny, int nz, const double* diag, const double* fw,
                      const double* bw, const double* z, const double* bsub, double* w,
                      double* zcopy, const double* V, int nvec, double* parts, hipStream_t st) {
   const long N = (long)nx * ny * nz;
   const int nb = reduce_blocks(N);
-  hipLaunchKernelGGL(k_spmv_full, dim3(nb), dim3(BLOCK), 0, st, nx, ny, nz, diag, fw, bw, z, bsub,
-                     w, zcopy, V, nvec, parts, nb);
+  switch (nvec) {
+#define RT_SPMV_CASE(NV)                                                                      \
+  case NV:                                                                                   \
+    hipLaunchKernelGGL(k_spmv_full<NV>, dim3(nb), dim3(BLOCK), 0, st, nx, ny, nz, diag, fw,  \
+                       bw, z, bsub, w, zcopy, V, parts, nb);                                  \
+    break;
+    RT_VEC_CASES(RT_SPMV_CASE)
+#undef RT_SPMV_CASE
+    default:
+      return -1;   // beyond KMAX - 1: the host never asks for it (restart <= KMAX - 2)
+  }
   return nb;
 }
 int launch_gs_pass(long N, double* w, const double* V, int nvec, const double* coef, int dots,
                    double* parts, hipStream_t st) {
   const int nb = reduce_blocks(N);
-  hipLaunchKernelGGL(k_gs_pass, dim3(nb), dim3(BLOCK), 0, st, N, w, V, nvec, coef, dots, parts, nb);
+  switch (nvec) {
+#define RT_GS_CASE(NV)                                                                    \
+  case NV:                                                                               \
+    if (dots)                                                                            \
+      hipLaunchKernelGGL((k_gs_pass<NV, true>), dim3(nb), dim3(BLOCK), 0, st, N, w, V,   \
+                         coef, parts, nb);                                               \
+    else                                                                                 \
+      hipLaunchKernelGGL((k_gs_pass<NV, false>), dim3(nb), dim3(BLOCK), 0, st, N, w, V,  \
+                         coef, parts, nb);                                               \
+    break;
+    RT_VEC_CASES_1(RT_GS_CASE)
+#undef RT_GS_CASE
+    default:
+      return -1;
+  }
   return nb;
 }
 void launch_scale(long N, double* v, double sf, double* copy, float* r32, int ny, int nz,
@@ -1747,7 +1786,17 @@ void launch_scale(long N, double* v, double sf, double* copy, float* r32, int ny
 }
 void launch_combine(long N, double* x, const double* Z, int nvec, const double* y,
                     hipStream_t st) {
-  hipLaunchKernelGGL(k_combine, dim3(reduce_blocks(N)), dim3(BLOCK), 0, st, N, x, Z, nvec, y);
+  switch (nvec) {
+#define RT_COMBINE_CASE(NV)                                                                   \
+  case NV:                                                                                   \
+    hipLaunchKernelGGL(k_combine<NV>, dim3(reduce_blocks(N)), dim3(BLOCK), 0, st, N, x, Z,   \
+                       y);                                                                   \
+    break;
+    RT_VEC_CASES_1(RT_COMBINE_CASE)
+#undef RT_COMBINE_CASE
+    default:
+      break;
+  }
 }
 void launch_final_multi(const double* parts, int nblk, int ncomp, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_final_multi, dim3(ncomp), dim3(1024), 0, st, parts, nblk, out);
