@@ -9,10 +9,13 @@ The convergence test runs before every iteration, so an initial guess that
 already satisfies the tolerance takes zero iterations (Sec. 3.2.4).
 
 Line-search rule (a reading; the paper states only the interval): start at
-lambda = 1 and halve while the trial point leaves the physical bounds
-(E < 0, any fraction outside [0, 1], x_HeI + x_HeII > 1, e_h + e_c <= 0) or
-fails the sufficient-decrease test ||f(U_t)|| <= (1 - 1e-4 lambda) ||f(U_k)||;
-below lambda_min = 2^-10 the step fails.
+lambda = 1; the trial point is projected onto the physical bounds (fractions
+into [0, 1], the helium pair rescaled to a sum <= 1, E >= 0) and accepted
+when e_h + e_c > 0 (the one bound the projection does not enforce) and the
+sufficient-decrease test ||f(U_t)|| <= (1 - 1e-4 lambda) ||f(U_k)|| holds,
+else lambda is halved; below lambda_min = 2^-10 the step fails.  (The
+rescaled helium pair sums to 1 only to within a rounding, so the projected
+bounds are not re-tested.)
 
 Two linear-solve modes: 'mgpcg' (the algorithm: MG-preconditioned FGMRES on
 the Schur system, or flexible PCG for a symmetric one) and 'direct' (a sparse
@@ -52,6 +55,11 @@ def project(U, eh, model):
         V[3] = np.where(over, V[3] / np.where(over, tot, 1.0), V[3])
     V[-1] = np.maximum(V[-1], 0.0)
     return V
+
+
+def energy_ok(U, eh):
+    """The bound a projected state is tested on: e_h + e_c > 0 everywhere."""
+    return bool(np.all(eh + U[0] > 0.0))
 
 
 def bounds_ok(U, eh, model):
@@ -143,7 +151,7 @@ def newton_step(Un, U0, nH, eh, src_cells, src_Q, dt, cosmo, model,
             Ut = U + lam * step
             if PROJECT:
                 Ut = project(Ut, eh, model)
-            if bounds_ok(Ut, eh, model):
+            if energy_ok(Ut, eh) if PROJECT else bounds_ok(Ut, eh, model):
                 ft = residual.residual(Ut, tl, nH, eh, dt, a, H, model, D)
                 ftn = residual.rms(ft)
                 if ftn <= (1.0 - ARMIJO * lam) * fn:

@@ -60,7 +60,9 @@ def adaptive_step(Un, nH, eh, src_cells, src_Q, dt, cosmo, model, p=np.inf):
     a, H = cosmo[2], cosmo[3]
     f0 = residual.rms(residual.residual(Un, tl, nH, eh, dt, a, H, model))
     fp = residual.rms(residual.residual(Up, tl, nH, eh, dt, a, H, model))
-    use_pred = bool(np.isfinite(fp) and newton.bounds_ok(Up, eh, model) and fp < f0)
+    # the predictor is projected like a trial point: only e_h + e_c > 0 is
+    # tested (the projection enforces the other bounds)
+    use_pred = bool(np.isfinite(fp) and newton.energy_ok(Up, eh) and fp < f0)
     U, st = newton.newton_step(Un, Up if use_pred else Un, nH, eh, src_cells, src_Q, dt, cosmo,
                                model, tl=tl)
     st["used_predictor"] = int(use_pred)

@@ -172,3 +172,27 @@ def test_temperature_reading():
     T = temperature(synth.E_GAS_1E4K_X09999, 0.9999, 0.0, 0.0, m)
     assert abs(T / 1e4 - 1) < 1e-12
     assert recombination_coefficients(1e4)[0] == ALPHA_B_1E4
+
+
+def test_projected_helium_pair_rounding():
+    """Rescaling a helium pair with x_HeI + x_HeII > 1 to unit sum leaves the
+    sum at 1 only to within a rounding: pairs exist whose rescaled sum is
+    above 1 by an ulp.  The line search therefore tests a projected trial
+    point on e_h + e_c > 0 alone (the bound the projection does not
+    enforce); a re-test of all bounds would reject such points."""
+    from oracle import newton
+    w = synth.CFG_HHE.replace(n=4, mg_levels=2)
+    m = oracle.model_from_workload(w)
+    rng = np.random.default_rng(7)
+    n = 20000
+    U = np.zeros((5, n, 1, 1))
+    U[1] = rng.uniform(0.0, 1.0, (n, 1, 1))
+    U[2] = rng.uniform(0.5, 1.0, (n, 1, 1))
+    U[3] = rng.uniform(0.5, 1.0, (n, 1, 1))
+    U[4] = 1.0
+    eh = np.full((n, 1, 1), 1.0e12)
+    V = newton.project(U, eh, m)
+    tot = V[2] + V[3]
+    assert np.all(tot <= 1.0 + 4.0 * np.finfo(float).eps)
+    assert np.any(tot > 1.0)
+    assert newton.energy_ok(V, eh) and not newton.bounds_ok(V, eh, m)
