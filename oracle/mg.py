@@ -265,7 +265,9 @@ def pcg(op, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=Non
     return x, maxit, rn / bn
 
 
-REORTH = 0.7071067811865476     # second Gram-Schmidt pass below this ratio
+# second Gram-Schmidt pass when the projection leaves less than this
+# fraction of the product's norm: a loss of two digits or more
+REORTH = 0.01
 
 
 def fgmres(op, pop, b, model, rtol=None, maxit=None, precond=True, atol=0.0, centres=None,
@@ -280,9 +282,11 @@ def fgmres(op, pop, b, model, rtol=None, maxit=None, precond=True, atol=0.0, cen
 
     Arnoldi with classical Gram-Schmidt and one conditional second pass:
     v_0 = r / ||r||, z_j = P v_j, w = S z_j, h_ij = w . v_i (i <= j),
-    w' = w - sum_i h_ij v_i; if ||w'|| < ||w|| / sqrt(2) (cancellation: the
-    criterion of Daniel, Gragg, Kaufman and Stewart) the projection is
-    repeated on w' and its coefficients added to h; h_{j+1,j} = ||w'||,
+    w' = w - sum_i h_ij v_i; if ||w'|| < REORTH ||w|| (cancellation of two
+    digits or more: the test of Daniel, Gragg, Kaufman and Stewart with a
+    smaller threshold than their 1/sqrt(2); the orthogonality lost by one
+    pass is then at most ~1e-14) the projection is repeated on w' and its
+    coefficients added to h; h_{j+1,j} = ||w'||,
     v_{j+1} = w' / h_{j+1,j}.  The Hessenberg columns are reduced by Givens
     rotations, whose last sine gives the residual norm, and the update is
     s += sum_j y_j z_j.  Returns (s, iterations, estimate / ||b||)."""

@@ -826,13 +826,15 @@ int pcg(rt_grid* g, const double* b, double* x, double rtol, double atol, int ma
   return RT_OK;
 }
 
-constexpr double REORTH = 0.7071067811865476;   // second Gram-Schmidt pass below this ratio
+// second Gram-Schmidt pass when the projection leaves less than this
+// fraction of the product's norm (a loss of two digits or more)
+constexpr double REORTH = 0.01;
 
 // Flexible GMRES(m) on the workspace Schur operator (diag, fw, bw), right-
 // preconditioned by apply_precond (the V-cycle of the preconditioner's
 // operator plus the subdomain correction), from x = 0.  Classical
 // Gram-Schmidt in one fused pass (the product forms the dots), a second pass
-// where the first cancelled (DGKS: ||w'|| < ||w|| / sqrt 2), Givens
+// where the first cancelled two digits or more (||w'|| < REORTH ||w||), Givens
 // rotations on the host; stops once the least-squares residual
 // <= max(rtol ||b||_2, atol), after maxit iterations in all (rtol = atol = 0:
 // exactly maxit), restarting every m.  The host reads j + 2 scalars per
