@@ -11,8 +11,12 @@ On random physical states (Sec. 3.2.1, Eqs. 31-35):
   (iii) the dense Schur complement D - L M^-1 U equals the 7-point arrays;
   (iv)  the diffusion part is conservative: every column of S sums to the
         cell's local part 1 + dt theta dL_E/dE - L M^-1 U, which is at least
-        1 for monochromatic hydrogen; the preconditioner's operator is the
-        symmetric part (S + S^T)/2.
+        1 for monochromatic hydrogen; the preconditioner's operator is that
+        local part plus a symmetric diffusion with non-negative face
+        couplings: a symmetric positive definite M-matrix with the same
+        column sums.
+The lagged reading (face coefficients held at U^n) is checked the same way
+with those coefficients fixed in the differences.
 """
 import numpy as np
 import pytest
