@@ -39,17 +39,38 @@ sys.path.insert(0, ROOT)
 METRIC = "Newton-step cell-updates/s at 256^3, mixed+learned vs plain FP64, Newton tol 1e-6"
 METRIC_SG = "Newton-step cell-updates/s, expanding-universe I-front (Sec. 4.6), Newton tol 1e-6"
 WORKLOAD_HII = ("hii_256: %d^3 periodic hydrogen, centred 5e48 photons/s source, 13.2 kpc box, "
-                "dt=1e11 s, theta=1, Newton tol 1e-6, PCG rtol 1e-8%s, 5-level V-cycle RB-GS 2+2%s")
+                "dt=1e11 s, theta=1, Newton tol 1e-6, FGMRES(30) rtol 1e-8%s, 5-level V-cycle RB-GS %d+%d%s")
+METRIC_HHE = ("Newton-step cell-updates/s at 512^3 H+He (lognormal, 64 sources), mixed+learned vs "
+              "plain FP64, Newton tol 1e-6")
+WORKLOAD_HHE = ("hhe_lognormal_512: %d^3 periodic hydrogen+helium, lognormal sigma_ln=1.5, 64 sources "
+                "log-uniform in [1e47, 1e49] photons/s, grey T_B=1e5 K, a=0.1 -> 0.125 over 50 steps, "
+                "limiter held at time level n, Newton tol 1e-6, FGMRES(30) rtol 1e-8%s, 6-level "
+                "V-cycle RB-GS %d+%d%s")
 WORKLOAD_SG = ("sg_q05_z4: %d^3 periodic uniform hydrogen, 0.625 kpc proper cells at z=4, "
                "centred 5e48 photons/s source, isothermal 1e4 K, Einstein-de Sitter from z=4, "
-               "dt=2e15 s, theta=1, Newton tol 1e-6, PCG rtol 1e-8%s, 4-level V-cycle RB-GS 2+2%s")
+               "dt=2e15 s, theta=1, limiter held at time level n, Newton tol 1e-6, FGMRES(30) rtol "
+               "1e-8%s, 4-level V-cycle RB-GS %d+%d%s")
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic per launch of a kernel class, keyed (class, mode, grid), from
-# two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by what the
-# counters read for a plain device copy of known size.  A figure belongs to
-# the kernel source it was measured on and is reported as null for any other.
-PMC_TRAFFIC = {}
+# HBM traffic of a kernel class, keyed (class, mode, grid), from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled
+# by what the counters read for a plain 2 GiB device copy (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0), as the ratio of the summed traffic to the summed
+# algorithmic bytes over the class's dispatches of a one-step run; a run's
+# traffic per launch is that ratio times its own algorithmic bytes per
+# launch (the vector count, hence the bytes, differs from launch to launch).
+# A figure belongs to the kernel source it was measured on and is reported
+# as null for any other.
+PMC_TRAFFIC = {
+    ("cg_vector", "mixed", 256): {"ratio": 1.000, "kernels_sha256":
+                                  "8c211a876bc79dfcf2907350a79fb0813e3f74558464a4e7fa98224b63d1eafd"},
+    ("cg_vector", "mixed+learned", 256): {"ratio": 1.000, "kernels_sha256":
+                                          "8c211a876bc79dfcf2907350a79fb0813e3f74558464a4e7fa98224b63d1eafd"},
+    ("spmv", "mixed", 256): {"ratio": 1.285, "kernels_sha256":
+                             "8c211a876bc79dfcf2907350a79fb0813e3f74558464a4e7fa98224b63d1eafd"},
+    ("spmv", "mixed+learned", 256): {"ratio": 1.285, "kernels_sha256":
+                                     "8c211a876bc79dfcf2907350a79fb0813e3f74558464a4e7fa98224b63d1eafd"},
+}
 
 
 def kernels_sha256():
@@ -59,16 +80,20 @@ def kernels_sha256():
 
 
 def train_guess(n_train=128, steps=100, epochs=8, lr=3e-4, log=None, box=(0, 3, 6, 0),
-                trajectories=1):
-    """Train the learned-guess network on plain-method trajectories."""
+                trajectories=1, workload="hii_256"):
+    """Train the learned-guess network on plain-method trajectories of the
+    workload's generator at n_train^3 (same cell size and time step; the
+    source count scaled with the volume, at least one)."""
     import numpy as np
     import synth
     from paper_0901_1110_amd.binding import RtNet
     from paper_0901_1110_amd.driver import generate_trajectory, init_net_params, train_net
 
     t0 = time.perf_counter()
-    base = synth.CFG_256.replace(n=n_train, mg_levels=4, box_size=box[0], box_levels=box[1],
-                                 box_inner=box[2], box_coarse_sweeps=box[3])
+    W = synth.WORKLOADS[workload]
+    base = W.replace(n=n_train, mg_levels=4, box_size=box[0], box_levels=box[1],
+                     box_inner=box[2], box_coarse_sweeps=box[3], mg_fp32=0,
+                     nsources=max(1, (W.nsources * n_train ** 3) // W.n ** 3))
     media = [base, base.replace(nsources=2, centred=False, seed=100,
                                 logQ_range=(48.0, 48.7))][:trajectories]
     trajs = []
@@ -83,7 +108,7 @@ def train_guess(n_train=128, steps=100, epochs=8, lr=3e-4, log=None, box=(0, 3, 
                    sum(s["cg_its_total"] for s in st),
                    max(s["cg_its_total"] / max(1, s["newton_its"]) for s in st)))
     t1 = time.perf_counter()
-    net = RtNet(1, (n_train,) * 3)
+    net = RtNet(W.nspecies, (n_train,) * 3)
     net.set_params(init_net_params(net.nin, net.nout, seed=0))
     hist = train_net(net, trajs, epochs=epochs, lr=lr, seed=0, log=log)
     t2 = time.perf_counter()
@@ -102,7 +127,7 @@ def train_guess(n_train=128, steps=100, epochs=8, lr=3e-4, log=None, box=(0, 3, 
 
 
 def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 0),
-             workload="hii_256", adaptive=0.0):
+             workload="hii_256", adaptive=0.0, smoothing=(2, 2)):
     import torch
     import synth
     from paper_0901_1110_amd.binding import RtNet
@@ -110,9 +135,10 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
 
     w = synth.WORKLOADS[workload].replace(
         n=n, mg_fp32=1 if mode.startswith("mixed") else 0, pcg_forcing=forcing,
-        box_size=box[0], box_levels=box[1], box_inner=box[2], box_coarse_sweeps=box[3])
+        box_size=box[0], box_levels=box[1], box_inner=box[2], box_coarse_sweeps=box[3],
+        mg_pre=smoothing[0], mg_post=smoothing[1])
     if mode.endswith("learned"):
-        net = RtNet(1, (n, n, n))
+        net = RtNet(w.nspecies, (n, n, n))
         net.set_params(theta)
         sim = LearnedSimulation(w, net)
         warmup = max(warmup, 2)
@@ -188,7 +214,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
         tr = PMC_TRAFFIC.get((dom, mode, n))
         traffic = None
         if tr and kernels_sha256() == tr["kernels_sha256"]:
-            traffic = tr["bytes_per_launch"]
+            traffic = round(tr["ratio"] * nbytes / cnt)
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -282,9 +308,12 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=100)
     ap.add_argument("--train-trajectories", type=int, default=1)
-    ap.add_argument("--workload", default="hii_256", choices=["hii_256", "sg_q05_z4"],
+    ap.add_argument("--workload", default="hii_256",
+                    choices=["hii_256", "sg_q05_z4", "hhe_lognormal_512"],
                     help="hii_256: the timed 256^3 HII region; sg_q05_z4: the expanding-universe "
-                         "I-front of Sec. 4.6 at 128^3 (cell size fixed, --n sets the box)")
+                         "I-front of Sec. 4.6 at 128^3; hhe_lognormal_512: the 512^3 "
+                         "hydrogen+helium medium with 64 sources (cell size fixed, --n sets the "
+                         "box)")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--pcg-forcing", type=float, default=1e-6,
                     help="inexact-Newton forcing factor delta_k / ||f(U_k)|| (Sec. 3.2.1; "
@@ -296,6 +325,8 @@ def main():
     ap.add_argument("--box-inner", type=int, default=20)
     ap.add_argument("--box-coarse-sweeps", type=int, default=4,
                     help="sweeps of the coarsest box level (0: those of the main hierarchy)")
+    ap.add_argument("--mg-pre", type=int, default=2, help="V-cycle pre-smoothing (red, black) pairs")
+    ap.add_argument("--mg-post", type=int, default=2, help="V-cycle post-smoothing pairs")
     ap.add_argument("--adaptive", type=float, default=0.0,
                     help="tau_tol > 0: adaptive steps with the explicit predictor as the guess "
                          "(plain and mixed modes; 0: the fixed step)")
@@ -318,19 +349,19 @@ def main():
               flush=True)
         del a, b
     if args.n is None:
-        args.n = 256 if args.workload == "hii_256" else 128
+        args.n = {"hii_256": 256, "sg_q05_z4": 128, "hhe_lognormal_512": 512}[args.workload]
     if args.box_size is None:
         args.box_size = 32 if args.workload == "hii_256" else 0
     if args.modes is None:
-        args.modes = "plain,mixed,learned,mixed+learned" if args.workload == "hii_256" \
-            else "plain,mixed"
+        args.modes = "plain,mixed" if args.workload == "sg_q05_z4" \
+            else "plain,mixed,learned,mixed+learned"
     modes = [m for m in args.modes.split(",") if m]
     if args.adaptive > 0.0 and any(m.endswith("learned") for m in modes):
         print("--adaptive offers the predictor as the guess: plain and mixed modes only",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload != "hii_256" and any(m.endswith("learned") for m in modes):
-        print("the learned guess is trained for the HII-region workload only", file=sys.stderr)
+    if args.workload == "sg_q05_z4" and any(m.endswith("learned") for m in modes):
+        print("no learned guess for the expanding-universe front", file=sys.stderr)
         sys.exit(2)
     box = (args.box_size, args.box_levels, args.box_inner, args.box_coarse_sweeps)
     results = {}
@@ -339,28 +370,32 @@ def main():
         print("# training the learned guess (untimed)", file=sys.stderr, flush=True)
         theta, train_info = train_guess(steps=args.train_steps, epochs=args.train_epochs,
                                         log=lambda s: print("#   " + s, file=sys.stderr, flush=True),
-                                        box=box, trajectories=args.train_trajectories)
+                                        box=box, trajectories=args.train_trajectories,
+                                        workload=args.workload)
         print("# trained: %s" % train_info, file=sys.stderr, flush=True)
     for mode in modes:
         print("# mode %s: %d warm-up + %d timed steps at %d^3" % (mode, args.warmup, args.steps, args.n),
               file=sys.stderr, flush=True)
         results[mode] = run_mode(mode, args.steps, args.warmup, args.n, theta, args.pcg_forcing,
-                                 box, args.workload, args.adaptive)
+                                 box, args.workload, args.adaptive, (args.mg_pre, args.mg_post))
         print("# %s: %.3e cell-updates/s, %.1f ms/step" % (mode, results[mode]["value"],
                                                           results[mode]["ms_per_step"]),
               file=sys.stderr, flush=True)
     head = next((m for m in ("mixed+learned", "mixed", "learned") if m in results), modes[0])
     H = results[head]
     line = {
-        "metric": METRIC if args.workload == "hii_256" else METRIC_SG,
+        "metric": {"hii_256": METRIC, "sg_q05_z4": METRIC_SG,
+                   "hhe_lognormal_512": METRIC_HHE}[args.workload],
         "value": H["value"], "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": H["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32" if head.startswith("mixed") else "f64",
         "data": "synthetic",
-        "config": {"workload": (WORKLOAD_HII if args.workload == "hii_256" else WORKLOAD_SG) % (
+        "config": {"workload": {"hii_256": WORKLOAD_HII, "sg_q05_z4": WORKLOAD_SG,
+                                "hhe_lognormal_512": WORKLOAD_HHE}[args.workload] % (
                                    args.n, " or ||r|| <= %g ||f(U_k)|| (inexact-Newton forcing)"
                                    % args.pcg_forcing if args.pcg_forcing > 0 else "",
+                                   args.mg_pre, args.mg_post,
                                    ", then a %d^3 source-subdomain correction (%d inner PCG its, "
                                    "%d-level box V-cycle)" % (args.box_size, args.box_inner,
                                                               args.box_levels)
