@@ -135,14 +135,16 @@ def generate_trajectory(w, steps, device="cuda", state=None, **overrides):
                 grid=sim.grid, dt=w.dt, cosmology=w.cosmology)
 
 
-def guess_score(net, trajectories, grids, every=10):
+def guess_score(net, trajectories, grids, every=1, first=2):
     """Mean log10 of ||f(network guess)|| / ||f(U^n)|| over every `every`-th
-    sample: the Newton initial residual the guess would save (negative is
-    better than the previous-state guess)."""
+    sample from level `first` on (the first levels follow the start-up
+    transient of a cold box, where no extrapolation holds): the Newton
+    initial residual the guess would save (negative is better than the
+    previous-state guess)."""
     tot, cnt = 0.0, 0
     for T, g in zip(trajectories, grids):
         Ug = torch.empty_like(T["U"][0])
-        for n in range(1, len(T["U"]) - 1, every):
+        for n in range(max(1, first), len(T["U"]) - 1, every):
             g.rt_set_medium(T["nH"], T["e"][n])
             c = T["cosmology"](n)
             gn = g.rt_time_level(T["U"][n], T["dt"], c)
