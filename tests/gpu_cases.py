@@ -66,7 +66,7 @@ def random_case(ns, n, theta, a, seed, levels=2, **kw):
     return w, dict(U=U, Un=Un, nH=nH, eh=eh, cells=cells, Q=Q, cosmo=cosmo, dt=dt)
 
 
-def newton_parity(w, state, steps=1, tol_fields=1e-10, tol_elem=1e-8):
+def newton_parity(w, state, steps=1, tol_fields=1e-10, tol_elem=1e-8, keep=False):
     """Run `steps` implicit steps on both sides from the same state and
     compare each.  The oracle runs with its own decisions: Newton count and
     line search factors must equal the library's, and so must the Krylov
@@ -75,7 +75,8 @@ def newton_parity(w, state, steps=1, tol_fields=1e-10, tol_elem=1e-8):
     step), and the library's step is compared with the oracle replaying the
     library's schedule (replay mode: its Krylov counts and lambdas), so that
     the comparison stays iterate for iterate.  Fields: normwise to
-    tol_fields and per element (state_floors) to tol_elem."""
+    tol_fields and per element (state_floors) to tol_elem.  keep: the
+    entries also carry the oracle's new state of the step."""
     from oracle import newton as onewt
     from paper_0901_1110_amd.driver import Simulation
     m = oracle.model_from_workload(w)
@@ -104,7 +105,7 @@ def newton_parity(w, state, steps=1, tol_fields=1e-10, tol_elem=1e-8):
             assert rel(U[v], U_o[v]) <= tol_fields, (n, v, rel(U[v], U_o[v]))
             e = rel_elem(U[v], U_o[v], floors[v])
             assert e <= tol_elem, (n, v, e)
-        out.append((st, st_o))
+        out.append((st, st_o, U_o.copy()) if keep else (st, st_o))
         sim.advance()
         eh = eh + U_o[0]
         U_o[0] = 0.0

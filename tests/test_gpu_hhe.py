@@ -159,38 +159,46 @@ def densest_block(s, n, b=64):
     return sub, tuple(int(c) for c in best), int(inside.sum())
 
 
+SUB_STEPS = 50
+
+
 def test_hhe512_densest_subvolume_rerun(hhe512):
-    """The 512^3 H+He workload against the oracle on a 64^3 subvolume:
-    the block with the most sources, made periodic with them, three steps.
-    FP64 library against the oracle: equal Newton and Krylov counts and
-    line-search factors, fields to 1e-10 (per element 1e-8).  FP32 V-cycle
-    with the learned guess: every step meets the FP64 tolerance and its
-    fields lie within 1e-5 (L2, relative) of the FP64 oracle's."""
+    """The 512^3 H+He workload against the oracle on a 64^3 subvolume: the
+    block of the initial state with the most sources, made periodic with
+    them, for the workload's 50 steps.  FP64 library against the oracle:
+    equal Newton and Krylov counts and line-search factors (a Krylov count
+    within rounding of its stop test may differ by one, then the oracle
+    replays the library's schedule), fields to 1e-10 (per element 1e-8).
+    FP32 V-cycle with the learned guess (untrained network: the
+    extrapolation base): every step meets the FP64 tolerance and its fields
+    lie within 1e-5 (L2, relative) of the FP64 oracle's."""
     s, _, _ = hhe512
     sub, best, nsrc = densest_block(s, W.n)
     assert nsrc >= 2, (best, nsrc)
     w = W.replace(n=64, mg_levels=4, nsources=nsrc)
-    newton_parity(w.replace(mg_fp32=0), sub, steps=STEPS)
-    m = oracle.model_from_workload(w)
+    ref = newton_parity(w.replace(mg_fp32=0), sub, steps=SUB_STEPS, keep=True)
     sim = learned_sim(w, {k: (v.copy() if hasattr(v, "copy") else v) for k, v in sub.items()})
-    Un, eh = sub["U"].copy(), sub["eh"].copy()
+    eh = sub["eh"].copy()
     names = ["e_c", "x_HI", "x_HeI", "x_HeII", "E"]
-    for k in range(STEPS):
+    worst = np.zeros(5)
+    used = 0
+    for k in range(SUB_STEPS):
         st = sim.step()
-        assert st["status"] == 0 and st["fnorm_final"] < w.newton_tol, st
-        U_o, st_o = onewt.newton_step(Un, Un, sub["nH"], eh, sub["src_cells"], sub["src_Q"],
-                                      w.dt, w.cosmology(k), m)
-        assert st_o["status"] == 0
+        assert st["status"] == 0 and st["fnorm_final"] < w.newton_tol, (k, st)
+        used += st["used_alt_guess"]
+        U_o = ref[k][2]
         U = host(sim.U)
         errs = [np.linalg.norm(U[v] - U_o[v]) / max(np.linalg.norm(U_o[v]), 1e-300)
                 for v in range(5)]
-        print("512^3 block %s (%d sources), mixed+learned step %d: " % (best, nsrc, k)
-              + ", ".join("%s %.2e" % (a, b) for a, b in zip(names, errs)), flush=True)
+        errs[0] = np.linalg.norm(U[0] - U_o[0]) / np.linalg.norm(eh + U_o[0])
+        worst = np.maximum(worst, errs)
         for v in range(1, 5):
             assert errs[v] < 1e-5, (k, names[v], errs[v])
-        etot = np.linalg.norm(eh + U_o[0])
-        assert np.linalg.norm(U[0] - U_o[0]) / etot < 1e-8
+        # e_c is a correction around zero: compared against the total energy
+        assert errs[0] < 1e-8, (k, errs[0])
         sim.advance()
         eh = eh + U_o[0]
-        U_o[0] = 0.0
-        Un = U_o
+    print("512^3 block %s (%d sources), %d steps: FP64 Newton its %d; mixed+learned worst "
+          "per-field L2 %s, proposal taken in %d steps"
+          % (best, nsrc, SUB_STEPS, sum(r[0]["newton_its"] for r in ref),
+             ", ".join("%s %.1e" % (a, b) for a, b in zip(names, worst)), used), flush=True)
