@@ -27,10 +27,12 @@ def test_cpu_baseline_fields():
         assert cb["one_core"]["value"] > 0
 
 
-def test_traffic_is_null_for_other_kernel_sources():
-    """A PMC traffic figure is reported only for the kernel source it was
-    measured on."""
+def test_traffic_table_is_tied_to_the_measured_source():
+    """A PMC traffic ratio is keyed by (class, mode, grid) and carries the
+    hash of the kernel source it was measured on; the bench reports it only
+    while the source hashes to that value."""
     sha = bench.kernels_sha256()
     assert len(sha) == 64
     for key, tr in bench.PMC_TRAFFIC.items():
-        assert len(key) == 3 and tr["bytes_per_launch"] > 0
+        assert len(key) == 3 and key[0] in ("cg_vector", "spmv", "rbgs_fine")
+        assert 0.5 < tr["ratio"] < 3.0 and len(tr["kernels_sha256"]) == 64
