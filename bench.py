@@ -70,6 +70,10 @@ PMC_TRAFFIC = {
                              "8c211a876bc79dfcf2907350a79fb0813e3f74558464a4e7fa98224b63d1eafd"},
     ("spmv", "mixed+learned", 256): {"ratio": 1.285, "kernels_sha256":
                                      "8c211a876bc79dfcf2907350a79fb0813e3f74558464a4e7fa98224b63d1eafd"},
+    ("rbgs_fine", "mixed", 256): {"ratio": 1.134, "kernels_sha256":
+                                  "8c211a876bc79dfcf2907350a79fb0813e3f74558464a4e7fa98224b63d1eafd"},
+    ("rbgs_fine", "mixed+learned", 256): {"ratio": 1.134, "kernels_sha256":
+                                          "8c211a876bc79dfcf2907350a79fb0813e3f74558464a4e7fa98224b63d1eafd"},
 }
 
 
