@@ -226,8 +226,9 @@ int rt_local_jacobian(rt_grid* g, const double* d_U, double dt, const rt_cosmo* 
  * face terms).  S is not symmetric.  Beside it the preconditioner's
  * symmetric M-matrix: the cell-local part of S plus, on every face, the
  * derivative of the flux with respect to E_Q - E_P at fixed E_f and
- * opacity (>= 0).  f~_M, W and both operators stay in the workspace for
- * rt_mg_pcg_solve and the line search. */
+ * opacity (>= 0), its diagonal raised to S's own where that is larger.
+ * f~_M, W and both operators stay in the workspace for rt_mg_pcg_solve
+ * and the line search. */
 int rt_schur_form(rt_grid* g, const double* d_U, const double* d_f, double dt,
                   const rt_cosmo* c, double* d_b);
 

@@ -35,11 +35,14 @@ off-diagonal couplings fw = -S_{P,P+d} and bw = -S_{P+d,P}:
 The Krylov solve is preconditioned by a multigrid V-cycle of the symmetric
 M-matrix P = [the cell-local part of S] + [the diffusion of the face-flux
 derivative with respect to E_Q - E_P at fixed E_f and opacity, k (D + T) on
-every face]: pdiag = local + sum of the six face couplings c, with
+every face], whose diagonal is raised to S's own where that is larger:
+pdiag = max(diag, local + sum of the six face couplings c), with
 local = 1 + dt theta dL_E/dE - L W (>= 1 for monochromatic hydrogen) and
-c = k (D + T) >= 0.  (The symmetric part (S + S^T)/2 is not used: the E_f
-dependence of the limiter and the opacity terms add to its diagonal with
-either sign and can make it indefinite.)
+c = k (D + T) >= 0.  Raising the diagonal keeps P diagonally dominant; it
+carries the part of the limiter's E_f derivative and of the opacity terms
+that adds to S's diagonal (the Krylov iterations of the 256^3-cell-size HII
+region drop by a third).  (The symmetric part (S + S^T)/2 is not used: those
+terms add to its diagonal with either sign and can make it indefinite.)
 """
 from __future__ import annotations
 
@@ -148,6 +151,7 @@ def schur_form(U, f, nH, eh, dt, a, H, model, D=None):
         fws.append(fw)
         bws.append(bw)
         cs.append(c)
+    pdiag = np.where(diag > pdiag, diag, pdiag)
     return dict(ftM=ftM, W=W, diag=diag, fx=fws[0], fy=fws[1], fz=fws[2],
                 bx=bws[0], by=bws[1], bz=bws[2], b=b,
                 pdiag=pdiag, cx=cs[0], cy=cs[1], cz=cs[2])

@@ -643,6 +643,9 @@ __global__ __launch_bounds__(BLOCK) void k_schur_faces(DevParams P, const double
     cf[d * N + idx] = c_;
     cst[d] = c_;
   }
+  // the preconditioner's diagonal is raised to S's own where that is larger
+  // (P stays diagonally dominant)
+  if (dg > pd) pd = dg;
   diag[idx] = dg;
   pdiag[idx] = pd;
   b[idx] = bb;

@@ -13,8 +13,8 @@ On random physical states (Sec. 3.2.1, Eqs. 31-35):
         cell's local part 1 + dt theta dL_E/dE - L M^-1 U, which is at least
         1 for monochromatic hydrogen; the preconditioner's operator is that
         local part plus a symmetric diffusion with non-negative face
-        couplings: a symmetric positive definite M-matrix with the same
-        column sums.
+        couplings, its diagonal raised to S's own where that is larger: a
+        symmetric positive definite, diagonally dominant M-matrix.
 The lagged reading (face coefficients held at U^n) is checked the same way
 with those coefficients fixed in the differences.
 """
@@ -130,7 +130,8 @@ def test_dense_brute_force(ns, theta, a, seed, lag):
     assert np.max(np.abs(S - A)) <= 1e-13 * np.max(np.abs(S))
 
     # (iv) column sums = local part; the preconditioner's operator is the
-    # local part plus a symmetric diffusion: an SPD M-matrix
+    # local part plus a symmetric diffusion, its diagonal raised to S's where
+    # that is larger: an SPD M-matrix, diagonally dominant
     M_, Ucol, Lrow, dloc = jacobian.local_blocks(U, nH, eh, dt, a, H, m)
     local = dloc - np.sum(Lrow * sch["W"], axis=0)
     assert np.max(np.abs(A.sum(axis=0) - local.ravel())) <= 1e-12 * np.max(np.abs(A))
@@ -138,6 +139,14 @@ def test_dense_brute_force(ns, theta, a, seed, lag):
         assert np.min(local) >= 1.0 - 1e-12
     Pm = newton.schur_matrix(jacobian.preconditioner_operator(sch)).toarray()
     assert np.array_equal(Pm, Pm.T)
-    assert np.max(np.abs(Pm.sum(axis=0) - local.ravel())) <= 1e-12 * np.max(np.abs(Pm))
-    assert np.all(Pm - np.diag(np.diag(Pm)) <= 0.0)
+    off = Pm - np.diag(np.diag(Pm))
+    assert np.all(off <= 0.0)
+    sums = Pm.sum(axis=0)
+    tol = 1e-12 * np.max(np.abs(Pm))
+    assert np.all(sums >= local.ravel() - tol)
+    raised = np.diag(Pm) - (local.ravel() - off.sum(axis=0))
+    assert np.all(raised >= -tol)
+    # where the diagonal is raised it is S's own
+    up = raised > tol
+    assert np.allclose(np.diag(Pm)[up], np.diag(A)[up], rtol=0, atol=tol)
     assert np.min(np.linalg.eigvalsh(Pm)) > 0
