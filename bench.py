@@ -324,9 +324,9 @@ def main():
                          "0: the fixed relative CG tolerance alone)")
     ap.add_argument("--box-size", type=int, default=None,
                     help="source-subdomain correction: box edge in cells (0: V-cycle alone; "
-                         "default 32 for hii_256, 0 for sg_q05_z4)")
+                         "default 16 for hii_256, 0 for the others)")
     ap.add_argument("--box-levels", type=int, default=2)
-    ap.add_argument("--box-inner", type=int, default=20)
+    ap.add_argument("--box-inner", type=int, default=12)
     ap.add_argument("--box-coarse-sweeps", type=int, default=4,
                     help="sweeps of the coarsest box level (0: those of the main hierarchy)")
     ap.add_argument("--mg-pre", type=int, default=2, help="V-cycle pre-smoothing (red, black) pairs")
@@ -355,7 +355,7 @@ def main():
     if args.n is None:
         args.n = {"hii_256": 256, "sg_q05_z4": 128, "hhe_lognormal_512": 512}[args.workload]
     if args.box_size is None:
-        args.box_size = 32 if args.workload == "hii_256" else 0
+        args.box_size = 16 if args.workload == "hii_256" else 0
     if args.modes is None:
         args.modes = "plain,mixed" if args.workload == "sg_q05_z4" \
             else "plain,mixed,learned,mixed+learned"

@@ -111,10 +111,10 @@ def test_residual_and_schur_sampled_blocks(full, c0):
     assert rel(inner(block(b, c0)), inner(so["b"])) <= 1e-12
 
 
-# the benchmark's default preconditioner: the 32^3 subdomain correction with
-# a two-level box V-cycle (4 coarsest sweeps) and 20 inner iterations, and
+# the benchmark's default preconditioner: the 16^3 subdomain correction with
+# a two-level box V-cycle (4 coarsest sweeps) and 12 inner iterations, and
 # the inexact-Newton forcing 1e-6
-BENCH = dict(box_size=32, box_levels=2, box_inner=20, box_coarse_sweeps=4, pcg_forcing=1e-6)
+BENCH = dict(box_size=16, box_levels=2, box_inner=12, box_coarse_sweeps=4, pcg_forcing=1e-6)
 
 
 # far more inner iterations than the FP32 box solve can use: its residual
