@@ -96,7 +96,8 @@ def train_guess(n_train=128, steps=100, epochs=8, lr=3e-4, log=None, box=(0, 3, 
     t0 = time.perf_counter()
     W = synth.WORKLOADS[workload]
     base = W.replace(n=n_train, mg_levels=4, box_size=box[0], box_levels=box[1],
-                     box_inner=box[2], box_coarse_sweeps=box[3], mg_fp32=0,
+                     box_inner=box[2], box_coarse_sweeps=box[3],
+                     box_s_sweeps=box[4] if len(box) > 4 and box[0] > 0 else 0, mg_fp32=0,
                      nsources=max(1, (W.nsources * n_train ** 3) // W.n ** 3))
     media = [base, base.replace(nsources=2, centred=False, seed=100,
                                 logQ_range=(48.0, 48.7))][:trajectories]
@@ -130,7 +131,7 @@ def train_guess(n_train=128, steps=100, epochs=8, lr=3e-4, log=None, box=(0, 3, 
     return theta, info
 
 
-def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 0),
+def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 0, 0),
              workload="hii_256", adaptive=0.0, smoothing=(2, 2)):
     import torch
     import synth
@@ -140,7 +141,7 @@ def run_mode(mode, steps, warmup, n=256, theta=None, forcing=0.0, box=(0, 3, 6, 
     w = synth.WORKLOADS[workload].replace(
         n=n, mg_fp32=1 if mode.startswith("mixed") else 0, pcg_forcing=forcing,
         box_size=box[0], box_levels=box[1], box_inner=box[2], box_coarse_sweeps=box[3],
-        mg_pre=smoothing[0], mg_post=smoothing[1])
+        box_s_sweeps=box[4] if box[0] > 0 else 0, mg_pre=smoothing[0], mg_post=smoothing[1])
     if mode.endswith("learned"):
         net = RtNet(w.nspecies, (n, n, n))
         net.set_params(theta)
@@ -275,7 +276,9 @@ def cpu_baseline(n=64, box=(0, 3, 6, 0), workload="hii_256"):
 
     w = synth.WORKLOADS[workload].replace(n=n, mg_levels=min(4, synth.WORKLOADS[workload].mg_levels),
                                           box_size=box[0], box_levels=box[1],
-                                          box_inner=box[2], box_coarse_sweeps=box[3])
+                                          box_inner=box[2], box_coarse_sweeps=box[3],
+                                          box_s_sweeps=box[4] if len(box) > 4 and box[0] > 0
+                                          else 0)
     m = oracle.model_from_workload(w)
     s = synth.initial_state(w)
     out = {}
@@ -326,9 +329,12 @@ def main():
                     help="source-subdomain correction: box edge in cells (0: V-cycle alone; "
                          "default 16 for hii_256, 0 for the others)")
     ap.add_argument("--box-levels", type=int, default=2)
-    ap.add_argument("--box-inner", type=int, default=12)
+    ap.add_argument("--box-inner", type=int, default=4)
     ap.add_argument("--box-coarse-sweeps", type=int, default=4,
                     help="sweeps of the coarsest box level (0: those of the main hierarchy)")
+    ap.add_argument("--box-s-sweeps", type=int, default=24,
+                    help="red-black sweeps on the Schur matrix itself over each box after the "
+                         "correction")
     ap.add_argument("--mg-pre", type=int, default=2, help="V-cycle pre-smoothing (red, black) pairs")
     ap.add_argument("--mg-post", type=int, default=2, help="V-cycle post-smoothing pairs")
     ap.add_argument("--adaptive", type=float, default=0.0,
@@ -367,7 +373,8 @@ def main():
     if args.workload == "sg_q05_z4" and any(m.endswith("learned") for m in modes):
         print("no learned guess for the expanding-universe front", file=sys.stderr)
         sys.exit(2)
-    box = (args.box_size, args.box_levels, args.box_inner, args.box_coarse_sweeps)
+    box = (args.box_size, args.box_levels, args.box_inner, args.box_coarse_sweeps,
+           args.box_s_sweeps)
     results = {}
     theta, train_info = None, None
     if any(m.endswith("learned") for m in modes):
@@ -401,8 +408,9 @@ def main():
                                    % args.pcg_forcing if args.pcg_forcing > 0 else "",
                                    args.mg_pre, args.mg_post,
                                    ", then a %d^3 source-subdomain correction (%d inner PCG its, "
-                                   "%d-level box V-cycle)" % (args.box_size, args.box_inner,
-                                                              args.box_levels)
+                                   "%d-level box V-cycle, %d red-black sweeps on S)"
+                                   % (args.box_size, args.box_inner, args.box_levels,
+                                      args.box_s_sweeps)
                                    if args.box_size > 0 else ""),
                    "mode": head, "grid": args.n, "parallelism": "single GPU"},
         "roofline": H.get("roofline"),

@@ -122,6 +122,11 @@ typedef struct rt_params {
                             /* in E and the Schur matrix symmetric); needs         */
                             /* rt_time_level before rt_eval_residual and           */
                             /* rt_schur_form                                       */
+  int32_t box_s_sweeps;     /* with box_size > 0: after the correction, this many  */
+                            /* red-black Gauss-Seidel (red, black) pairs on the    */
+                            /* Schur matrix S itself (not the symmetric operator)  */
+                            /* over the cells of each box, box by box; 0..64, and  */
+                            /* > 0 only with krylov_restart > 0                    */
 } rt_params;
 
 /* Scale factor a and adot/a at t^n (old) and t^{n+1} (new). */

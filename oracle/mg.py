@@ -198,14 +198,47 @@ def pcg_fixed(op, b, ops, model, k, dtype=np.float64):
     return x
 
 
-def preconditioner(op, model, centres=None, precond=True):
+def box_smooth(z, r, sop, centres, B, sweeps):
+    """Red-black Gauss-Seidel on S z = r over the cells of each source's box
+    (the box_cells of box_operator), box by box in source order, `sweeps`
+    (red, black) pairs per box, with the full (non-symmetric) 7-point
+    operator sop = (diag, fx, fy, fz, bx, by, bz); cells outside the boxes
+    are read, not changed.  Each half-sweep works on the box plus a one-cell
+    halo (periodic), so the update of a box cell sees its six neighbours."""
+    diag, fx, fy, fz, bx, by, bz = sop
+    shape = z.shape
+    inner = (slice(1, B + 1),) * 3
+    for c in centres:
+        idx = [(np.arange(-1, B + 1) - B // 2 + ci) % n for ci, n in zip(c, shape)]
+        sel = np.ix_(*idx)
+        box = np.ix_(*[i[1:-1] for i in idx])
+        parity = (idx[0][:, None, None] + idx[1][None, :, None] + idx[2][None, None, :]) % 2
+        d_box = diag[box]
+        fb = [a[sel] for a in (fx, fy, fz)]
+        bb = [a[sel] for a in (bx, by, bz)]
+        r_box = r[box]
+        for _ in range(sweeps):
+            for colour in (0, 1):
+                zh = z[sel]
+                t = r_box.copy()
+                for d in range(3):
+                    t = t + fb[d][inner] * np.roll(zh, -1, axis=d)[inner] \
+                        + np.roll(bb[d] * zh, 1, axis=d)[inner]
+                z[box] = np.where(parity[inner] == colour, t / d_box, zh[inner])
+    return z
+
+
+def preconditioner(op, model, centres=None, precond=True, sop=None):
     """z = P r for the symmetric 7-point operator op = (diag, cx, cy, cz):
     the V-cycle on its hierarchy, followed (model.box_size > 0 with source
     `centres`, (i, j, k) cells) by the source-subdomain correction: on a
     box_size^3 box around every source, model.box_inner iterations of
     flexible PCG from zero for the operator restricted to the boxes, with its
     own box_levels-level V-cycle, applied to the residual the V-cycle left;
-    the boxes' parts are added box by box."""
+    the boxes' parts are added box by box.  With model.box_s_sweeps > 0 and
+    the full operator sop, box_smooth then runs that many (red, black) pairs
+    on S z = r over each box: the part of S that the symmetric operator
+    leaves out matters most around the sources."""
     op = tuple(op[:4])
     if not precond:
         return lambda r: r.copy()
@@ -228,6 +261,8 @@ def preconditioner(op, model, centres=None, precond=True):
             y = pcg_fixed(bop, rb, bops, bmodel, model.box_inner, dt)
             for s_, sel in enumerate(sels):
                 z[sel] += y[s_ * B:(s_ + 1) * B]
+            if model.box_s_sweeps > 0 and sop is not None:
+                z = box_smooth(z, r, sop, centres, B, model.box_s_sweeps)
         return z
     return V
 
@@ -293,7 +328,7 @@ def fgmres(op, pop, b, model, rtol=None, maxit=None, precond=True, atol=0.0, cen
     rtol = model.pcg_rtol if rtol is None else rtol
     maxit = model.pcg_maxit if maxit is None else maxit
     m = model.krylov_restart if restart is None else restart
-    P = preconditioner(pop, model, centres, precond)
+    P = preconditioner(pop, model, centres, precond, sop=op)
     x = np.zeros_like(b)
     bn = np.sqrt(np.sum(b * b))
     if bn == 0.0:

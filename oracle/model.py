@@ -86,6 +86,7 @@ class Model:
     box_levels: int = 3
     box_inner: int = 6
     box_coarse_sweeps: int = 0   # coarsest box level's sweeps, 0: mg_coarse_sweeps
+    box_s_sweeps: int = 0    # red-black sweeps on the Schur matrix itself over each box
 
     @property
     def nv(self):
@@ -160,7 +161,8 @@ def model_from_workload(w, **overrides) -> Model:
               krylov_restart=w.krylov_restart, limiter_lag=w.limiter_lag,
               box_size=w.box_size,
               box_levels=w.box_levels, box_inner=w.box_inner,
-              box_coarse_sweeps=w.box_coarse_sweeps, lte=w.lte, kappa_lte=w.kappa_lte,
+              box_coarse_sweeps=w.box_coarse_sweeps, box_s_sweeps=w.box_s_sweeps,
+              lte=w.lte, kappa_lte=w.kappa_lte,
               kappaP_lte=w.kappaP_lte, mu_lte=w.mu_lte, boundary=w.boundary,
               E_dirichlet=w.E_dirichlet)
     return dataclasses.replace(m, **overrides) if overrides else m

@@ -41,7 +41,7 @@ class RtParams(ctypes.Structure):
         ("lte", ctypes.c_int32), ("kappa_lte", ctypes.c_double), ("kappaP_lte", ctypes.c_double),
         ("mu_lte", ctypes.c_double), ("boundary", ctypes.c_int32),
         ("E_dirichlet", ctypes.c_double), ("krylov_restart", ctypes.c_int32),
-        ("limiter_lag", ctypes.c_int32),
+        ("limiter_lag", ctypes.c_int32), ("box_s_sweeps", ctypes.c_int32),
     ]
 
 
@@ -210,6 +210,7 @@ def params_from_workload(w, **overrides) -> RtParams:
     p.boundary, p.E_dirichlet = w.boundary, w.E_dirichlet
     p.krylov_restart = w.krylov_restart
     p.limiter_lag = w.limiter_lag
+    p.box_s_sweeps = w.box_s_sweeps
     for k, v in overrides.items():
         if k in ("K_gamma", "K_kappa", "K_heat"):
             getattr(p, k)[:] = list(v)

@@ -227,6 +227,10 @@ int validate(const rt_params* p, std::string* why) {
   if (p->krylov_restart < 0 || p->krylov_restart > KMAX - 2)
     return bad("krylov_restart out of range (0: PCG, 1..30: FGMRES restart length)");
   if (p->box_size < 0) return bad("box_size < 0");
+  if (p->box_s_sweeps < 0 || p->box_s_sweeps > 64) return bad("box_s_sweeps out of range (0..64)");
+  if (p->box_s_sweeps > 0 && p->krylov_restart == 0)
+    return bad("box_s_sweeps needs FGMRES (krylov_restart > 0): the sweeps make the "
+               "preconditioner non-symmetric");
   if (p->box_size > 0) {
     if (p->box_levels < 1 || p->box_levels > 12 || p->box_inner < 1 || p->box_coarse_sweeps < 0)
       return bad("box_levels out of range, box_inner < 1 or box_coarse_sweeps < 0");
@@ -652,6 +656,14 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
                                   dots > 0 ? w.parts + (size_t)(dots + s * nbb) * NCOMP_MAX
                                            : nullptr,
                                   st));
+  // red-black sweeps on S itself over each box, box by box in source order:
+  // per half-sweep the box's diag, fw, bw, r and z cells (FP64)
+  for (int s = 0; s < g->nbox; ++s)
+    for (int k = 0; k < g->prm.box_s_sweeps; ++k)
+      for (int colour = 0; colour < 2; ++colour)
+        TKB(g, RT_K_BOX, Fb * 8.0 * 5.0,
+            launch_box_smooth_s(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, s, colour,
+                                w.diag, w.fw, w.bw, r, z, st));
   g->tk_override = -1;
 }
 

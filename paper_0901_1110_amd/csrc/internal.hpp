@@ -150,6 +150,11 @@ template <class T>
 void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
                             const T* y, double* z, const double* r, const double* q,
                             double* parts, hipStream_t st);
+// red-black half-sweep of colour `colour` on S z = r (full Schur operator,
+// FP64 main grid) over the cells of box s
+void launch_box_smooth_s(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
+                         int colour, const double* diag, const double* fw, const double* bw,
+                         const double* r, double* z, hipStream_t st);
 // inner PCG of the correction on the stacked boxes (level L: the box
 // operator in T); the reduction launches return their partial count
 template <class T>

@@ -1432,6 +1432,32 @@ __global__ __launch_bounds__(BLOCK) void k_box_scatter_add(BoxMap m, const long 
   if (parts) block_reduce<2>(acc, parts);
 }
 
+// one red-black Gauss-Seidel half-sweep of colour `colour` on S z = r over
+// the cells of box s, with the full Schur operator (diag, fw, bw; FP64, the
+// main grid): z_P = (r_P + sum_d [fw_d[P] z_{P+d} + bw_d[P-d] z_{P-d}]) / diag_P
+// for the box's cells of that colour (colour = (i + j + k) & 1 on the grid)
+__global__ __launch_bounds__(BLOCK) void k_box_smooth_s(BoxMap m, const long long* __restrict__ cells,
+                                                         int s, int colour,
+                                                         const double* __restrict__ diag,
+                                                         const double* __restrict__ fw,
+                                                         const double* __restrict__ bw,
+                                                         const double* __restrict__ r,
+                                                         double* __restrict__ z) {
+  const C3 c = coord3(m.B, m.B);
+  if (!c.ok) return;
+  const int g = box_global(m, cells[s], c.i, c.j, c.k);
+  const int nyz = m.ny * m.nz;
+  const int gi = g / nyz, gj = (g - gi * nyz) / m.nz, gk = g - gi * nyz - gj * m.nz;
+  if (((gi + gj + gk) & 1) != colour) return;
+  const Nb nb = nbrs(gi, gj, gk, m.nx, m.ny, m.nz);
+  const long N = (long)m.nx * nyz;
+  double t = r[g];
+  t = t + fw[g] * z[nb.xp] + bw[nb.xm] * z[nb.xm];
+  t = t + fw[N + g] * z[nb.yp] + bw[N + nb.ym] * z[nb.ym];
+  t = t + fw[2 * N + g] * z[nb.zp] + bw[2 * N + nb.zm] * z[nb.zm];
+  z[g] = t / diag[g];
+}
+
 // ---- inner PCG of the subdomain correction, T the box V-cycle's type (the
 // vectors are kept in it; dot products accumulate in FP64 and leave block
 // partials, which the kernel that needs a CG scalar sums itself).
@@ -1889,6 +1915,13 @@ void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long 
   const BoxMap m{nx, ny, nz, B, nbox};
   const Geo gq = geo3(B, B, B);
   hipLaunchKernelGGL(k_box_scatter_add<T>, gq.g, gq.b, 0, st, m, cells, s, y, z, r, q, parts);
+}
+void launch_box_smooth_s(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
+                         int colour, const double* diag, const double* fw, const double* bw,
+                         const double* r, double* z, hipStream_t st) {
+  const BoxMap m{nx, ny, nz, B, nbox};
+  const Geo gq = geo3(B, B, B);
+  hipLaunchKernelGGL(k_box_smooth_s, gq.g, gq.b, 0, st, m, cells, s, colour, diag, fw, bw, r, z);
 }
 template <class T>
 int launch_box_dot1p(long n, const T* r, const T* z, T* p, double* parts, hipStream_t st) {

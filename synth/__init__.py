@@ -88,6 +88,7 @@ class Workload:
     box_levels: int = 3
     box_inner: int = 6
     box_coarse_sweeps: int = 0  # coarsest box level's sweeps (0: mg_coarse_sweeps)
+    box_s_sweeps: int = 0       # red-black sweeps on the Schur matrix over each box
     lte: int = 0                # 1: LTE coupling, no species (nspecies = 0)
     kappa_lte: float = 0.0      # LTE absorption coefficient (proper, 1/cm)
     kappaP_lte: float = 0.0     # LTE Planck-mean coefficient (proper, 1/cm)

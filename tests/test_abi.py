@@ -62,12 +62,18 @@ def test_workspace_bytes_and_validation():
                        ("u_E", -1.0), ("newton_maxit", 99), ("limiter_mode", 5),
                        ("nspecies", 0), ("lte", 1), ("lte", 2), ("boundary", 3),
                        ("boundary", -1), ("pcg_forcing", -1e-6), ("box_size", 20),
-                       ("box_size", 512), ("krylov_restart", -1), ("krylov_restart", 31)):
+                       ("box_size", 512), ("krylov_restart", -1), ("krylov_restart", 31),
+                       ("box_s_sweeps", -1), ("box_s_sweeps", 65)):
         q = b.params_from_workload(synth.CFG_256, **{field: bad})
         assert lib.rt_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == b.RT_EINVAL, field
         h = ctypes.c_void_p()
         assert lib.rt_create_grid(ctypes.byref(q), ctypes.c_void_p(256), 1 << 40, None,
                                   ctypes.byref(h)) == b.RT_EINVAL
+    # the box sweeps on S make the preconditioner non-symmetric: FGMRES only
+    q = b.params_from_workload(synth.CFG_256, box_s_sweeps=2, krylov_restart=0)
+    assert lib.rt_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == b.RT_EINVAL
+    q = b.params_from_workload(synth.CFG_256, box_s_sweeps=2)
+    assert lib.rt_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == b.RT_OK
     # combinations: LTE needs nspecies = 0 and finite coefficients; a held
     # face needs a finite, non-negative value
     for over in (dict(lte=1, nspecies=0, mu_lte=0.0), dict(lte=1, nspecies=0, kappa_lte=-1.0),

@@ -185,11 +185,14 @@ def test_fgmres_fixed_iterations(k):
     assert abs(rr - rr_o) <= 1e-9 * max(rr_o, 1e-30) + 1e-14
 
 
-@pytest.mark.parametrize("k", [4, 11])
-def test_fgmres_fixed_iterations_with_boxes(k):
+@pytest.mark.parametrize("k,sweeps", [(4, 0), (11, 0), (4, 2), (11, 1)])
+def test_fgmres_fixed_iterations_with_boxes(k, sweeps):
     """The same with the source-subdomain correction in the preconditioner
-    (8^3 boxes around the case's three sources, 4 inner iterations)."""
-    m, g, sch = schur_case(32, 3, 33, box_size=8, box_levels=2, box_inner=4, box_coarse_sweeps=3)
+    (8^3 boxes around the case's three sources, 4 inner iterations), and
+    with red-black sweeps on S over the boxes after it (overlapping boxes
+    are swept in source order)."""
+    m, g, sch = schur_case(32, 3, 33, box_size=8, box_levels=2, box_inner=4, box_coarse_sweeps=3,
+                           box_s_sweeps=sweeps)
     w_cells = g._cells
     centres = [np.unravel_index(int(c), sch["b"].shape) for c in w_cells]
     s, its, rr = g.rt_mg_pcg_solve(dev(sch["b"]), 0.0, k)
@@ -253,6 +256,15 @@ def test_newton_steps_source_boxes():
     counts, fields to 1e-10."""
     w = synth.CFG_256.replace(n=64, mg_levels=4, box_size=16, box_levels=2, box_inner=4,
                               box_coarse_sweeps=3)
+    newton_parity(w, synth.initial_state(w), steps=3)
+
+
+def test_newton_steps_source_boxes_with_s_sweeps():
+    """The correction followed by two red-black sweeps on the Schur matrix
+    itself over the box (the benchmark's preconditioner at 64^3): equal
+    counts, fields to 1e-10."""
+    w = synth.CFG_256.replace(n=64, mg_levels=4, box_size=16, box_levels=2, box_inner=12,
+                              box_coarse_sweeps=4, box_s_sweeps=2, pcg_forcing=1e-6)
     newton_parity(w, synth.initial_state(w), steps=3)
 
 

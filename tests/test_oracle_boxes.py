@@ -86,3 +86,46 @@ def test_fixed_count_pcg_stops_moving_once_converged():
         x = mg.pcg_fixed(op, b, ops, m, k)
         assert np.all(np.isfinite(x))
         assert np.max(np.abs(x - x_ref)) <= 1e-10 * np.max(np.abs(x_ref)), k
+
+
+def test_box_smoothing_on_the_full_operator():
+    """box_smooth: Gauss-Seidel on S z = r over a box.  With the box covering
+    the whole grid, repeated sweeps on a diagonally dominant non-symmetric
+    7-point operator converge to the direct solution; with a smaller box only
+    its cells change, and one sweep there equals the red then black updates
+    written out cell by cell."""
+    import scipy.sparse.linalg as spla
+    from oracle import mg, newton
+    rng = np.random.default_rng(5)
+    n = 8
+    shape = (n, n, n)
+    fs = [rng.uniform(0.0, 1.0, shape) for _ in range(3)]
+    bs = [rng.uniform(0.0, 1.0, shape) for _ in range(3)]
+    diag = 7.0 + rng.uniform(0.0, 1.0, shape)
+    sop = (diag, fs[0], fs[1], fs[2], bs[0], bs[1], bs[2])
+    r = rng.standard_normal(shape)
+    A = newton.schur_matrix(sop).tocsc()
+    exact = spla.spsolve(A, r.ravel()).reshape(shape)
+    z = mg.box_smooth(np.zeros(shape), r, sop, [(4, 4, 4)], n, 60)
+    assert np.max(np.abs(z - exact)) <= 1e-10 * np.max(np.abs(exact))
+    # a 4^3 box: cells outside keep their values
+    z0 = rng.standard_normal(shape)
+    z1 = mg.box_smooth(z0.copy(), r, sop, [(2, 3, 4)], 4, 1)
+    inside = np.zeros(shape, dtype=bool)
+    inside[np.ix_(*mg.box_cells((2, 3, 4), 4, shape))] = True
+    assert np.array_equal(z1[~inside], z0[~inside])
+    # the same sweep written cell by cell (red cells first, then black)
+    z2 = z0.copy()
+    for colour in (0, 1):
+        for i, j, k in zip(*np.nonzero(inside)):
+            if (i + j + k) % 2 != colour:
+                continue
+            t = r[i, j, k]
+            for d, (f, b) in enumerate(zip(fs, bs)):
+                p = [i, j, k]
+                q = list(p)
+                p[d] = (p[d] + 1) % n
+                q[d] = (q[d] - 1) % n
+                t += f[i, j, k] * z2[tuple(p)] + b[tuple(q)] * z2[tuple(q)]
+            z2[i, j, k] = t / diag[i, j, k]
+    assert np.allclose(z1, z2, rtol=1e-14, atol=0.0)
