@@ -63,17 +63,17 @@ HBM_PEAK_GBS = 8000.0
 # as null for any other.
 PMC_TRAFFIC = {
     ("cg_vector", "mixed", 256): {"ratio": 1.000, "kernels_sha256":
-                                  "3117e82e5796eb51d3fd0e97dfbf73f7d40a4e88dac2fb37729a39074ffd6014"},
+                                  "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
     ("cg_vector", "mixed+learned", 256): {"ratio": 1.000, "kernels_sha256":
-                                          "3117e82e5796eb51d3fd0e97dfbf73f7d40a4e88dac2fb37729a39074ffd6014"},
-    ("spmv", "mixed", 256): {"ratio": 1.291, "kernels_sha256":
-                             "3117e82e5796eb51d3fd0e97dfbf73f7d40a4e88dac2fb37729a39074ffd6014"},
-    ("spmv", "mixed+learned", 256): {"ratio": 1.291, "kernels_sha256":
-                                     "3117e82e5796eb51d3fd0e97dfbf73f7d40a4e88dac2fb37729a39074ffd6014"},
+                                          "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
+    ("spmv", "mixed", 256): {"ratio": 1.349, "kernels_sha256":
+                             "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
+    ("spmv", "mixed+learned", 256): {"ratio": 1.349, "kernels_sha256":
+                                     "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
     ("rbgs_fine", "mixed", 256): {"ratio": 1.134, "kernels_sha256":
-                                  "3117e82e5796eb51d3fd0e97dfbf73f7d40a4e88dac2fb37729a39074ffd6014"},
+                                  "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
     ("rbgs_fine", "mixed+learned", 256): {"ratio": 1.134, "kernels_sha256":
-                                          "3117e82e5796eb51d3fd0e97dfbf73f7d40a4e88dac2fb37729a39074ffd6014"},
+                                          "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
 }
 
 
