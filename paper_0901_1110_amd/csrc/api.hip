@@ -656,14 +656,24 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
                                   dots > 0 ? w.parts + (size_t)(dots + s * nbb) * NCOMP_MAX
                                            : nullptr,
                                   st));
-  // red-black sweeps on S itself over each box, box by box in source order:
-  // per half-sweep the box's diag, fw, bw, r and z cells (FP64)
-  for (int s = 0; s < g->nbox; ++s)
+  // red-black sweeps on S itself over each box, box by box in source order;
+  // a box below BOX_S_LDS_MAX and the grid size takes all its sweeps in one
+  // on-chip launch (diag, fw, bw, r in, z in and out once), a larger one a
+  // launch per half-sweep (the box's diag, fw, bw, r and z cells each time)
+  const bool s_lds = B <= BOX_S_LDS_MAX && B < g->P.nx && B < g->P.ny && B < g->P.nz;
+  for (int s = 0; s < g->nbox && g->prm.box_s_sweeps > 0; ++s) {
+    if (s_lds) {
+      TKB(g, RT_K_BOX, Fb * 8.0 * 10.0,
+          launch_box_smooth_s_lds(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, s,
+                                  g->prm.box_s_sweeps, w.diag, w.fw, w.bw, r, z, st));
+      continue;
+    }
     for (int k = 0; k < g->prm.box_s_sweeps; ++k)
       for (int colour = 0; colour < 2; ++colour)
         TKB(g, RT_K_BOX, Fb * 8.0 * 5.0,
             launch_box_smooth_s(g->P.nx, g->P.ny, g->P.nz, B, g->nbox, w.src_cells, s, colour,
                                 w.diag, w.fw, w.bw, r, z, st));
+  }
   g->tk_override = -1;
 }
 

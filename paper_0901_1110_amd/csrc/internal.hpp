@@ -155,6 +155,13 @@ void launch_box_scatter_add(int nx, int ny, int nz, int B, int nbox, const long 
 void launch_box_smooth_s(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
                          int colour, const double* diag, const double* fw, const double* bw,
                          const double* r, double* z, hipStream_t st);
+// all `sweeps` (red, black) sweeps of launch_box_smooth_s over box s in one
+// workgroup with the box in LDS; for B <= BOX_S_LDS_MAX and B smaller than
+// nx, ny and nz
+constexpr int BOX_S_LDS_MAX = 16;
+void launch_box_smooth_s_lds(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
+                             int sweeps, const double* diag, const double* fw, const double* bw,
+                             const double* r, double* z, hipStream_t st);
 // inner PCG of the correction on the stacked boxes (level L: the box
 // operator in T); the reduction launches return their partial count
 template <class T>

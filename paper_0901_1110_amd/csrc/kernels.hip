@@ -1458,6 +1458,81 @@ __global__ __launch_bounds__(BLOCK) void k_box_smooth_s(BoxMap m, const long lon
   z[g] = t / diag[g];
 }
 
+// all `sweeps` (red, black) sweeps of k_box_smooth_s over box s in one
+// workgroup, for B <= BOX_S_LDS_MAX and B below the grid size in every
+// direction: the box's z and its one-cell halo sit in LDS, each owned cell's
+// r, diagonal and six couplings in registers, so the 2 * sweeps half-sweeps
+// touch no memory.  The halo is not updated, as in the per-half-sweep form:
+// with B < n no halo cell is also a box cell.  Same arithmetic per cell.
+constexpr int BS_THREADS = 1024, BS_CPT = 4;   // BOX_S_LDS_MAX^3 = BS_CPT * BS_THREADS
+static_assert(BOX_S_LDS_MAX * BOX_S_LDS_MAX * BOX_S_LDS_MAX <= BS_CPT * BS_THREADS, "box cells");
+__global__ __launch_bounds__(BS_THREADS) void k_box_smooth_s_lds(BoxMap m,
+                                                                  const long long* __restrict__ cells,
+                                                                  int s, int sweeps,
+                                                                  const double* __restrict__ diag,
+                                                                  const double* __restrict__ fw,
+                                                                  const double* __restrict__ bw,
+                                                                  const double* __restrict__ r,
+                                                                  double* __restrict__ z) {
+  constexpr int E = BOX_S_LDS_MAX + 2;
+  __shared__ double zs[E * E * E];
+  const int B = m.B, H = B + 2, H2 = H * H, nb3 = B * B * B;
+  const int nyz = m.ny * m.nz;
+  const long N = (long)m.nx * nyz;
+  const long long c0 = cells[s];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < H2 * H; t += BS_THREADS) {
+    const int hi = t / H2, hj = (t / H) % H, hk = t % H;
+    zs[t] = z[box_global(m, c0, hi - 1, hj - 1, hk - 1)];
+  }
+  double cr[BS_CPT], cd[BS_CPT], c6[BS_CPT][6];
+  int own[BS_CPT], col[BS_CPT], gl[BS_CPT];
+#pragma unroll
+  for (int q = 0; q < BS_CPT; ++q) {
+    const int t = tid + q * BS_THREADS;
+    own[q] = -1;
+    col[q] = -1;
+    gl[q] = 0;
+    if (t < nb3) {
+      const int bi = t / (B * B), bj = (t / B) % B, bk = t % B;
+      const int g = box_global(m, c0, bi, bj, bk);
+      const int gi = g / nyz, gj = (g - gi * nyz) / m.nz, gk = g - gi * nyz - gj * m.nz;
+      const Nb nb = nbrs(gi, gj, gk, m.nx, m.ny, m.nz);
+      own[q] = ((bi + 1) * H + (bj + 1)) * H + (bk + 1);
+      col[q] = (gi + gj + gk) & 1;
+      gl[q] = g;
+      cr[q] = r[g];
+      cd[q] = diag[g];
+      c6[q][0] = fw[g];
+      c6[q][1] = bw[nb.xm];
+      c6[q][2] = fw[N + g];
+      c6[q][3] = bw[N + nb.ym];
+      c6[q][4] = fw[2 * N + g];
+      c6[q][5] = bw[2 * N + nb.zm];
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < sweeps; ++k) {
+    for (int colour = 0; colour < 2; ++colour) {
+#pragma unroll
+      for (int q = 0; q < BS_CPT; ++q) {
+        if (col[q] == colour) {
+          const int o = own[q];
+          double t = cr[q];
+          t = t + c6[q][0] * zs[o + H2] + c6[q][1] * zs[o - H2];
+          t = t + c6[q][2] * zs[o + H] + c6[q][3] * zs[o - H];
+          t = t + c6[q][4] * zs[o + 1] + c6[q][5] * zs[o - 1];
+          zs[o] = t / cd[q];
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < BS_CPT; ++q)
+    if (own[q] >= 0) z[gl[q]] = zs[own[q]];
+}
+
 // ---- inner PCG of the subdomain correction, T the box V-cycle's type (the
 // vectors are kept in it; dot products accumulate in FP64 and leave block
 // partials, which the kernel that needs a CG scalar sums itself).
@@ -1922,6 +1997,13 @@ void launch_box_smooth_s(int nx, int ny, int nz, int B, int nbox, const long lon
   const BoxMap m{nx, ny, nz, B, nbox};
   const Geo gq = geo3(B, B, B);
   hipLaunchKernelGGL(k_box_smooth_s, gq.g, gq.b, 0, st, m, cells, s, colour, diag, fw, bw, r, z);
+}
+void launch_box_smooth_s_lds(int nx, int ny, int nz, int B, int nbox, const long long* cells, int s,
+                             int sweeps, const double* diag, const double* fw, const double* bw,
+                             const double* r, double* z, hipStream_t st) {
+  const BoxMap m{nx, ny, nz, B, nbox};
+  hipLaunchKernelGGL(k_box_smooth_s_lds, dim3(1), dim3(BS_THREADS), 0, st, m, cells, s, sweeps, diag,
+                     fw, bw, r, z);
 }
 template <class T>
 int launch_box_dot1p(long n, const T* r, const T* z, T* p, double* parts, hipStream_t st) {

@@ -185,14 +185,16 @@ def test_fgmres_fixed_iterations(k):
     assert abs(rr - rr_o) <= 1e-9 * max(rr_o, 1e-30) + 1e-14
 
 
-@pytest.mark.parametrize("k,sweeps", [(4, 0), (11, 0), (4, 2), (11, 1)])
-def test_fgmres_fixed_iterations_with_boxes(k, sweeps):
+@pytest.mark.parametrize("k,sweeps,bsize", [(4, 0, 8), (11, 0, 8), (4, 2, 8), (11, 1, 8),
+                                             (4, 3, 24)])
+def test_fgmres_fixed_iterations_with_boxes(k, sweeps, bsize):
     """The same with the source-subdomain correction in the preconditioner
-    (8^3 boxes around the case's three sources, 4 inner iterations), and
-    with red-black sweeps on S over the boxes after it (overlapping boxes
-    are swept in source order)."""
-    m, g, sch = schur_case(32, 3, 33, box_size=8, box_levels=2, box_inner=4, box_coarse_sweeps=3,
-                           box_s_sweeps=sweeps)
+    (boxes around the case's three sources, 4 inner iterations), and with
+    red-black sweeps on S over the boxes after it (overlapping boxes are
+    swept in source order).  8^3 boxes take all their sweeps in one on-chip
+    launch per box, 24^3 boxes a launch per half-sweep."""
+    m, g, sch = schur_case(32, 3, 33, box_size=bsize, box_levels=2, box_inner=4,
+                           box_coarse_sweeps=3, box_s_sweeps=sweeps)
     w_cells = g._cells
     centres = [np.unravel_index(int(c), sch["b"].shape) for c in w_cells]
     s, its, rr = g.rt_mg_pcg_solve(dev(sch["b"]), 0.0, k)
