@@ -125,7 +125,7 @@ typedef struct rt_params {
   int32_t box_s_sweeps;     /* with box_size > 0: after the correction, this many  */
                             /* red-black Gauss-Seidel (red, black) pairs on the    */
                             /* Schur matrix S itself (not the symmetric operator)  */
-                            /* over the cells of each box, box by box; 0..64, and  */
+                            /* over the cells of each box, box by box; 0..256, and */
                             /* > 0 only with krylov_restart > 0                    */
 } rt_params;
 

@@ -227,7 +227,7 @@ int validate(const rt_params* p, std::string* why) {
   if (p->krylov_restart < 0 || p->krylov_restart > KMAX - 2)
     return bad("krylov_restart out of range (0: PCG, 1..30: FGMRES restart length)");
   if (p->box_size < 0) return bad("box_size < 0");
-  if (p->box_s_sweeps < 0 || p->box_s_sweeps > 64) return bad("box_s_sweeps out of range (0..64)");
+  if (p->box_s_sweeps < 0 || p->box_s_sweeps > 256) return bad("box_s_sweeps out of range (0..256)");
   if (p->box_s_sweeps > 0 && p->krylov_restart == 0)
     return bad("box_s_sweeps needs FGMRES (krylov_restart > 0): the sweeps make the "
                "preconditioner non-symmetric");

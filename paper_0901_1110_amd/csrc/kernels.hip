@@ -838,10 +838,38 @@ __device__ inline void block_reduce_n(const double (&v)[NC], double* __restrict_
 // number of blocks (reduce_blocks), so the partial sums, and hence the
 // results, do not depend on timing.
 
+// Cells of this block in a grid-stride walk that keeps each XCD on one
+// contiguous part of the grid.  The hardware places block b on XCD b mod 8;
+// with a block count and N divisible by 8, XCD x walks cells
+// [x N/8, (x+1) N/8) with its gridDim/8 blocks, so the neighbour rows and
+// planes a stencil reads were fetched into the same XCD's L2 by its own
+// blocks (with plain round-robin every row's y-neighbours sit on two other
+// XCDs).  Otherwise the plain grid-stride walk.  Either way each block's cell
+// set is fixed, so its partial sums do not depend on timing.
+struct XcdRange {
+  long first, end, stride;
+};
+__device__ inline XcdRange xcd_range(long N) {
+  const int nb = gridDim.x;
+  if ((nb & 7) == 0 && (N & 7) == 0) {
+    const long chunk = N >> 3;
+    const long base = (long)(blockIdx.x & 7) * chunk;
+    return XcdRange{base + (long)(blockIdx.x >> 3) * BLOCK + threadIdx.x, base + chunk,
+                    (long)(nb >> 3) * BLOCK};
+  }
+  return XcdRange{blockIdx.x * (long)BLOCK + threadIdx.x, N, (long)nb * BLOCK};
+}
+
+// a load of a value this launch reads once: marked non-temporal so that it
+// does not push out of L2 the values that neighbouring cells read again
+__device__ inline double ldnt(const double* p) { return __builtin_nontemporal_load(p); }
+
 // w = S z (bsub null) or w = bsub - S z for the full 7-point operator
 // (S x)_P = diag_P x_P - sum_d [fw_d[P] x_{P+d} + bw_d[P-d] x_{P-d}];
 // zcopy non-null: also zcopy = z.  Partials of w.V_i (i < NV, V_i at
-// V + i N) and of w.w (component NV).
+// V + i N) and of w.w (component NV).  The operator and the basis vectors
+// are read once (non-temporal); z at seven points, and the XCD-contiguous
+// walk keeps its neighbour rows and planes in the walking XCD's L2.
 template <int NV>
 __global__ __launch_bounds__(BLOCK) void k_spmv_full(int nx, int ny, int nz,
                                                       const double* __restrict__ diag,
@@ -857,19 +885,20 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_full(int nx, int ny, int nz,
   double acc[NV + 1];
 #pragma unroll
   for (int c = 0; c <= NV; ++c) acc[c] = 0.0;
-  for (long n = blockIdx.x * (long)BLOCK + threadIdx.x; n < N; n += (long)gridDim.x * BLOCK) {
+  const XcdRange xr = xcd_range(N);
+  for (long n = xr.first; n < xr.end; n += xr.stride) {
     int i, j, k;
     cell_ijk(n, ny, nz, i, j, k);
     const Nb nb = nbrs(i, j, k, nx, ny, nz);
     const int idx = (int)n;
     double vv[NV > 0 ? NV : 1];
 #pragma unroll
-    for (int c = 0; c < NV; ++c) vv[c] = V[(size_t)c * N + idx];
+    for (int c = 0; c < NV; ++c) vv[c] = ldnt(&V[(size_t)c * N + idx]);
     const double zv = z[idx];
-    double y = diag[idx] * zv;
-    y = y - fw[idx] * z[nb.xp] - bw[nb.xm] * z[nb.xm];
-    y = y - fw[N + idx] * z[nb.yp] - bw[N + nb.ym] * z[nb.ym];
-    y = y - fw[2 * N + idx] * z[nb.zp] - bw[2 * N + nb.zm] * z[nb.zm];
+    double y = ldnt(&diag[idx]) * zv;
+    y = y - ldnt(&fw[idx]) * z[nb.xp] - ldnt(&bw[nb.xm]) * z[nb.xm];
+    y = y - ldnt(&fw[N + idx]) * z[nb.yp] - ldnt(&bw[N + nb.ym]) * z[nb.ym];
+    y = y - ldnt(&fw[2 * N + idx]) * z[nb.zp] - ldnt(&bw[2 * N + nb.zm]) * z[nb.zm];
     if (bsub) y = bsub[idx] - y;
     w[idx] = y;
     if (zcopy) zcopy[idx] = zv;
@@ -1464,8 +1493,12 @@ __global__ __launch_bounds__(BLOCK) void k_box_smooth_s(BoxMap m, const long lon
 // r, diagonal and six couplings in registers, so the 2 * sweeps half-sweeps
 // touch no memory.  The halo is not updated, as in the per-half-sweep form:
 // with B < n no halo cell is also a box cell.  Same arithmetic per cell.
-constexpr int BS_THREADS = 1024, BS_CPT = 4;   // BOX_S_LDS_MAX^3 = BS_CPT * BS_THREADS
-static_assert(BOX_S_LDS_MAX * BOX_S_LDS_MAX * BOX_S_LDS_MAX <= BS_CPT * BS_THREADS, "box cells");
+// Threads own cells by colour: place p of a colour's list is the m-th cell of
+// that colour in z-line (bi, bj) (p = line * B/2 + m; B is even, so every line
+// holds B/2 cells of each colour), so a half-sweep keeps every lane busy.
+constexpr int BS_THREADS = 1024;
+constexpr int BS_CPC = (BOX_S_LDS_MAX * BOX_S_LDS_MAX * BOX_S_LDS_MAX / 2 + BS_THREADS - 1) /
+                       BS_THREADS;   // cells per thread and colour
 __global__ __launch_bounds__(BS_THREADS) void k_box_smooth_s_lds(BoxMap m,
                                                                   const long long* __restrict__ cells,
                                                                   int s, int sweeps,
@@ -1476,7 +1509,7 @@ __global__ __launch_bounds__(BS_THREADS) void k_box_smooth_s_lds(BoxMap m,
                                                                   double* __restrict__ z) {
   constexpr int E = BOX_S_LDS_MAX + 2;
   __shared__ double zs[E * E * E];
-  const int B = m.B, H = B + 2, H2 = H * H, nb3 = B * B * B;
+  const int B = m.B, H = B + 2, H2 = H * H, hb = B >> 1, nhalf = B * B * hb;
   const int nyz = m.ny * m.nz;
   const long N = (long)m.nx * nyz;
   const long long c0 = cells[s];
@@ -1485,52 +1518,62 @@ __global__ __launch_bounds__(BS_THREADS) void k_box_smooth_s_lds(BoxMap m,
     const int hi = t / H2, hj = (t / H) % H, hk = t % H;
     zs[t] = z[box_global(m, c0, hi - 1, hj - 1, hk - 1)];
   }
-  double cr[BS_CPT], cd[BS_CPT], c6[BS_CPT][6];
-  int own[BS_CPT], col[BS_CPT], gl[BS_CPT];
+  // colour of box cell (0, 0, 0); box cell (bi, bj, bk) has colour
+  // (p0 + bi + bj + bk) & 1 (the grid sizes are even)
+  const int g0 = box_global(m, c0, 0, 0, 0);
+  const int p0 = (g0 / nyz + (g0 % nyz) / m.nz + g0 % m.nz) & 1;
+  double cr[2][BS_CPC], cd[2][BS_CPC], c6[2][BS_CPC][6];
+  int own[2][BS_CPC], gl[2][BS_CPC];
 #pragma unroll
-  for (int q = 0; q < BS_CPT; ++q) {
-    const int t = tid + q * BS_THREADS;
-    own[q] = -1;
-    col[q] = -1;
-    gl[q] = 0;
-    if (t < nb3) {
-      const int bi = t / (B * B), bj = (t / B) % B, bk = t % B;
-      const int g = box_global(m, c0, bi, bj, bk);
-      const int gi = g / nyz, gj = (g - gi * nyz) / m.nz, gk = g - gi * nyz - gj * m.nz;
-      const Nb nb = nbrs(gi, gj, gk, m.nx, m.ny, m.nz);
-      own[q] = ((bi + 1) * H + (bj + 1)) * H + (bk + 1);
-      col[q] = (gi + gj + gk) & 1;
-      gl[q] = g;
-      cr[q] = r[g];
-      cd[q] = diag[g];
-      c6[q][0] = fw[g];
-      c6[q][1] = bw[nb.xm];
-      c6[q][2] = fw[N + g];
-      c6[q][3] = bw[N + nb.ym];
-      c6[q][4] = fw[2 * N + g];
-      c6[q][5] = bw[2 * N + nb.zm];
+  for (int colour = 0; colour < 2; ++colour) {
+#pragma unroll
+    for (int q = 0; q < BS_CPC; ++q) {
+      const int p = tid + q * BS_THREADS;
+      own[colour][q] = -1;
+      gl[colour][q] = 0;
+      if (p < nhalf) {
+        const int line = p / hb, mm = p - line * hb;
+        const int bi = line / B, bj = line - bi * B;
+        const int bk = 2 * mm + ((colour + p0 + bi + bj) & 1);
+        const int g = box_global(m, c0, bi, bj, bk);
+        const int gi = g / nyz, gj = (g - gi * nyz) / m.nz, gk = g - gi * nyz - gj * m.nz;
+        const Nb nb = nbrs(gi, gj, gk, m.nx, m.ny, m.nz);
+        own[colour][q] = ((bi + 1) * H + (bj + 1)) * H + (bk + 1);
+        gl[colour][q] = g;
+        cr[colour][q] = r[g];
+        cd[colour][q] = diag[g];
+        c6[colour][q][0] = fw[g];
+        c6[colour][q][1] = bw[nb.xm];
+        c6[colour][q][2] = fw[N + g];
+        c6[colour][q][3] = bw[N + nb.ym];
+        c6[colour][q][4] = fw[2 * N + g];
+        c6[colour][q][5] = bw[2 * N + nb.zm];
+      }
     }
   }
   __syncthreads();
   for (int k = 0; k < sweeps; ++k) {
+#pragma unroll
     for (int colour = 0; colour < 2; ++colour) {
 #pragma unroll
-      for (int q = 0; q < BS_CPT; ++q) {
-        if (col[q] == colour) {
-          const int o = own[q];
-          double t = cr[q];
-          t = t + c6[q][0] * zs[o + H2] + c6[q][1] * zs[o - H2];
-          t = t + c6[q][2] * zs[o + H] + c6[q][3] * zs[o - H];
-          t = t + c6[q][4] * zs[o + 1] + c6[q][5] * zs[o - 1];
-          zs[o] = t / cd[q];
+      for (int q = 0; q < BS_CPC; ++q) {
+        const int o = own[colour][q];
+        if (o >= 0) {
+          double t = cr[colour][q];
+          t = t + c6[colour][q][0] * zs[o + H2] + c6[colour][q][1] * zs[o - H2];
+          t = t + c6[colour][q][2] * zs[o + H] + c6[colour][q][3] * zs[o - H];
+          t = t + c6[colour][q][4] * zs[o + 1] + c6[colour][q][5] * zs[o - 1];
+          zs[o] = t / cd[colour][q];
         }
       }
       __syncthreads();
     }
   }
 #pragma unroll
-  for (int q = 0; q < BS_CPT; ++q)
-    if (own[q] >= 0) z[gl[q]] = zs[own[q]];
+  for (int colour = 0; colour < 2; ++colour)
+#pragma unroll
+    for (int q = 0; q < BS_CPC; ++q)
+      if (own[colour][q] >= 0) z[gl[colour][q]] = zs[own[colour][q]];
 }
 
 // ---- inner PCG of the subdomain correction, T the box V-cycle's type (the

@@ -63,7 +63,7 @@ def test_workspace_bytes_and_validation():
                        ("nspecies", 0), ("lte", 1), ("lte", 2), ("boundary", 3),
                        ("boundary", -1), ("pcg_forcing", -1e-6), ("box_size", 20),
                        ("box_size", 512), ("krylov_restart", -1), ("krylov_restart", 31),
-                       ("box_s_sweeps", -1), ("box_s_sweeps", 65)):
+                       ("box_s_sweeps", -1), ("box_s_sweeps", 257)):
         q = b.params_from_workload(synth.CFG_256, **{field: bad})
         assert lib.rt_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == b.RT_EINVAL, field
         h = ctypes.c_void_p()
