@@ -332,7 +332,7 @@ def main():
     ap.add_argument("--box-inner", type=int, default=4)
     ap.add_argument("--box-coarse-sweeps", type=int, default=4,
                     help="sweeps of the coarsest box level (0: those of the main hierarchy)")
-    ap.add_argument("--box-s-sweeps", type=int, default=24,
+    ap.add_argument("--box-s-sweeps", type=int, default=48,
                     help="red-black sweeps on the Schur matrix itself over each box after the "
                          "correction")
     ap.add_argument("--mg-pre", type=int, default=2, help="V-cycle pre-smoothing (red, black) pairs")

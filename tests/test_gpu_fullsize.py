@@ -112,10 +112,10 @@ def test_residual_and_schur_sampled_blocks(full, c0):
 
 
 # the benchmark's default preconditioner: the 16^3 subdomain correction with
-# a two-level box V-cycle (4 coarsest sweeps), 4 inner iterations and 24
+# a two-level box V-cycle (4 coarsest sweeps), 4 inner iterations and 48
 # red-black sweeps on the Schur matrix over the box, and
 # the inexact-Newton forcing 1e-6
-BENCH = dict(box_size=16, box_levels=2, box_inner=4, box_coarse_sweeps=4, box_s_sweeps=24,
+BENCH = dict(box_size=16, box_levels=2, box_inner=4, box_coarse_sweeps=4, box_s_sweeps=48,
              pcg_forcing=1e-6)
 
 
