@@ -427,6 +427,20 @@ def main():
         line["learned_training"] = train_info
     if "plain" in results and head != "plain":
         line["speedup_vs_plain"] = H["value"] / results["plain"]["value"]
+    if head.endswith("learned"):
+        # what the learned guess did in the timed steps: the proposals the
+        # initial-residual test accepted, the network's cost, and the gain
+        # over the same mode without the network
+        taken = H["network_guess_used"]
+        base = results.get(head.replace("+learned", "") if "+" in head else "plain")
+        line["learned_guess"] = {
+            "proposals_taken": taken, "timed_steps": args.steps,
+            "network_ms_per_step": H["network_ms_per_step"],
+            "speedup_vs_same_mode_without_network":
+                None if base is None else H["value"] / base["value"],
+            "outcome": ("no proposal passed the initial-residual test: the learned mode ran "
+                        "the previous-state guess plus the network's cost") if taken == 0 else
+                       ("the proposal was taken in %d of %d timed steps" % (taken, args.steps))}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         # about 10-30 s of oracle work in all: 96^3 for the HII region, 64^3 otherwise

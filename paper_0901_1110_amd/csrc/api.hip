@@ -461,9 +461,14 @@ void vcycle(rt_grid* g, std::vector<Level<T>>& Ls, int l, int cs, double* out64 
   }
   if (!coarsest) {
     // residual: operator (4), x, b in, r out; restriction: r in, coarse b out;
-    // prolongation: coarse x in, the corrected cells of x in and out
-    TKB(g, RT_K_MG_TRANSFER, 7.0 * F, launch_mg_residual<T>(L, st));
-    TKB(g, RT_K_MG_TRANSFER, 1.125 * F, launch_restrict<T>(L, Ls[l + 1], st));
+    // prolongation: coarse x in, the corrected cells of x in and out.  After
+    // a pre-smoothing (which ends with the black half-sweep) only the red
+    // cells have a residual: the residual reads the red cells' diag, b, x and
+    // own couplings, the black cells' couplings and x, and writes the red r
+    // (5.5 fields); the restriction reads the red r (0.5 + 0.125)
+    const int ro = pre > 0 ? 1 : 0;
+    TKB(g, RT_K_MG_TRANSFER, (ro ? 5.5 : 7.0) * F, launch_mg_residual<T>(L, ro, st));
+    TKB(g, RT_K_MG_TRANSFER, (ro ? 0.625 : 1.125) * F, launch_restrict<T>(L, Ls[l + 1], ro, st));
     vcycle<T>(g, Ls, l + 1, cs);
     // the post-smoothing starts with black: only red cells need the correction
     TKB(g, RT_K_MG_TRANSFER, (post > 0 ? 1.125 : 2.125) * F,

@@ -128,8 +128,11 @@ template <class T> void launch_coarse_solve_lds(const Level<T>& L, int sweeps, h
 constexpr int COARSE_LDS_MAX = 4096;
 int stencil_blocks(int nx, int ny, int nz);   // blocks (= partial sums) of a 3-D stencil launch
 constexpr int COARSE_SOLVE_MAX = 8192;        // coarsest levels up to this size: one workgroup
-template <class T> void launch_mg_residual(const Level<T>& L, hipStream_t st);
-template <class T> void launch_restrict(const Level<T>& F, const Level<T>& C, hipStream_t st);
+// red_only: the level's black cells satisfy their equations (the smoothing
+// ended with the black half-sweep), so their residual is taken as zero
+template <class T> void launch_mg_residual(const Level<T>& L, int red_only, hipStream_t st);
+template <class T> void launch_restrict(const Level<T>& F, const Level<T>& C, int red_only,
+                                        hipStream_t st);
 // colour >= 0: correct only the cells of that colour
 template <class T> void launch_prolong_add(const Level<T>& C, const Level<T>& F, int colour, hipStream_t st);
 template <class T> void launch_coarsen(const Level<T>& F, const Level<T>& C, hipStream_t st);

@@ -1252,11 +1252,16 @@ __global__ __launch_bounds__(CS_THREADS) void k_coarse_solve_lds(Level<T> L, int
   for (int t = tid; t < 2 * n2; t += CS_THREADS) L.x[base + t] = xs[t];
 }
 
+// r = b - A x.  red_only: after a smoothing that ended with the black
+// half-sweep every black cell satisfies its equation (its residual is zero up
+// to rounding), so only the red cells' residual is formed and stored; the
+// black places of r are left as they are and k_restrict does not read them
 template <class T, bool SF>
-__global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L) {
-  const C3 c = coord3(L.ny, L.nz);
+__global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L, int red_only) {
+  const C3 c = coord3(L.ny, red_only ? L.nz >> 1 : L.nz);
   if (!c.ok) return;
-  const Nb7 nb = nbrs7<SF>(c.i, c.j, stored_k<SF>(c.i, c.j, c.k, L.nz), L.nx, L.ny, L.nz);
+  const int k = red_only ? 2 * c.k + ((c.i + c.j) & 1) : stored_k<SF>(c.i, c.j, c.k, L.nz);
+  const Nb7 nb = nbrs7<SF>(c.i, c.j, k, L.nx, L.ny, L.nz);
   const int idx = nb.c;
   const T* x = L.x;
   T y = L.diag[idx] * x[idx];
@@ -1267,9 +1272,11 @@ __global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L) {
 }
 
 // b_coarse = R r_fine with R = P^T / 8: weights (1,3,3,1)/8 per axis over
-// fine cells 2I-1 .. 2I+2
+// fine cells 2I-1 .. 2I+2; red_only: the black cells' residual is zero (see
+// k_mg_residual) and is not read.  For one (i, j) the parity of each of the
+// four k is the same in every lane, so the test does not diverge.
 template <class T, bool SF>
-__global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C) {
+__global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C, int red_only) {
   const C3 c = coord3(C.ny, C.nz);
   if (!c.ok) return;
   const int I = c.i, J = c.j, K = c.k;
@@ -1287,7 +1294,9 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C) {
       const int j = wrap(2 * J - 1 + b, F.ny);
       T acc_k = T(0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc_k += w[q] * F.r[lidx<SF>(i, j, kk[q], F.ny, F.nz)];
+      for (int q = 0; q < 4; ++q)
+        if (!red_only || ((i + j + kk[q]) & 1) == 0)
+          acc_k += w[q] * F.r[lidx<SF>(i, j, kk[q], F.ny, F.nz)];
       acc_j += w[b] * acc_k;
     }
     acc += w[a] * acc_j;
@@ -1992,14 +2001,14 @@ void launch_coarse_solve(const Level<T>& L, int sweeps, hipStream_t st) {
   hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(1024), 0, st, L, sweeps);
 }
 template <class T>
-void launch_mg_residual(const Level<T>& L, hipStream_t st) {
-  const Geo q = geo3(L.nx, L.ny, L.nz);
-  RT_LAYOUT(L, k_mg_residual, T, q.g, q.b, 0, st, L);
+void launch_mg_residual(const Level<T>& L, int red_only, hipStream_t st) {
+  const Geo q = geo3(L.nx, L.ny, red_only ? L.nz / 2 : L.nz);
+  RT_LAYOUT(L, k_mg_residual, T, q.g, q.b, 0, st, L, red_only);
 }
 template <class T>
-void launch_restrict(const Level<T>& F, const Level<T>& C, hipStream_t st) {
+void launch_restrict(const Level<T>& F, const Level<T>& C, int red_only, hipStream_t st) {
   const Geo q = geo3(C.nx, C.ny, C.nz);
-  RT_LAYOUT(F, k_restrict, T, q.g, q.b, 0, st, F, C);
+  RT_LAYOUT(F, k_restrict, T, q.g, q.b, 0, st, F, C, red_only);
 }
 template <class T>
 void launch_prolong_add(const Level<T>& C, const Level<T>& F, int colour, hipStream_t st) {
@@ -2127,8 +2136,8 @@ void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st) {
   template int launch_rbgs_dots<T>(const Level<T>&, int, const T*, const T*, double*, hipStream_t); \
   template void launch_coarse_solve<T>(const Level<T>&, int, hipStream_t);           \
   template void launch_coarse_solve_lds<T>(const Level<T>&, int, hipStream_t); \
-  template void launch_mg_residual<T>(const Level<T>&, hipStream_t);                 \
-  template void launch_restrict<T>(const Level<T>&, const Level<T>&, hipStream_t);   \
+  template void launch_mg_residual<T>(const Level<T>&, int, hipStream_t);            \
+  template void launch_restrict<T>(const Level<T>&, const Level<T>&, int, hipStream_t); \
   template void launch_prolong_add<T>(const Level<T>&, const Level<T>&, int, hipStream_t); \
   template void launch_coarsen<T>(const Level<T>&, const Level<T>&, hipStream_t);
 RT_INST(double)
