@@ -1273,8 +1273,8 @@ __global__ __launch_bounds__(BLOCK) void k_mg_residual(Level<T> L, int red_only)
 
 // b_coarse = R r_fine with R = P^T / 8: weights (1,3,3,1)/8 per axis over
 // fine cells 2I-1 .. 2I+2; red_only: the black cells' residual is zero (see
-// k_mg_residual) and is not read.  For one (i, j) the parity of each of the
-// four k is the same in every lane, so the test does not diverge.
+// k_mg_residual) and is not read: two of the four k per fine (i, j), picked
+// without a branch so that all 32 loads issue together.
 template <class T, bool SF>
 __global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C, int red_only) {
   const C3 c = coord3(C.ny, C.nz);
@@ -1293,10 +1293,17 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(Level<T> F, Level<T> C, int 
     for (int b = 0; b < 4; ++b) {
       const int j = wrap(2 * J - 1 + b, F.ny);
       T acc_k = T(0);
+      if (red_only) {
+        // the red k of this (i, j) are kk[q0] and kk[q0 + 2]: kk[q] has the
+        // parity of q + 1 (nz is even, so the wrap keeps it)
+        const int q0 = (i + j + 1) & 1;
+        const int ka = q0 ? kk[1] : kk[0], kb = q0 ? kk[3] : kk[2];
+        const T wa = q0 ? w[1] : w[0], wb = q0 ? w[3] : w[2];
+        acc_k = wa * F.r[lidx<SF>(i, j, ka, F.ny, F.nz)] + wb * F.r[lidx<SF>(i, j, kb, F.ny, F.nz)];
+      } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (!red_only || ((i + j + kk[q]) & 1) == 0)
-          acc_k += w[q] * F.r[lidx<SF>(i, j, kk[q], F.ny, F.nz)];
+        for (int q = 0; q < 4; ++q) acc_k += w[q] * F.r[lidx<SF>(i, j, kk[q], F.ny, F.nz)];
+      }
       acc_j += w[b] * acc_k;
     }
     acc += w[a] * acc_j;
