@@ -63,17 +63,21 @@ HBM_PEAK_GBS = 8000.0
 # as null for any other.
 PMC_TRAFFIC = {
     ("cg_vector", "mixed", 256): {"ratio": 1.000, "kernels_sha256":
-                                  "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
+        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
     ("cg_vector", "mixed+learned", 256): {"ratio": 1.000, "kernels_sha256":
-                                          "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
-    ("spmv", "mixed", 256): {"ratio": 1.349, "kernels_sha256":
-                             "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
-    ("spmv", "mixed+learned", 256): {"ratio": 1.349, "kernels_sha256":
-                                     "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
+        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+    ("spmv", "mixed", 256): {"ratio": 1.031, "kernels_sha256":
+        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+    ("spmv", "mixed+learned", 256): {"ratio": 1.031, "kernels_sha256":
+        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
     ("rbgs_fine", "mixed", 256): {"ratio": 1.134, "kernels_sha256":
-                                  "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
+        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
     ("rbgs_fine", "mixed+learned", 256): {"ratio": 1.134, "kernels_sha256":
-                                          "02731e0bd5d700c2591a15393df27007ddb035f2147b494e885d1b0734e9463e"},
+        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+    ("mg_transfer", "mixed", 256): {"ratio": 1.124, "kernels_sha256":
+        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+    ("mg_transfer", "mixed+learned", 256): {"ratio": 1.124, "kernels_sha256":
+        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
 }
 
 
