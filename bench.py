@@ -74,10 +74,6 @@ PMC_TRAFFIC = {
         "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
     ("rbgs_fine", "mixed+learned", 256): {"ratio": 1.134, "kernels_sha256":
         "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
-    ("mg_transfer", "mixed", 256): {"ratio": 1.124, "kernels_sha256":
-        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
-    ("mg_transfer", "mixed+learned", 256): {"ratio": 1.124, "kernels_sha256":
-        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
 }
 
 
