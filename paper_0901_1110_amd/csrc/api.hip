@@ -618,24 +618,36 @@ void box_correct_t(rt_grid* g, const double* r, double* z, int dots) {
   const bool fuse_first = Ls.size() > 1 && g->prm.mg_pre > 0;
   T* rb[2] = {br, reinterpret_cast<T*>(w.br2)};
   int ri = 0;
+  // every block of the product and of the update sums all block partials of
+  // the kernel before it (blocks x partials reads); with many boxes one
+  // launch reduces them first, into box scalar slots laid out as a single
+  // partial, and the kernels read that one
+  auto once = [&](double* parts, int np_, int ncomp, int slot) -> std::pair<const double*, int> {
+    if (np_ <= BOX_INLINE_PARTS) return {parts, np_};
+    TK(g, RT_K_BOX, launch_final_reduce(parts, np_, ncomp, w.bsc + slot, st));
+    return {w.bsc + slot, 1};
+  };
   for (int it = 1; it <= g->prm.box_inner; ++it) {
     const int rho = (it & 1) ? S_RHO : S_RHO2, rho_prev = (it & 1) ? S_RHO2 : S_RHO;
     T* p = pb[it & 1];
     const T* p_prev = pb[(it + 1) & 1];
     // operator (4), z, p_prev in; p, q out
+    const std::pair<const double*, int> zp =
+        it == 1 ? std::pair<const double*, int>{w.bparts, 0} : once(w.bparts, nzp, 2, BOX_SLOT_ZPARTS);
     TKB(g, RT_K_BOX, (it == 1 ? 7.0 : 8.0) * F,
-        np = launch_box_spmv_p<T>(L0, bz, p_prev, p, bq, w.bparts, nzp, w.bsc, rho_prev, rho,
-                                  it == 1, w.bparts2, st));
+        np = launch_box_spmv_p<T>(L0, bz, p_prev, p, bq, zp.first, zp.second, w.bsc, rho_prev,
+                                  rho, it == 1, w.bparts2, st));
+    const std::pair<const double*, int> pq = once(w.bparts2, np, 1, BOX_SLOT_PQPARTS);
     const bool last = it == g->prm.box_inner;
     if (last || !fuse_first) {
       TKB(g, RT_K_BOX, 6.0 * F,
-          launch_box_update_xr<T>(n, x, rb[ri], p, bq, w.bparts2, np, w.bsc, rho, st));
+          launch_box_update_xr<T>(n, x, rb[ri], p, bq, pq.first, pq.second, w.bsc, rho, st));
       if (last) break;
     } else {
       // x, p, q, r in, x, the new r and the pair's z out, the operator (4)
       TKB(g, RT_K_BOX, 11.0 * F,
-          launch_box_update_first_pair<T>(L0, x, rb[ri], rb[ri ^ 1], p, bq, w.bparts2, np, w.bsc,
-                                          rho, st));
+          launch_box_update_first_pair<T>(L0, x, rb[ri], rb[ri ^ 1], p, bq, pq.first, pq.second,
+                                          w.bsc, rho, st));
       ri ^= 1;
     }
     T* r = rb[ri];

@@ -23,6 +23,12 @@ inline int reduce_blocks(long n) {
 // Indices of the device scalar slots used by CG.
 enum Scalar { S_RHO = 0, S_PQ, S_ALPHA, S_RR, S_ZR, S_ZQ, S_BETA, S_BB, S_FN, S_VIOL, S_TSUM, S_TMAX,
               S_RHO2, S_COUNT };
+// the box correction's inner CG: partial sets longer than this are reduced by
+// a launch of their own into these box scalar slots (one partial of
+// NCOMP_MAX components each) instead of by every block of the next kernel
+constexpr int BOX_INLINE_PARTS = 256;
+constexpr int BOX_SLOT_ZPARTS = 16, BOX_SLOT_PQPARTS = 20;
+static_assert(S_COUNT <= BOX_SLOT_ZPARTS && BOX_SLOT_PQPARTS + NCOMP_MAX <= 32, "box scalar slots");
 
 struct Step {     // per-call time-step data
   double dt, a, H;

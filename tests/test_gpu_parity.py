@@ -297,6 +297,16 @@ def test_newton_steps_overlapping_boxes():
     newton_parity(w, synth.initial_state(w), steps=2)
 
 
+def test_newton_steps_many_boxes():
+    """40 sources in a 32^3 lognormal cut with 8^3 boxes: the inner CG's
+    partial sets (320 blocks) are longer than the library sums inside each
+    block, so each is reduced by a launch of its own first."""
+    w = synth.CFG_COSMO.replace(n=32, mg_levels=3, dx=synth.CFG_COSMO.dx, nsources=40,
+                                box_size=8, box_levels=2, box_inner=3)
+    assert w.nsources * w.box_size > 256
+    newton_parity(w, synth.initial_state(w), steps=1)
+
+
 def test_newton_steps_expanding_lognormal():
     """Expanding lognormal medium with 16 sources (32^3 cut of the 128^3 workload)."""
     w = synth.CFG_COSMO.replace(n=32, mg_levels=3, dx=synth.CFG_COSMO.dx)
