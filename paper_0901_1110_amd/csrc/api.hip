@@ -110,7 +110,10 @@ struct rt_grid {
     double* z = nullptr;
     int nbox = 0, dots = 0;
     double bytes = 0.0;     // algorithmic bytes of one replay
-  } box_graph[2];           // without and with the dot partials
+  };
+  // one captured correction per (r, z, dots) in use: FGMRES applies the
+  // preconditioner to each basis vector v_j into its own z_j
+  std::vector<BoxGraph> box_graphs;
   std::string err;
 };
 
@@ -391,10 +394,9 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
 
 // extent of the box levels in use for nbox boxes (0: no subdomain correction)
 void drop_box_graph(rt_grid* g) {
-  for (auto& b : g->box_graph) {
+  for (auto& b : g->box_graphs)
     if (b.exec) (void)hipGraphExecDestroy(b.exec);   // nothing to report on release
-    b.exec = nullptr;
-  }
+  g->box_graphs.clear();
 }
 
 void set_box_extent(rt_grid* g, int nbox) {
@@ -746,9 +748,21 @@ int box_correct(rt_grid* g, const double* r, double* z, int dots) {
     box_correct_launches(g, r, z, dots);
     return RT_OK;
   }
-  rt_grid::BoxGraph& bg = g->box_graph[dots > 0 ? 1 : 0];
-  if (!bg.exec || bg.r != r || bg.z != z || bg.nbox != g->nbox || bg.dots != dots)
-    RTCHK(capture_box(g, bg, r, z, dots));
+  rt_grid::BoxGraph* hit = nullptr;
+  for (auto& b : g->box_graphs)
+    if (b.exec && b.r == r && b.z == z && b.nbox == g->nbox && b.dots == dots) hit = &b;
+  if (!hit) {
+    // at most one graph per FGMRES basis vector and dot variant
+    if (g->box_graphs.size() >= (size_t)(2 * KMAX + 4)) drop_box_graph(g);
+    g->box_graphs.emplace_back();
+    const int rc = capture_box(g, g->box_graphs.back(), r, z, dots);
+    if (rc != RT_OK) {
+      g->box_graphs.pop_back();
+      return rc;
+    }
+    hit = &g->box_graphs.back();
+  }
+  rt_grid::BoxGraph& bg = *hit;
   hipError_t e = hipSuccess;
   TKB(g, RT_K_BOX, bg.bytes, e = hipGraphLaunch(bg.exec, g->st));
   HIPCHK(g, e);
@@ -901,15 +915,14 @@ int fgmres(rt_grid* g, const double* b, double* x, double rtol, double atol, int
     HIPCHK(g, hipGetLastError());
     return RT_OK;
   }
-  // with the subdomain correction the preconditioner runs on fixed buffers
-  // (its captured graph is bound to them): the normalisation copies v_j to
-  // w.r, the product copies w.z to z_j
-  const bool fixed = g->nbox > 0;
+  // the preconditioner maps v_j to z_j directly (the subdomain correction
+  // keeps one captured graph per pair); the normalisation also writes the
+  // FP32 colour-split copy of v_j for the FP32 cycle
   float* r32 = fp32_fused(&g->prm) ? w.L32[0].b : nullptr;
   auto normalise = [&](double* v, double sf) {
-    TKB(g, RT_K_CG_VECTOR, 2.0 * F + (fixed ? F : 0.0) + (r32 ? 0.5 * F : 0.0),
-        launch_scale(N, v, sf, fixed ? w.r : nullptr, r32, P.ny, P.nz, g->st));
-    g->r32_of = r32 ? (fixed ? w.r : v) : nullptr;
+    TKB(g, RT_K_CG_VECTOR, 2.0 * F + (r32 ? 0.5 * F : 0.0),
+        launch_scale(N, v, sf, nullptr, r32, P.ny, P.nz, g->st));
+    g->r32_of = r32 ? v : nullptr;
   };
   std::vector<double> H((size_t)m * (m + 1)), cs(m), sn(m), gv(m + 1), y(m);
   int its = 0;
@@ -941,12 +954,12 @@ int fgmres(rt_grid* g, const double* b, double* x, double rtol, double atol, int
       double* vn = w.V + (size_t)(j + 1) * N;
       double* zj = w.Z + (size_t)j * N;
       int nd = 0;
-      RTCHK(apply_precond(g, fixed ? w.r : vj, fixed ? w.z : zj, false, &nd));
+      RTCHK(apply_precond(g, vj, zj, false, &nd));
       ++*vcycles;
       int nb = 0;
-      TKB(g, RT_K_SPMV, (9.0 + (j + 1) + (fixed ? 1.0 : 0.0)) * F,
-          nb = launch_spmv_full(P.nx, P.ny, P.nz, w.diag, w.fw, w.bw, fixed ? w.z : zj, nullptr,
-                                vn, fixed ? zj : nullptr, w.V, j + 1, w.gparts, g->st));
+      TKB(g, RT_K_SPMV, (9.0 + (j + 1)) * F,
+          nb = launch_spmv_full(P.nx, P.ny, P.nz, w.diag, w.fw, w.bw, zj, nullptr, vn, nullptr,
+                                w.V, j + 1, w.gparts, g->st));
       TK(g, RT_K_REDUCE, launch_final_multi(w.gparts, nb, j + 2, w.gh, g->st));
       TKB(g, RT_K_CG_VECTOR, (j + 3.0) * F,
           nb = launch_gs_pass(N, vn, w.V, j + 1, w.gh, 1, w.gparts, g->st));
