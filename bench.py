@@ -66,9 +66,9 @@ PMC_TRAFFIC = {
         "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
     ("cg_vector", "mixed+learned", 256): {"ratio": 1.000, "kernels_sha256":
         "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
-    ("spmv", "mixed", 256): {"ratio": 1.031, "kernels_sha256":
+    ("spmv", "mixed", 256): {"ratio": 1.029, "kernels_sha256":
         "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
-    ("spmv", "mixed+learned", 256): {"ratio": 1.031, "kernels_sha256":
+    ("spmv", "mixed+learned", 256): {"ratio": 1.029, "kernels_sha256":
         "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
     ("rbgs_fine", "mixed", 256): {"ratio": 1.134, "kernels_sha256":
         "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
