@@ -91,7 +91,7 @@ struct rt_grid {
   bool have_tl = false;     // lagged limiter: time-level face coefficients present
   bool mg_stale = true;     // coarse operators need rebuilding
   bool have_op = false;     // a Schur matrix is present
-  bool l0_fp32 = false;     // the FP32 finest-level operator copy matches the FP64 one
+  bool l0_fp32 = false;     // the finest level's operator copy (FP32, or colour-split FP64) is current
   const double* r32_of = nullptr;   // the CG residual whose FP32 copy is the finest right side
   double* hpin = nullptr;   // pinned host scalars for asynchronous read-back
   int nbox = 0;             // active source subdomains (0: V-cycle alone)
@@ -274,6 +274,13 @@ void fill_params(const rt_params* p, DevParams& P) {
 bool fp32_fused(const rt_params* p) {
   return p->mg_fp32 && p->mg_levels > 1 && p->mg_pre > 0 && p->mg_post > 0;
 }
+// The same layout for the finest level of the FP64 cycle: its operator, right
+// side and iterate are colour-split copies (the operator converted once per
+// Newton iteration, the right side per application) and its last half-sweep
+// writes the result in natural order
+bool fp64_split(const rt_params* p) {
+  return !p->mg_fp32 && p->mg_levels > 1 && p->mg_pre > 0 && p->mg_post > 0;
+}
 
 size_t carve(const rt_params* p, char* base, Workspace* w) {
   Carver c{base, 0, base == nullptr};
@@ -326,7 +333,14 @@ size_t carve(const rt_params* p, char* base, Workspace* w) {
     const size_t n = (size_t)nx * ny * nz;
     if (!p->mg_fp32) {
       Level<double> L{nx, ny, nz};
-      if (l == 0) {
+      if (l == 0 && fp64_split(p)) {
+        // colour-split copies of the preconditioner's operator, right side
+        // and iterate
+        L.diag = c.take<double>(n); L.cx = c.take<double>(n); L.cy = c.take<double>(n);
+        L.cz = c.take<double>(n); L.x = c.take<double>(n); L.b = c.take<double>(n);
+        L.r = c.take<double>(n);
+        L.split = 1;
+      } else if (l == 0) {
         // the V-cycle is built on the preconditioner's operator
         L.diag = w->pdiag; L.cx = w->cx; L.cy = w->cy; L.cz = w->cz;
         L.x = nullptr; L.b = nullptr;          // bound per application
@@ -419,9 +433,9 @@ Step step_new(double dt, const rt_cosmo* c) { return Step{dt, c->a_new, c->H_new
 
 // ---------------------------------------------------------------------------
 // multigrid
-// cs: sweeps of the coarsest solve.  out64 (finest level of the FP32 cycle
-// only): the last smoothing launch writes the result widened to this FP64
-// vector itself
+// cs: sweeps of the coarsest solve.  out64 (the colour-split finest level of
+// the FP32 or FP64 cycle): the last smoothing launch writes the result, in
+// FP64 and natural order, to this vector itself
 // rd, qd, pd (a level in natural layout): the last smoothing launch also
 // leaves the block partials of x.rd and x.qd in pd
 template <class T>
@@ -496,6 +510,14 @@ int build_hierarchy(rt_grid* g) {
   Workspace& w = g->w;
   const long N = g->P.N;
   if (!g->prm.mg_fp32) {
+    Level<double>& L0 = w.L64[0];
+    if (L0.split && !g->l0_fp32) {
+      TK(g, RT_K_MG_SETUP, launch_cvt_split_d(L0, w.pdiag, L0.diag, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_split_d(L0, w.cx, L0.cx, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_split_d(L0, w.cy, L0.cy, g->st));
+      TK(g, RT_K_MG_SETUP, launch_cvt_split_d(L0, w.cz, L0.cz, g->st));
+      g->l0_fp32 = true;
+    }
     for (size_t l = 1; l < w.L64.size(); ++l) TK(g, RT_K_MG_SETUP, launch_coarsen<double>(w.L64[l - 1], w.L64[l], g->st));
   } else {
     Level<float>& L0 = w.L32[0];
@@ -538,8 +560,15 @@ int apply_vcycle(rt_grid* g, const double* r, double* z, bool dots = false) {
   Workspace& w = g->w;
   const long N = g->P.N;
   if (!g->prm.mg_fp32) {
-    w.L64[0].b = const_cast<double*>(r);
-    w.L64[0].x = z;
+    Level<double>& L0 = w.L64[0];
+    if (L0.split) {
+      // r into the colour-split right side; the last half-sweep writes z
+      TKB(g, RT_K_MG_TRANSFER, 16.0 * N, launch_cvt_split_d(L0, r, L0.b, g->st));
+      vcycle<double>(g, w.L64, 0, g->prm.mg_coarse_sweeps, z);
+      return 0;
+    }
+    L0.b = const_cast<double*>(r);
+    L0.x = z;
     vcycle<double>(g, w.L64, 0, g->prm.mg_coarse_sweeps);
     return 0;
   }

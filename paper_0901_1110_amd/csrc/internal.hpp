@@ -195,6 +195,8 @@ template <class T>
 int launch_box_dot2(long n, const T* z, const T* r, const T* q, double* parts, hipStream_t st);
 // FP64 natural field -> FP32 field in the layout of level L
 void launch_cvt_d2f_level(const Level<float>& L, const double* a, float* b, hipStream_t st);
+// FP64 natural field -> the colour-split FP64 finest level L (L.split set)
+void launch_cvt_split_d(const Level<double>& L, const double* a, double* b, hipStream_t st);
 void launch_cvt_f2d(long n, const float* a, double* b, hipStream_t st);
 
 }  // namespace rtk

@@ -1739,14 +1739,15 @@ __global__ __launch_bounds__(BLOCK) void k_box_dot2(long n, const T* __restrict_
   block_reduce<2>(acc, parts);
 }
 
-// FP64 natural -> FP32 colour-split finest level
+// FP64 natural -> colour-split finest level (FP32, or FP64 for the FP64 cycle)
+template <class TO>
 __global__ __launch_bounds__(BLOCK) void k_cvt_d2f_split(int nx, int ny, int nz,
                                                           const double* __restrict__ a,
-                                                          float* __restrict__ b) {
+                                                          TO* __restrict__ b) {
   const C3 c = coord3(ny, nz);
   if (!c.ok) return;
   const int k = stored_k<true>(c.i, c.j, c.k, nz);
-  b[(c.i * ny + c.j) * nz + c.k] = (float)a[(c.i * ny + c.j) * nz + k];
+  b[(c.i * ny + c.j) * nz + c.k] = (TO)a[(c.i * ny + c.j) * nz + k];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cvt_d2f(long n, const double* __restrict__ a,
@@ -2116,10 +2117,14 @@ int launch_box_dot2(long n, const T* z, const T* r, const T* q, double* parts, h
 RT_BOX_INST(double)
 RT_BOX_INST(float)
 #undef RT_BOX_INST
+void launch_cvt_split_d(const Level<double>& L, const double* a, double* b, hipStream_t st) {
+  const Geo q = geo3(L.nx, L.ny, L.nz);
+  hipLaunchKernelGGL(k_cvt_d2f_split<double>, q.g, q.b, 0, st, L.nx, L.ny, L.nz, a, b);
+}
 void launch_cvt_d2f_level(const Level<float>& L, const double* a, float* b, hipStream_t st) {
   if (L.split) {
     const Geo q = geo3(L.nx, L.ny, L.nz);
-    hipLaunchKernelGGL(k_cvt_d2f_split, q.g, q.b, 0, st, L.nx, L.ny, L.nz, a, b);
+    hipLaunchKernelGGL(k_cvt_d2f_split<float>, q.g, q.b, 0, st, L.nx, L.ny, L.nz, a, b);
   } else {
     const long n = (long)L.nx * L.ny * L.nz;
     hipLaunchKernelGGL(k_cvt_d2f, grid_for(n), dim3(BLOCK), 0, st, n, a, b);

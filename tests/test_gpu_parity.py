@@ -385,9 +385,11 @@ def test_algorithmic_byte_counts():
     whose launches a fixed-count FGMRES solve fixes: k products from x = 0
     (no restart, no subdomain correction), product j reading the operator
     (7 fields), z_j and basis vectors 0..j and writing w (10 + j fields); and
-    k FP64 V-cycles, whose finest smoothing with V(pre, post) reads and writes
-    6 fields for the first (red, black) pair from zero and 5 per further
-    half-sweep."""
+    k FP64 V-cycles, whose colour-split finest smoothing with V(pre, post)
+    reads and writes 6 fields for the first (red, black) pair from zero, 5 per
+    further half-sweep, and for the last half-sweep, which writes z of both
+    colours in natural order instead of its colour's x, 4.5 fields and 8 B
+    per cell."""
     m, g, sch = schur_case(32, 3, 31)
     p = g.params
     N = 32 ** 3
@@ -400,4 +402,4 @@ def test_algorithmic_byte_counts():
     assert t["spmv"][2] == sum(10 + j for j in range(k)) * 8.0 * N
     half_sweeps = 2 * (p.mg_pre - 1) + 2 * p.mg_post
     assert t["rbgs_fine"][0] == k * (1 + half_sweeps)
-    assert t["rbgs_fine"][2] == k * (6 + 5 * half_sweeps) * 8.0 * N
+    assert t["rbgs_fine"][2] == k * ((6 + 5 * (half_sweeps - 1) + 4.5) * 8.0 + 8.0) * N
