@@ -63,17 +63,17 @@ HBM_PEAK_GBS = 8000.0
 # as null for any other.
 PMC_TRAFFIC = {
     ("cg_vector", "mixed", 256): {"ratio": 1.000, "kernels_sha256":
-        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+        "0f5ef77ae2f9c6e4290132ac295879fbbe56a2f6f0e8c311c39c85680033313a"},
     ("cg_vector", "mixed+learned", 256): {"ratio": 1.000, "kernels_sha256":
-        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+        "0f5ef77ae2f9c6e4290132ac295879fbbe56a2f6f0e8c311c39c85680033313a"},
     ("spmv", "mixed", 256): {"ratio": 1.029, "kernels_sha256":
-        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+        "0f5ef77ae2f9c6e4290132ac295879fbbe56a2f6f0e8c311c39c85680033313a"},
     ("spmv", "mixed+learned", 256): {"ratio": 1.029, "kernels_sha256":
-        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+        "0f5ef77ae2f9c6e4290132ac295879fbbe56a2f6f0e8c311c39c85680033313a"},
     ("rbgs_fine", "mixed", 256): {"ratio": 1.134, "kernels_sha256":
-        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+        "0f5ef77ae2f9c6e4290132ac295879fbbe56a2f6f0e8c311c39c85680033313a"},
     ("rbgs_fine", "mixed+learned", 256): {"ratio": 1.134, "kernels_sha256":
-        "b0645d798a6ffe315d903555ce3645c3c9cdba5011e1312e4a5a8947e0fe2c8a"},
+        "0f5ef77ae2f9c6e4290132ac295879fbbe56a2f6f0e8c311c39c85680033313a"},
 }
 
 
