@@ -337,9 +337,12 @@ int rt_timing(rt_grid* g, int32_t enable, rt_kernel_timing* out);
 int rt_timing_classes(rt_grid* g, uint32_t mask);
 
 /* The source-subdomain correction (box_size > 0) issues a few hundred small
- * launches per V-cycle; by default the library captures them once into a
- * HIP graph (on a private stream) and replays it, re-capturing when the
- * number of sources changes.  enable = 0 issues them one by one instead:
+ * launches per V-cycle; by default the library captures them into a HIP
+ * graph (on a private stream) per pair of input and output vectors in use
+ * (FGMRES maps each basis vector to its own preconditioned vector: up to 31
+ * pairs), replays the matching one, and drops them all when the number of
+ * sources changes or graphs are switched off.  enable = 0 issues them one
+ * by one instead:
  * the same kernels in the same order, so the results are identical.  A
  * timed correction counts as one RT_K_BOX entry per replay.  RT_EINVAL for
  * a null grid. */
